@@ -1,0 +1,179 @@
+"""Benchmark of the coupled LBM + Nernst-Planck step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 512^3 D3Q19 overlapping-sphere electrode (porosity 0.4, radii
+3-6 lattice units, seeded, about 54M fluid nodes), inlet/outlet flow, Na+/Cl-
+with a 20-thermal-voltage ramp. A "step" is one fused LBM collide-stream +
+Nernst-Planck update over all fluid nodes (with the inlet/outlet condition and
+the FP64 adsorbed/flux accumulators). Geometry, compaction and
+initialisation happen once, before the timed region; all state is resident
+in HBM. MLUPS counts fluid nodes only.
+
+Prints one JSON line. ``value`` is the FP32-storage fused MLUPS; the FP16
+deviation-storage form, LBM-only and NP-only rates are reported beside it.
+``roofline`` prices the fused kernel's algorithmic bytes per node against
+8 TB/s; ``cpu_baseline`` is the FP64 reference on this host's cores, on a
+bounded sample (the seeded 64^3 sub-case).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "spheres3d_512"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per fluid-node update (D3Q19): populations read + write,
+# concentrations read + write (2 species), ion-advecting flux read + write
+# (FP32: j, 3 floats; FP16: the moments rho-1, u as one float4)
+BYTES_FUSED = {"fp32": 19 * 4 * 2 + 16 + 24, "fp16_dev": 19 * 2 * 2 + 16 + 32}
+BYTES_LBM = {"fp32": 19 * 4 * 2, "fp16_dev": 19 * 2 * 2 + 32}
+BYTES_NP = 16 + 12  # C read + write, frozen j read
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("step.hip", "device_common.h", "cdi_internal.h"):
+        with open(os.path.join(ROOT, "paper_2110_13055_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind: str):
+    """HBM bytes per fused-step launch from the committed counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_spheres3d_512_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(kind)
+
+
+def time_region(fn, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def gpu_rates(precision: int, steps: int, warmup: int):
+    import torch
+    import paper_2110_13055_amd as P
+    g, p, _ = P.preset(WORKLOAD, precision=precision)
+    s = P.Solver(g, p)
+    nf = s.n_fluid
+    stream = s.stream
+    # develop the flow a little so the step sees a realistic state
+    s.flow_steps(2)
+    if warmup:
+        s.np_step(warmup, fused=True)
+    fused = time_region(lambda: s.np_step(steps, fused=True), stream)
+    lbm = time_region(lambda: s.flow_steps(steps), stream)
+    npo = time_region(lambda: s.np_step(steps, fused=False), stream)
+    res = dict(n_fluid=nf, fused_s=fused, lbm_s=lbm, np_s=npo)
+    del s
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(budget_s: float = 12.0):
+    """FP64 reference on the host: fused steps of the seeded 64^3 sub-case."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    import paper_2110_13055_amd as P
+    from helpers import oracle_solver
+    g, p, _ = P.preset("spheres3d_64")
+    o = oracle_solver(g, p)
+    o.flow_steps(2)
+    o.np_steps(2, fused=True)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.np_steps(10, fused=True)
+        steps += 10
+    dt = time.perf_counter() - t0
+    return {"value": o.nf * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} fused LBM+NP steps (FP64) of the seeded 64^3 sub-case "
+                      f"({o.nf} fluid nodes), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps % 2:
+        args.steps += 1  # whole AA step pairs (even + odd)
+
+    import torch
+    import paper_2110_13055_amd as P
+
+    r32 = gpu_rates(P.FP32, args.steps, args.warmup)
+    r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup)
+    nf = r32["n_fluid"]
+    K = args.steps
+
+    def mlups(sec):
+        return nf * K / sec / 1e6
+
+    ms_step = r32["fused_s"] / K * 1e3
+    achieved = BYTES_FUSED["fp32"] * nf / (r32["fused_s"] / K) / 1e9
+    traffic = measured_traffic("fp32")
+    out = {
+        "metric": "MLUPS coupled LBM+NP step (FP32 vs FP16-store); solves/hr + p50/p99 latency",
+        "value": round(mlups(r32["fused_s"]), 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "lattice": "D3Q19 512^3", "porosity": 0.4,
+                   "n_fluid": nf, "storage": "fp32", "step": "fused LBM+NP"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_node": BYTES_FUSED["fp32"]},
+        "fp16_dev": {"fused_mlups": round(mlups(r16["fused_s"]), 1),
+                     "lbm_mlups": round(mlups(r16["lbm_s"]), 1),
+                     "np_mlups": round(mlups(r16["np_s"]), 1),
+                     "fused_gbs": round(BYTES_FUSED["fp16_dev"] * nf / (r16["fused_s"] / K) / 1e9, 1)},
+        "fp32": {"fused_mlups": round(mlups(r32["fused_s"]), 1),
+                 "lbm_mlups": round(mlups(r32["lbm_s"]), 1),
+                 "np_mlups": round(mlups(r32["np_s"]), 1),
+                 "lbm_gbs": round(BYTES_LBM["fp32"] * nf / (r32["lbm_s"] / K) / 1e9, 1),
+                 "np_gbs": round(BYTES_NP * nf / (r32["np_s"] / K) / 1e9, 1)},
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

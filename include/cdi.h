@@ -1,0 +1,232 @@
+/*
+ * cdi.h -- C ABI of the MI355X (gfx950) pore-scale capacitive-deionisation
+ * solver: lattice Boltzmann Stokes flow coupled to an explicit finite-volume
+ * Nernst-Planck update for Na+ and Cl- with surface adsorption.
+ *
+ * Model (Liu, Waugh, Komini Babu, Spendelow, Kang, 2021):
+ *   - flow: Stokes equations, Eq. (1)-(2), solved by the lattice Boltzmann
+ *     equation with BGK collision, Eq. (7)-(8); D2Q9 or D3Q19; moments
+ *     rho = sum f, u = sum e f / rho; viscosity nu = (tau - 1/2)/3; no-flow
+ *     by bounce-back at solid faces (Sec. 2);
+ *   - ions: Nernst-Planck, Eq. (3), advection + diffusion + migration in a
+ *     prescribed potential (thermal voltages, psi~ = e psi / k_B T);
+ *   - adsorption: linear law D dC/dn = K_a C at electrode faces, Eq. (6);
+ *   - geometry: one lattice node per image voxel (Sec. 2, MAC grid).
+ *
+ * Conventions for every entry point:
+ *   - x is the flow axis; voxel index v = x + nx*(y + ny*z), x fastest.
+ *   - "device" pointers are HIP device allocations owned by the caller; the
+ *     library never allocates, frees or resizes them. "host" pointers are
+ *     ordinary host memory, read or written synchronously.
+ *   - stream is a hipStream_t passed as void* (NULL = default stream). All
+ *     device work of a solver is ordered on its stream.
+ *   - Every call returns an int status: CDI_OK (0), a positive warning, or a
+ *     negative CDI_E_* code; cdi_last_error() then describes the failure
+ *     (thread-local string, valid until the next call on that thread).
+ *     Nothing is thrown or aborted across the ABI.
+ *   - A solver handle is not thread-safe: drive each one from one thread.
+ */
+#ifndef CDI_H
+#define CDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define CDI_OK 0
+#define CDI_STAGNATED 1          /* flow stopped: residual stopped decreasing (FP32/FP16) */
+#define CDI_E_INVALID (-1)       /* bad argument or configuration */
+#define CDI_E_GEOMETRY (-2)      /* generator could not reach the porosity */
+#define CDI_E_UNSTABLE (-3)      /* tau <= 1/2, or NP positivity bound violated */
+#define CDI_E_NOT_CONVERGED (-4) /* max_steps reached; state remains valid */
+#define CDI_E_DIVERGED (-5)      /* NaN/Inf residual */
+#define CDI_E_DEVICE (-6)        /* HIP runtime error */
+#define CDI_E_BUFFER (-7)        /* workspace too small or misaligned */
+
+/* ---------------------------------------------------------------- enums */
+enum { CDI_DISKS = 0, CDI_SPHERES = 1, CDI_USER_LABELS = 2 };
+enum { CDI_INLET_OUTLET = 0, CDI_BODY_FORCE = 1 };
+enum { CDI_EQ_QUADRATIC = 0, CDI_EQ_LINEAR = 1 };
+enum { CDI_NPX_INLET_OUTLET = 0, CDI_NPX_PERIODIC = 1, CDI_NPX_CLOSED = 2, CDI_NPX_DIRICHLET = 3 };
+enum { CDI_FP32 = 0, CDI_FP16_DEV = 1 };
+
+/*
+ * Electrode geometry (Sec. 2: every grid block is one image voxel; Sec. 4-5:
+ * porous carbon electrodes). Voxel labels: 0 pore (fluid), 1 adsorbing
+ * electrode solid, 2 inert solid (channel wall).
+ *   dim          2 (D2Q9, nz ignored = 1) or 3 (D3Q19)
+ *   seed         SplitMix64 seed of the primitive generator
+ *   kind         CDI_DISKS (2D, non-overlapping, random sequential addition),
+ *                CDI_SPHERES (3D, overlapping, Boolean model, periodic y/z),
+ *                CDI_USER_LABELS (labels copied from user_labels)
+ *   porosity     target pore fraction over all voxels
+ *   r_min,r_max  primitive radius range (lattice units)
+ *   min_gap      disks only: minimum surface gap (lattice units)
+ *   walls_y      2D only: rows 0 and ny-1 are inert walls (else y periodic)
+ *   buffer_x     always-fluid planes at each x end (>= 2 with inlet/outlet)
+ *   user_labels  host, nx*ny*nz bytes, used for CDI_USER_LABELS only
+ */
+typedef struct {
+    int32_t dim, nx, ny, nz;
+    uint64_t seed;
+    int32_t kind;
+    double porosity, r_min, r_max, min_gap;
+    int32_t walls_y;
+    int32_t buffer_x;
+    const uint8_t *user_labels;
+} cdi_geometry;
+
+/*
+ * Physical and numerical parameters, lattice units (dx = dt = 1).
+ *   tau          BGK relaxation time, Eq. (8); must exceed 1/2
+ *   drive        CDI_INLET_OUTLET: plug velocity u_in at x = 0, density
+ *                rho_out at x = nx-1 (non-equilibrium extrapolation);
+ *                CDI_BODY_FORCE: periodic in x, driven by body_force
+ *                (Guo forcing), the paper's pressure-gradient-as-body-force
+ *   equilibrium  quadratic (default) or linear-in-u (Stokes limit)
+ *   D[2], z[2]   diffusivity and valence of Na+ (index 0) and Cl- (index 1)
+ *   c0           inlet and initial concentration ("initially saturated")
+ *   c_out        outlet ghost concentration (CDI_NPX_DIRICHLET only)
+ *   Ka           adsorption constant of Eq. (6); <= 0 selects
+ *                Ka = (4.28e-3 / 1.03e-2) * u_in / porosity, the paper's
+ *                Da/Pe ratio of its base case times the mean pore velocity
+ *   dpsi_vt      potential drop inlet minus outlet in thermal voltages; the
+ *                potential is the ramp dpsi_vt * (1 - (x + 1/2)/nx)
+ *   psi_field    device, N_f floats in fluid-node order, or NULL: a
+ *                prescribed potential (thermal voltages) replacing the ramp;
+ *                the buffer must outlive the solver
+ *   np_x_bc      treatment of the two x-end faces for Nernst-Planck
+ *   np_substeps  Nernst-Planck sub-steps per step (dt = 1/np_substeps);
+ *                fused steps need 1
+ *   precision    CDI_FP32: populations stored as f - w_i in FP32;
+ *                CDI_FP16_DEV: post-collision populations stored as FP16
+ *                deviations from the local equilibrium, with the
+ *                equilibrium's moments kept in FP32; all arithmetic FP32
+ */
+typedef struct {
+    double tau;
+    int32_t drive;
+    int32_t equilibrium;
+    double u_in, rho_out;
+    double body_force[3];
+    double D[2];
+    int32_t z[2];
+    double c0, c_out, Ka, dpsi_vt;
+    const float *psi_field;
+    int32_t np_x_bc;
+    int32_t np_substeps;
+    int32_t precision;
+} cdi_params;
+
+/* Sizes reported by cdi_plan. */
+typedef struct {
+    int64_t n_vox;          /* nx*ny*nz */
+    int64_t n_prims;        /* primitives drawn by the generator */
+    int64_t n_fluid_est;    /* target-porosity estimate of N_f (exact for disks) */
+    uint64_t vox_bytes;     /* device workspace of cdi_build_geometry */
+    uint64_t node_bytes_per_fluid; /* device workspace per fluid node (approximate) */
+} cdi_plan_info;
+
+typedef struct cdi_solver cdi_solver;
+
+/* Solver facts after initialisation. */
+typedef struct {
+    int64_t n_vox, n_fluid;
+    int32_t dim, q, nx, ny, nz;
+    int32_t precision;
+    int64_t flow_steps, np_steps;  /* steps taken so far */
+    double ka, keff[2];            /* resolved Ka and k_eff per species */
+    double porosity;               /* achieved N_f / N_vox */
+} cdi_solver_info;
+
+/* ------------------------------------------------------------ set-up */
+
+/* Host only, no device work. Draws the seeded primitives (cheap) and reports
+ * the voxel-level workspace size. INVALID on bad geometry, GEOMETRY when the
+ * disk generator jams. */
+int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *out);
+
+/* Voxelise the primitives and number the fluid voxels on the device (labels,
+ * fluid index map, compacted fluid list), into vox_ws (device, >= vox_bytes,
+ * 256-byte aligned). Synchronises once to return *n_fluid. Bit-identical to
+ * a sequential lexicographic numbering. */
+int cdi_build_geometry(const cdi_geometry *geom, void *vox_ws, uint64_t vox_ws_bytes,
+                       void *stream, int64_t *n_fluid);
+
+/* Device workspace needed by cdi_flow_init for n_fluid nodes. */
+int cdi_node_bytes(const cdi_geometry *geom, const cdi_params *params, int64_t n_fluid,
+                   uint64_t *bytes);
+
+/* Initialise a solver on a built geometry: fluid at rest (rho = 1, u = 0),
+ * C = c0, accumulators zero. vox_ws must hold the output of
+ * cdi_build_geometry; node_ws (device, >= cdi_node_bytes, 256-byte aligned)
+ * holds all per-node state. Both must outlive the solver. Asynchronous on
+ * stream. UNSTABLE if tau <= 1/2. *out is library-owned: cdi_destroy it. */
+int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_ws,
+                  uint64_t vox_ws_bytes, void *node_ws, uint64_t node_ws_bytes,
+                  int64_t n_fluid, void *stream, cdi_solver **out);
+
+int cdi_destroy(cdi_solver *s);
+int cdi_get_info(const cdi_solver *s, cdi_solver_info *out);
+
+/* ------------------------------------------------------------ time stepping */
+
+/* n lattice Boltzmann steps (collide, stream, bounce-back, inlet/outlet).
+ * Asynchronous. */
+int cdi_flow_steps(cdi_solver *s, int64_t n);
+
+/* Step the flow until r = |u^t - u^{t-1}|_2 / |u^t|_2 <= tol, where u^t is the
+ * velocity of the state step t starts from (0-based within the call), and r
+ * is evaluated (FP64) at t = check_every, 2*check_every, ... The call stops
+ * after the step that evaluated r <= tol. Synchronises once per check.
+ * Returns OK, STAGNATED (r failed to decrease over 10 consecutive checks),
+ * NOT_CONVERGED (max_steps taken; state valid) or DIVERGED (r not finite).
+ * steps_out / residual_out (host, nullable) receive the steps taken and the
+ * last residual. */
+int cdi_flow_step_to_steady(cdi_solver *s, double tol, int64_t max_steps, int32_t check_every,
+                            int64_t *steps_out, double *residual_out);
+
+/* nsteps Nernst-Planck steps, asynchronous. fused_flow = 0: the advecting
+ * velocity is frozen at the mass flux j = rho u of the current populations
+ * (or the field set by cdi_set_np_velocity). fused_flow = 1: every step also
+ * advances the flow, and the ions see the mass flux of the previous step.
+ * Checks the positivity bound dt * sum(outflow coefficients) <= 1 once
+ * (synchronising) and returns UNSTABLE without stepping if it fails. */
+int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow);
+
+/* Total adsorbed amount per species [Na, Cl] (lattice units: concentration x
+ * voxel volume), FP64, since initialisation. Synchronises. */
+int cdi_adsorbed_total(cdi_solver *s, double out[2]);
+
+/* FP64 balance per species: out[4*s + k], k = 0 solute sum_C, 1 adsorbed A,
+ * 2 inflow In, 3 outflow Out. M + A + Out - In is conserved. Synchronises. */
+int cdi_mass_balance(cdi_solver *s, double out[8]);
+
+/* ------------------------------------------------------------ state access
+ * All copies are synchronous, into caller-owned host memory. Fields are in
+ * fluid-node order, component-major (component c of node n at c*N_f + n). */
+int cdi_copy_labels(cdi_solver *s, uint8_t *labels);                 /* N_vox */
+int cdi_copy_fluid_index(cdi_solver *s, int32_t *map, int32_t *fluid); /* N_vox, N_f (nullable) */
+int cdi_copy_velocity(cdi_solver *s, float *u);      /* dim x N_f, u of the current populations */
+int cdi_copy_density(cdi_solver *s, float *rho);     /* N_f */
+int cdi_copy_np_velocity(cdi_solver *s, float *j);   /* dim x N_f, advecting field in use */
+int cdi_set_np_velocity(cdi_solver *s, const float *j); /* dim x N_f, prescribe (frozen) */
+int cdi_copy_concentration(cdi_solver *s, float *c); /* 2 x N_f */
+int cdi_set_concentration(cdi_solver *s, const float *c); /* 2 x N_f */
+
+/* Checkpoint: the complete device state (populations, moments, fields,
+ * accumulators, counters, AA parity) to and from host memory. */
+int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes);
+int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes);
+int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes);
+
+const char *cdi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,273 @@
+// aux.hip -- read-only passes over the lattice state (moments of the stored
+// populations, the positivity bound of the explicit Nernst-Planck step) and
+// the fixed-order FP64 reductions behind the residual, the adsorbed amount and
+// the solute mass.
+#include "device_common.h"
+
+namespace cdi {
+
+namespace {
+
+// Moments of the stored state (what the next step would see), including the
+// inlet/outlet extrapolation for boundary nodes with a fluid interior
+// neighbour. rho, u, j are optional outputs.
+template <class L, int FP16, int ODD>
+__global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, const void *F,
+                                                      const float4 *M, float *rho, float *u, float *j)
+{
+    constexpr int Q = L::Q, D = L::D;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.n_f) return;
+    const int v = g.fluid[n];
+    const int x = v % g.nx, t = v / g.nx, y = t % g.ny, z = t / g.ny;
+    int src = n, sx = x;
+    bool inlet = false;
+    if (nee && g.inout && (x == 0 || x == g.nx - 1)) {
+        const int c = nb_map<L>(g, x, y, z, x == 0 ? 1 : 2, false);
+        if (c >= 0) {
+            src = c;
+            sx = x == 0 ? 1 : g.nx - 2;
+            inlet = x == 0;
+        }
+    }
+    int nb[Q];
+    nb[0] = src;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) nb[i] = (ODD || FP16) ? nb_map<L>(g, sx, y, z, i, g.periodic_x) : kOutside;
+    float f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = gather<L, FP16, ODD>(F, g.P, nb, src, i, M, p);
+    if (src != n) {
+        float fb[Q];
+        nee_populations<L>(p, inlet, f, fb);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = fb[i];
+    }
+    float drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += f[i];
+        jx += L::ex[i] * f[i];
+        jy += L::ey[i] * f[i];
+        jz += L::ez[i] * f[i];
+    }
+    if (p.forced) {
+        jx += 0.5f * p.F[0];
+        jy += 0.5f * p.F[1];
+        jz += 0.5f * p.F[2];
+    }
+    const float ri = 1.f / (1.f + drho);
+    const int P = g.P;
+    if (rho) rho[n] = 1.f + drho;
+    if (u) {
+        u[n] = jx * ri;
+        u[P + n] = jy * ri;
+        if (D == 3) u[2 * P + n] = jz * ri;
+    }
+    if (j) {
+        j[n] = jx;
+        j[P + n] = jy;
+        if (D == 3) j[2 * P + n] = jz;
+    }
+}
+
+__global__ void tile_heads_kernel(Grid g, int *heads)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t * kTile < g.n_f) heads[t] = g.fluid[t * kTile];
+}
+
+template <int D>
+__global__ void j_from_m_kernel(Grid g, const float4 *M, float *j)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.n_f) return;
+    const float4 m = M[n];
+    const float r = 1.f + m.x;
+    j[n] = r * m.y;
+    j[g.P + n] = r * m.z;
+    if (D == 3) j[2 * g.P + n] = r * m.w;
+}
+
+// Single block of 1024 threads; fixed summation order.
+__global__ __launch_bounds__(1024) void reduce_tiles_kernel(const double *in, int ntiles, int stride,
+                                                            int width, double *out)
+{
+    __shared__ double sm[1024];
+    for (int k = 0; k < width; ++k) {
+        double s = 0;
+        for (int t = threadIdx.x; t < ntiles; t += 1024) s += in[(size_t)t * stride + k];
+        sm[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 512; h > 0; h >>= 1) {
+            if (threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = sm[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void max_tiles_kernel(const double *in, int ntiles, double *out)
+{
+    __shared__ double sm[1024];
+    double s = 0;
+    for (int t = threadIdx.x; t < ntiles; t += 1024) s = fmax(s, in[t]);
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+__global__ __launch_bounds__(kTile) void mass_kernel(Grid g, const float *C, double *part)
+{
+    const int n = blockIdx.x * kTile + threadIdx.x;
+    double v[2] = {0, 0};
+    if (n < g.n_f) {
+        v[0] = C[n];
+        v[1] = C[g.P + n];
+    }
+    __shared__ double sm[(kTile / 64) * 2];
+    double s[2];
+    block_sum<2>(v, sm, s);
+    if (threadIdx.x == 0) {
+        part[2 * (size_t)blockIdx.x] = s[0];
+        part[2 * (size_t)blockIdx.x + 1] = s[1];
+    }
+}
+
+__device__ inline float bern(float x) { return x == 0.f ? 1.f : x / expm1f(x); }
+
+// dt * (sum of the coefficients multiplying C_P in the outflow), per node,
+// maximum over the block. Positivity of the explicit update needs <= 1.
+template <class L>
+__global__ __launch_bounds__(kTile) void stability_kernel(Grid g, Phys p, const float *j, double *part)
+{
+    constexpr int D = L::D;
+    const int n = blockIdx.x * kTile + threadIdx.x;
+    float worst = 0.f;
+    if (n < g.n_f) {
+        const int v = g.fluid[n];
+        const int x = v % g.nx, t = v / g.nx, y = t % g.ny, z = t / g.ny;
+        const int P = g.P;
+        const float psiP = p.psi ? p.psi[n] : 0.f;
+        for (int s = 0; s < 2; ++s) {
+            const float Ds = p.D[s];
+            float dg = 0.f;
+            for (int k = 0; k < 2 * D; ++k) {
+                const int axis = k >> 1;
+                const int sgi = (k & 1) ? -1 : 1;
+                const float sg = (float)sgi;
+                const bool xb = axis == 0 && (x + sgi < 0 || x + sgi >= g.nx);
+                if (xb && p.npx != kNpxPeriodic) {
+                    if (p.npx == kNpxClosed) continue;
+                    const float dpsi = p.psi ? 0.f : -sg * p.dpsi_dx;
+                    if (sgi < 0) {
+                        const float w = -p.u_in - p.z[s] * Ds * dpsi;
+                        dg += Ds * bern(-w / Ds);
+                    } else {
+                        const float w = j[n] - p.z[s] * Ds * dpsi;
+                        dg += p.npx == kNpxDirichlet ? Ds * bern(-w / Ds) : fmaxf(w, 0.f);
+                    }
+                    continue;
+                }
+                const int m = nb_map<L>(g, x, y, z, k + 1, xb ? true : (bool)g.periodic_x);
+                if (m == kElectrode) {
+                    dg += p.keff[s];
+                } else if (m >= 0) {
+                    const float un = 0.5f * (j[axis * P + n] + j[axis * P + m]) * sg;
+                    const float dpsi = p.psi ? p.psi[m] - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
+                    const float w = un - p.z[s] * Ds * dpsi;
+                    dg += Ds * bern(-w / Ds);
+                }
+            }
+            worst = fmaxf(worst, p.dt * dg);
+        }
+    }
+    __shared__ float sm[kTile];
+    sm[threadIdx.x] = worst;
+    __syncthreads();
+    for (int h = kTile / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+}  // namespace
+
+hipError_t launch_tile_heads(const Grid &g, int *heads, hipStream_t s)
+{
+    const int tiles = g.P / kTile;
+    if (tiles == 0) return hipSuccess;
+    tile_heads_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(g, heads);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int dim, int fp16, int odd, int nee, const Grid &g, const Phys &p,
+                          const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((g.n_f + 255) / 256);
+    if (blocks == 0) return hipSuccess;
+#define MOM(L, H, O) moments_kernel<L, H, O><<<blocks, 256, 0, s>>>(g, p, nee, f, M, rho, u, j)
+    if (dim == 2) {
+        if (fp16) {
+            if (odd) MOM(D2Q9, 1, 1); else MOM(D2Q9, 1, 0);
+        } else {
+            if (odd) MOM(D2Q9, 0, 1); else MOM(D2Q9, 0, 0);
+        }
+    } else {
+        if (fp16) {
+            if (odd) MOM(D3Q19, 1, 1); else MOM(D3Q19, 1, 0);
+        } else {
+            if (odd) MOM(D3Q19, 0, 1); else MOM(D3Q19, 0, 0);
+        }
+    }
+#undef MOM
+    return hipGetLastError();
+}
+
+hipError_t launch_j_from_m(int dim, const Grid &g, const float4 *M, float *j, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((g.n_f + 255) / 256);
+    if (blocks == 0) return hipSuccess;
+    if (dim == 2)
+        j_from_m_kernel<2><<<blocks, 256, 0, s>>>(g, M, j);
+    else
+        j_from_m_kernel<3><<<blocks, 256, 0, s>>>(g, M, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_tiles(const double *in, int ntiles, int stride, int width, double *out,
+                               hipStream_t s)
+{
+    reduce_tiles_kernel<<<1, 1024, 0, s>>>(in, ntiles, stride, width, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass(const Grid &g, const float *C, double *part, double *out, hipStream_t s)
+{
+    const int tiles = g.P / kTile;
+    if (tiles == 0) return hipSuccess;
+    mass_kernel<<<tiles, kTile, 0, s>>>(g, C, part);
+    reduce_tiles_kernel<<<1, 1024, 0, s>>>(part, tiles, 2, 2, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stability(int dim, const Grid &g, const Phys &p, const float *j, double *part,
+                            double *out, hipStream_t s)
+{
+    const int tiles = g.P / kTile;
+    if (tiles == 0) return hipSuccess;
+    if (dim == 2)
+        stability_kernel<D2Q9><<<tiles, kTile, 0, s>>>(g, p, j, part);
+    else
+        stability_kernel<D3Q19><<<tiles, kTile, 0, s>>>(g, p, j, part);
+    max_tiles_kernel<<<1, 1024, 0, s>>>(part, tiles, out);
+    return hipGetLastError();
+}
+
+}  // namespace cdi

@@ -1,0 +1,746 @@
+// cdi_api.hip -- host side of the C ABI declared in include/cdi.h: argument
+// checks, workspace carving, step sequencing (AA parity, double buffers) and
+// the synchronising read-backs. All arithmetic of the model runs in the
+// kernels of geometry.hip and step.hip.
+#include "cdi.h"
+#include "cdi_internal.h"
+#include "geomgen.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <algorithm>
+#include <vector>
+
+using namespace cdi;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(CDI_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr uint64_t kAlign = 256;
+constexpr float kHalfScale = 4096.f;  // FP16 deviations are stored times 2^12
+
+uint64_t up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Consumes an aligned slice of a workspace.
+struct Carver {
+    uint8_t *base;
+    uint64_t off = 0;
+    explicit Carver(void *b) : base((uint8_t *)b) {}
+    template <class T>
+    T *take(uint64_t bytes)
+    {
+        T *p = (T *)(base ? base + off : nullptr);
+        off += up(bytes);
+        return p;
+    }
+};
+
+int check_geometry(const cdi_geometry *g)
+{
+    if (!g) return fail(CDI_E_INVALID, "geometry is NULL");
+    if (g->dim != 2 && g->dim != 3) return fail(CDI_E_INVALID, "dim must be 2 or 3");
+    const int nz = g->dim == 2 ? 1 : g->nz;
+    if (g->nx < 4 || g->ny < 1 || nz < 1) return fail(CDI_E_INVALID, "lattice too small (nx >= 4)");
+    const double nvox = (double)g->nx * g->ny * nz;
+    if (nvox >= 2147483647.0) return fail(CDI_E_INVALID, "nx*ny*nz must be < 2^31");
+    if (g->kind == CDI_USER_LABELS) {
+        if (!g->user_labels) return fail(CDI_E_INVALID, "user_labels is NULL");
+        return CDI_OK;
+    }
+    if (g->kind == CDI_DISKS && g->dim != 2) return fail(CDI_E_INVALID, "disks need dim 2");
+    if (g->kind == CDI_SPHERES && g->dim != 3) return fail(CDI_E_INVALID, "spheres need dim 3");
+    if (g->kind != CDI_DISKS && g->kind != CDI_SPHERES) return fail(CDI_E_INVALID, "unknown kind");
+    if (!(g->porosity > 0 && g->porosity <= 1)) return fail(CDI_E_INVALID, "porosity out of (0, 1]");
+    if (!(g->r_min > 0 && g->r_max >= g->r_min)) return fail(CDI_E_INVALID, "bad radius range");
+    if (g->buffer_x < 0 || 2 * g->buffer_x >= g->nx) return fail(CDI_E_INVALID, "bad buffer_x");
+    return CDI_OK;
+}
+
+int check_params(const cdi_params *p)
+{
+    if (!p) return fail(CDI_E_INVALID, "params is NULL");
+    if (!(p->tau > 0.5)) return fail(CDI_E_UNSTABLE, "tau must exceed 1/2 (nu = (tau - 1/2)/3 > 0)");
+    if (p->drive != CDI_INLET_OUTLET && p->drive != CDI_BODY_FORCE) return fail(CDI_E_INVALID, "bad drive");
+    if (p->equilibrium != CDI_EQ_QUADRATIC && p->equilibrium != CDI_EQ_LINEAR)
+        return fail(CDI_E_INVALID, "bad equilibrium");
+    if (p->np_x_bc < 0 || p->np_x_bc > 3) return fail(CDI_E_INVALID, "bad np_x_bc");
+    if (p->np_substeps < 1) return fail(CDI_E_INVALID, "np_substeps must be >= 1");
+    if (p->precision != CDI_FP32 && p->precision != CDI_FP16_DEV) return fail(CDI_E_INVALID, "bad precision");
+    if (!(p->D[0] > 0 && p->D[1] > 0)) return fail(CDI_E_INVALID, "diffusivities must be positive");
+    return CDI_OK;
+}
+
+// Seeded primitives of the geometry (host). Returns CDI status.
+int make_prims(const cdi_geometry *g, std::vector<geomgen_prim> &out, int64_t *nfluid_exact)
+{
+    out.clear();
+    if (nfluid_exact) *nfluid_exact = -1;
+    geomgen_prim *pp = nullptr;
+    int64_t n = 0;
+    int rc;
+    if (g->kind == CDI_DISKS) {
+        int64_t nf = 0;
+        rc = geomgen_disks(g->nx, g->ny, g->buffer_x, g->walls_y, g->seed, g->porosity, g->r_min,
+                           g->r_max, g->min_gap, &pp, &n, &nf);
+        if (nfluid_exact) *nfluid_exact = nf;
+    } else if (g->kind == CDI_SPHERES) {
+        rc = geomgen_spheres(g->nx, g->ny, g->nz, g->buffer_x, g->seed, g->porosity, g->r_min,
+                             g->r_max, &pp, &n);
+    } else {
+        return CDI_OK;
+    }
+    if (rc == GEOMGEN_E_JAMMED) return fail(CDI_E_GEOMETRY, "random sequential addition jammed before the porosity");
+    if (rc != GEOMGEN_OK) return fail(CDI_E_INVALID, "primitive generator rejected the geometry (rc %d)", rc);
+    out.assign(pp, pp + n);
+    geomgen_free(pp);
+    return CDI_OK;
+}
+
+struct VoxLayout {
+    uint8_t *labels;
+    int *map, *fluid, *blk;
+    int64_t *nfluid;
+    int64_t *prims;
+    uint64_t bytes;
+};
+
+VoxLayout vox_layout(void *ws, int64_t nvox, int64_t nprims)
+{
+    Carver c(ws);
+    VoxLayout L;
+    L.labels = c.take<uint8_t>((uint64_t)nvox);
+    L.map = c.take<int>(4ull * nvox);
+    L.fluid = c.take<int>(4ull * nvox);
+    L.blk = c.take<int>(4ull * (uint64_t)compact_blocks(nvox));
+    L.nfluid = c.take<int64_t>(8);
+    L.prims = c.take<int64_t>(32ull * (uint64_t)(nprims > 0 ? nprims : 1));
+    L.bytes = c.off;
+    return L;
+}
+
+int64_t geom_nvox(const cdi_geometry *g) { return (int64_t)g->nx * g->ny * (g->dim == 2 ? 1 : g->nz); }
+
+}  // namespace
+
+struct NodeLayout {
+    void *f;
+    float4 *M[2];
+    float *j[2];
+    float *ubuf;
+    float *C[2];
+    float *tmp;
+    double *acc, *resid, *part, *red;
+    int *sched;
+    uint64_t bytes;
+};
+
+static NodeLayout node_layout(void *ws, int dim, int fp16, int64_t P, int64_t plane)
+{
+    const int Q = dim == 2 ? 9 : 19;
+    const int64_t ntiles = P / kTile;
+    Carver c(ws);
+    NodeLayout L;
+    L.f = c.take<void>((uint64_t)Q * P * (fp16 ? 2 : 4));
+    L.M[0] = c.take<float4>(fp16 ? 16ull * P : 0);
+    L.M[1] = c.take<float4>(fp16 ? 16ull * P : 0);
+    if (!fp16) L.M[0] = L.M[1] = nullptr;
+    L.j[0] = c.take<float>(4ull * dim * P);
+    L.j[1] = c.take<float>(4ull * dim * P);
+    L.ubuf = c.take<float>(4ull * dim * P);
+    L.C[0] = c.take<float>(8ull * P);
+    L.C[1] = c.take<float>(8ull * P);
+    L.tmp = c.take<float>(4ull * (1 + dim) * P);
+    L.acc = c.take<double>(64ull * ntiles);
+    L.resid = c.take<double>(16ull * ntiles);
+    L.part = c.take<double>(16ull * ntiles);
+    L.red = c.take<double>(64 * 8);
+    L.sched = c.take<int>(4ull * ntiles);
+    L.bytes = c.off;
+    return L;
+}
+
+enum { J_INVALID = 0, J_VALID = 1, J_IN_M = 2 };
+
+struct cdi_solver {
+    cdi_geometry geom;
+    cdi_params params;
+    int dim, Q, fp16, inout;
+    int64_t nvox, nf;
+    int P, ntiles;
+    hipStream_t stream;
+    VoxLayout vox;
+    NodeLayout node;
+    int parity = 0, mcur = 0, jcur = 0, ccur = 0, jstate = J_INVALID;
+    int64_t flow_steps = 0, np_steps = 0;
+    double ka, keff[2], porosity;
+    Grid g;
+    Phys p;
+};
+
+namespace {
+
+struct SnapHeader {
+    uint64_t magic, bytes;
+    int32_t parity, mcur, jcur, ccur, jstate, pad;
+    int64_t flow_steps, np_steps, nf;
+};
+constexpr uint64_t kSnapMagic = 0x43444931534e4150ull;
+
+int step_once(cdi_solver *s, int lbm, int np, int flags)
+{
+    Bufs b{};
+    b.f = s->node.f;
+    if (s->fp16) {
+        b.Min = s->node.M[s->mcur];
+        b.Mout = s->node.M[s->mcur ^ 1];
+    }
+    b.jin = s->node.j[s->jcur];
+    b.jout = s->node.j[s->jcur ^ 1];
+    b.Cin = s->node.C[s->ccur];
+    b.Cout = s->node.C[s->ccur ^ 1];
+    b.acc = s->node.acc;
+    b.resid = s->node.resid;
+    b.ubuf = s->node.ubuf;
+    b.flags = flags | (s->flow_steps > 0 ? kNee : 0);
+    HIPCHK(launch_step(s->dim, s->fp16, s->parity, lbm, np, s->g, s->p, b, s->stream));
+    if (lbm) {
+        s->parity ^= 1;
+        if (s->fp16) s->mcur ^= 1;
+        if (np && !s->fp16) s->jcur ^= 1;
+        s->flow_steps++;
+    }
+    if (np) s->ccur ^= 1;
+    return CDI_OK;
+}
+
+int ensure_j(cdi_solver *s)
+{
+    if (s->jstate == J_VALID) return CDI_OK;
+    if (s->jstate == J_IN_M) {
+        HIPCHK(launch_j_from_m(s->dim, s->g, s->node.M[s->mcur], s->node.j[s->jcur], s->stream));
+    } else {
+        HIPCHK(launch_moments(s->dim, s->fp16, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+                              s->fp16 ? s->node.M[s->mcur] : nullptr, nullptr, nullptr,
+                              s->node.j[s->jcur], s->stream));
+    }
+    s->jstate = J_VALID;
+    return CDI_OK;
+}
+
+// Tile schedule for 3D lattices: tiles sorted by (band of kBandRows rows, z,
+// y, index). Each XCD then sweeps its bands plane by plane, so the data of the
+// planes above and below a tile was touched a few tiles earlier by the same
+// XCD (L2 reuse) instead of a whole plane earlier.
+constexpr int kBandRows = 16;
+
+int build_schedule(cdi_solver *s)
+{
+    const int T = s->ntiles;
+    std::vector<int> heads(T);
+    HIPCHK(launch_tile_heads(s->g, s->node.sched, s->stream));
+    HIPCHK(hipMemcpyAsync(heads.data(), s->node.sched, 4ull * T, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const int64_t nx = s->g.nx, ny = s->g.ny;
+    std::vector<int64_t> key(T);
+    std::vector<int> order(T);
+    for (int t = 0; t < T; ++t) {
+        const int64_t v = heads[t];
+        const int64_t y = (v / nx) % ny, z = v / (nx * ny);
+        key[t] = ((y / kBandRows) * s->g.nz + z) * ny + y;
+        order[t] = t;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    HIPCHK(hipMemcpyAsync(s->node.sched, order.data(), 4ull * T, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->g.sched = s->node.sched;
+    return CDI_OK;
+}
+
+int d2h(cdi_solver *s, void *dst, const void *src, uint64_t bytes)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CDI_OK;
+}
+
+int h2d(cdi_solver *s, void *dst, const void *src, uint64_t bytes)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CDI_OK;
+}
+
+// d planes of stride P on the device <-> d planes of N_f on the host
+int planes_d2h(cdi_solver *s, float *host, const float *dev, int d)
+{
+    for (int k = 0; k < d; ++k)
+        HIPCHK(hipMemcpyAsync(host + (size_t)k * s->nf, dev + (size_t)k * s->P, 4ull * s->nf,
+                              hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CDI_OK;
+}
+
+int planes_h2d(cdi_solver *s, float *dev, const float *host, int d)
+{
+    for (int k = 0; k < d; ++k)
+        HIPCHK(hipMemcpyAsync(dev + (size_t)k * s->P, host + (size_t)k * s->nf, 4ull * s->nf,
+                              hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cdi_last_error(void) { return g_err; }
+
+int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *out)
+{
+    int rc = check_geometry(geom);
+    if (rc) return rc;
+    if (params && (rc = check_params(params)) != CDI_OK) return rc;
+    if (!out) return fail(CDI_E_INVALID, "out is NULL");
+    const int64_t nvox = geom_nvox(geom);
+    int64_t nprims = 0, nf_est = -1;
+    if (geom->kind == CDI_DISKS) {
+        std::vector<geomgen_prim> pr;
+        if ((rc = make_prims(geom, pr, &nf_est)) != CDI_OK) return rc;
+        nprims = (int64_t)pr.size();
+    } else if (geom->kind == CDI_SPHERES) {
+        nprims = geomgen_sphere_count(geom->nx, geom->ny, geom->nz, geom->buffer_x, geom->porosity,
+                                      geom->r_min, geom->r_max);
+        if (nprims < 0) return fail(CDI_E_INVALID, "sphere generator rejected the geometry");
+        nf_est = (int64_t)llround(geom->porosity * (double)nvox);
+    } else {
+        nf_est = 0;
+        for (int64_t v = 0; v < nvox; ++v) nf_est += geom->user_labels[v] == 0;
+    }
+    out->n_vox = nvox;
+    out->n_prims = nprims;
+    out->n_fluid_est = nf_est;
+    out->vox_bytes = vox_layout(nullptr, nvox, nprims).bytes;
+    const int dim = geom->dim;
+    const int fp16 = params ? params->precision == CDI_FP16_DEV : 0;
+    const int Q = dim == 2 ? 9 : 19;
+    out->node_bytes_per_fluid =
+        (uint64_t)Q * (fp16 ? 2 : 4) + (fp16 ? 32 : 0) + 12ull * dim + 16 + 4ull * (1 + dim) + 1;
+    g_err[0] = 0;
+    return CDI_OK;
+}
+
+int cdi_build_geometry(const cdi_geometry *geom, void *vox_ws, uint64_t vox_ws_bytes, void *stream,
+                       int64_t *n_fluid)
+{
+    int rc = check_geometry(geom);
+    if (rc) return rc;
+    if (!vox_ws || ((uintptr_t)vox_ws % kAlign)) return fail(CDI_E_BUFFER, "vox_ws NULL or not 256-byte aligned");
+    const int64_t nvox = geom_nvox(geom);
+    std::vector<geomgen_prim> pr;
+    if ((rc = make_prims(geom, pr, nullptr)) != CDI_OK) return rc;
+    const int64_t nprims = (int64_t)pr.size();
+    VoxLayout L = vox_layout(vox_ws, nvox, nprims);
+    if (vox_ws_bytes < L.bytes) return fail(CDI_E_BUFFER, "vox_ws too small: %llu < %llu",
+                                            (unsigned long long)vox_ws_bytes, (unsigned long long)L.bytes);
+    hipStream_t st = (hipStream_t)stream;
+    const int nz = geom->dim == 2 ? 1 : geom->nz;
+    if (geom->kind == CDI_USER_LABELS) {
+        HIPCHK(hipMemcpyAsync(L.labels, geom->user_labels, (size_t)nvox, hipMemcpyHostToDevice, st));
+    } else {
+        if (nprims > 0)
+            HIPCHK(hipMemcpyAsync(L.prims, pr.data(), sizeof(geomgen_prim) * (size_t)nprims,
+                                  hipMemcpyHostToDevice, st));
+        HIPCHK(launch_init_labels(L.labels, geom->nx, geom->ny, nz, geom->dim == 2 && geom->walls_y, st));
+        HIPCHK(launch_voxelize(L.labels, L.prims, nprims, geom->dim, geom->nx, geom->ny, nz,
+                               geom->walls_y, geom->buffer_x, st));
+    }
+    HIPCHK(launch_compact(L.labels, nvox, L.map, L.fluid, L.blk, L.nfluid, st));
+    int64_t nf = 0;
+    HIPCHK(hipMemcpyAsync(&nf, L.nfluid, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (n_fluid) *n_fluid = nf;
+    if (nf == 0) return fail(CDI_E_GEOMETRY, "geometry has no fluid voxel");
+    g_err[0] = 0;
+    return CDI_OK;
+}
+
+int cdi_node_bytes(const cdi_geometry *geom, const cdi_params *params, int64_t n_fluid, uint64_t *bytes)
+{
+    int rc = check_geometry(geom);
+    if (rc) return rc;
+    if ((rc = check_params(params)) != CDI_OK) return rc;
+    if (!bytes || n_fluid <= 0) return fail(CDI_E_INVALID, "bad n_fluid or bytes pointer");
+    const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
+    *bytes = node_layout(nullptr, geom->dim, params->precision == CDI_FP16_DEV, P, (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz)).bytes;
+    return CDI_OK;
+}
+
+int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_ws, uint64_t vox_ws_bytes,
+                  void *node_ws, uint64_t node_ws_bytes, int64_t n_fluid, void *stream, cdi_solver **out)
+{
+    int rc = check_geometry(geom);
+    if (rc) return rc;
+    if ((rc = check_params(params)) != CDI_OK) return rc;
+    if (!out) return fail(CDI_E_INVALID, "out is NULL");
+    if (!vox_ws || !node_ws || ((uintptr_t)vox_ws % kAlign) || ((uintptr_t)node_ws % kAlign))
+        return fail(CDI_E_BUFFER, "workspace NULL or not 256-byte aligned");
+    const int64_t nvox = geom_nvox(geom);
+    if (n_fluid <= 0 || n_fluid > nvox) return fail(CDI_E_INVALID, "bad n_fluid");
+    // the primitive count only sizes the tail of the voxel workspace
+    int64_t nprims = 0;
+    if (geom->kind == CDI_DISKS) {
+        std::vector<geomgen_prim> pr;
+        if ((rc = make_prims(geom, pr, nullptr)) != CDI_OK) return rc;
+        nprims = (int64_t)pr.size();
+    } else if (geom->kind == CDI_SPHERES) {
+        nprims = geomgen_sphere_count(geom->nx, geom->ny, geom->nz, geom->buffer_x, geom->porosity,
+                                      geom->r_min, geom->r_max);
+    }
+    VoxLayout V = vox_layout(vox_ws, nvox, nprims);
+    if (vox_ws_bytes < V.bytes) return fail(CDI_E_BUFFER, "vox_ws too small");
+    const int fp16 = params->precision == CDI_FP16_DEV;
+    const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
+    if (P > 2147483647LL) return fail(CDI_E_INVALID, "too many fluid nodes");
+    NodeLayout N = node_layout(node_ws, geom->dim, fp16, P, (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz));
+    if (node_ws_bytes < N.bytes) return fail(CDI_E_BUFFER, "node_ws too small: %llu < %llu",
+                                             (unsigned long long)node_ws_bytes, (unsigned long long)N.bytes);
+    if (params->np_x_bc != CDI_NPX_PERIODIC && params->np_x_bc != CDI_NPX_CLOSED && geom->nx < 2)
+        return fail(CDI_E_INVALID, "nx too small");
+
+    cdi_solver *s = new (std::nothrow) cdi_solver();
+    if (!s) return fail(CDI_E_INVALID, "out of host memory");
+    s->geom = *geom;
+    s->geom.user_labels = nullptr;
+    s->params = *params;
+    s->dim = geom->dim;
+    s->Q = geom->dim == 2 ? 9 : 19;
+    s->fp16 = fp16;
+    s->inout = params->drive == CDI_INLET_OUTLET;
+    s->nvox = nvox;
+    s->nf = n_fluid;
+    s->P = (int)P;
+    s->ntiles = (int)(P / kTile);
+    s->stream = (hipStream_t)stream;
+    s->vox = V;
+    s->node = N;
+    s->porosity = (double)n_fluid / (double)nvox;
+    s->ka = params->Ka > 0 ? params->Ka : (4.28e-3 / 1.03e-2) * params->u_in / s->porosity;
+    for (int k = 0; k < 2; ++k) s->keff[k] = s->ka * params->D[k] / (params->D[k] + 0.5 * s->ka);
+
+    Grid &g = s->g;
+    g.nx = geom->nx;
+    g.ny = geom->ny;
+    g.nz = geom->dim == 2 ? 1 : geom->nz;
+    g.n_f = (int)n_fluid;
+    g.P = (int)P;
+    g.periodic_x = params->drive == CDI_BODY_FORCE;
+    g.inout = params->drive == CDI_INLET_OUTLET;
+    g.fluid = V.fluid;
+    g.map = V.map;
+    g.sched = nullptr;
+    Phys &p = s->p;
+    p.omega = (float)(1.0 / params->tau);
+    p.fcoef = (float)(1.0 - 0.5 / params->tau);
+    for (int a = 0; a < 3; ++a) p.F[a] = (float)params->body_force[a];
+    p.forced = params->drive == CDI_BODY_FORCE;
+    p.linear_eq = params->equilibrium == CDI_EQ_LINEAR;
+    for (int k = 0; k < 2; ++k) {
+        p.D[k] = (float)params->D[k];
+        p.z[k] = (float)params->z[k];
+        p.keff[k] = (float)s->keff[k];
+    }
+    p.c0 = (float)params->c0;
+    p.c_out = (float)params->c_out;
+    p.u_in = (float)params->u_in;
+    p.rho_out = (float)params->rho_out;
+    p.dpsi_dx = (float)(params->dpsi_vt / geom->nx);
+    p.npx = params->np_x_bc;
+    p.dt = (float)(1.0 / params->np_substeps);
+    p.psi = params->psi_field;
+    p.hs = kHalfScale;
+    p.hs_inv = 1.f / kHalfScale;
+
+    hipStream_t st = s->stream;
+    int err = CDI_OK;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && err == CDI_OK) err = fail(CDI_E_DEVICE, "init: %s", hipGetErrorString(e));
+    };
+    // rest state: f - w_i = 0 (FP32) / zero deviations and zero moments (FP16)
+    if (fp16) {
+        chk(launch_fill_u32((uint32_t *)N.f, 0u, (int64_t)s->Q * P / 2, st));
+        chk(launch_fill_f32((float *)N.M[0], 0.f, 4 * P, st));
+        chk(launch_fill_f32((float *)N.M[1], 0.f, 4 * P, st));
+    } else {
+        chk(launch_fill_f32((float *)N.f, 0.f, (int64_t)s->Q * P, st));
+    }
+    chk(launch_fill_f32(N.j[0], 0.f, (int64_t)s->dim * P, st));
+    chk(launch_fill_f32(N.j[1], 0.f, (int64_t)s->dim * P, st));
+    chk(launch_fill_f32(N.ubuf, 0.f, (int64_t)s->dim * P, st));
+    chk(launch_fill_f32(N.C[0], (float)params->c0, 2 * P, st));
+    chk(launch_fill_f32(N.C[1], (float)params->c0, 2 * P, st));
+    chk(launch_fill_f64(N.acc, 0.0, 8ll * s->ntiles, st));
+    chk(launch_fill_f64(N.resid, 0.0, 2ll * s->ntiles, st));
+    if (err == CDI_OK && s->dim == 3) err = build_schedule(s);
+    if (err != CDI_OK) {
+        delete s;
+        return err;
+    }
+    *out = s;
+    g_err[0] = 0;
+    return CDI_OK;
+}
+
+int cdi_destroy(cdi_solver *s)
+{
+    delete s;
+    return CDI_OK;
+}
+
+int cdi_get_info(const cdi_solver *s, cdi_solver_info *out)
+{
+    if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
+    out->n_vox = s->nvox;
+    out->n_fluid = s->nf;
+    out->dim = s->dim;
+    out->q = s->Q;
+    out->nx = s->g.nx;
+    out->ny = s->g.ny;
+    out->nz = s->g.nz;
+    out->precision = s->params.precision;
+    out->flow_steps = s->flow_steps;
+    out->np_steps = s->np_steps;
+    out->ka = s->ka;
+    out->keff[0] = s->keff[0];
+    out->keff[1] = s->keff[1];
+    out->porosity = s->porosity;
+    return CDI_OK;
+}
+
+int cdi_flow_steps(cdi_solver *s, int64_t n)
+{
+    if (!s || n < 0) return fail(CDI_E_INVALID, "bad arguments");
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = step_once(s, 1, 0, 0);
+        if (rc) return rc;
+    }
+    if (n > 0) s->jstate = J_INVALID;
+    return CDI_OK;
+}
+
+int cdi_flow_step_to_steady(cdi_solver *s, double tol, int64_t max_steps, int32_t check_every,
+                            int64_t *steps_out, double *residual_out)
+{
+    if (!s || max_steps < 0 || check_every < 2) return fail(CDI_E_INVALID, "bad arguments");
+    const int K = check_every;
+    double r = INFINITY, best = INFINITY;
+    int since_best = 0;
+    int status = CDI_E_NOT_CONVERGED;
+    int64_t t = 0;
+    for (; t < max_steps; ++t) {
+        int flags = 0;
+        if (!s->fp16 && t % K == K - 1) flags |= kStoreU;
+        const bool check = t > 0 && t % K == 0;
+        if (check) flags |= kResid;
+        int rc = step_once(s, 1, 0, flags);
+        if (rc) return rc;
+        if (check) {
+            HIPCHK(launch_reduce_tiles(s->node.resid, s->ntiles, 2, 2, s->node.red, s->stream));
+            double h[2];
+            if ((rc = d2h(s, h, s->node.red, 16)) != CDI_OK) return rc;
+            r = std::sqrt(h[0]) / std::sqrt(h[1]);
+            if (!std::isfinite(r)) {
+                status = fail(CDI_E_DIVERGED, "residual is not finite");
+                ++t;
+                break;
+            }
+            if (r <= tol) {
+                status = CDI_OK;
+                ++t;
+                break;
+            }
+            if (r < best) {
+                best = r;
+                since_best = 0;
+            } else if (++since_best >= 10) {
+                status = CDI_STAGNATED;
+                ++t;
+                break;
+            }
+        }
+    }
+    s->jstate = J_INVALID;
+    if (steps_out) *steps_out = t;
+    if (residual_out) *residual_out = r;
+    if (status == CDI_E_NOT_CONVERGED) fail(CDI_E_NOT_CONVERGED, "max_steps reached, residual %g", r);
+    return status;
+}
+
+int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow)
+{
+    if (!s || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
+    if (fused_flow && s->params.np_substeps != 1) return fail(CDI_E_INVALID, "fused steps need np_substeps = 1");
+    if (nsteps == 0) return CDI_OK;
+    int rc = ensure_j(s);
+    if (rc) return rc;
+    HIPCHK(launch_stability(s->dim, s->g, s->p, s->node.j[s->jcur], s->node.part, s->node.red, s->stream));
+    double worst = 0;
+    if ((rc = d2h(s, &worst, s->node.red, 8)) != CDI_OK) return rc;
+    if (!(worst <= 1.0))
+        return fail(CDI_E_UNSTABLE, "positivity bound violated: dt * sum(outflow coefficients) = %g > 1", worst);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (fused_flow) {
+            const int flags = (s->fp16 && k > 0) ? kJFromM : 0;
+            if ((rc = step_once(s, 1, 1, flags)) != CDI_OK) return rc;
+        } else {
+            for (int m = 0; m < s->params.np_substeps; ++m)
+                if ((rc = step_once(s, 0, 1, 0)) != CDI_OK) return rc;
+        }
+        s->np_steps++;
+    }
+    if (fused_flow) s->jstate = s->fp16 ? J_IN_M : J_VALID;
+    return CDI_OK;
+}
+
+int cdi_adsorbed_total(cdi_solver *s, double out[2])
+{
+    if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
+    HIPCHK(launch_reduce_tiles(s->node.acc, s->ntiles, 8, 2, s->node.red, s->stream));
+    return d2h(s, out, s->node.red, 16);
+}
+
+int cdi_mass_balance(cdi_solver *s, double out[8])
+{
+    if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
+    HIPCHK(launch_reduce_tiles(s->node.acc, s->ntiles, 8, 6, s->node.red, s->stream));
+    HIPCHK(launch_mass(s->g, s->node.C[s->ccur], s->node.part, s->node.red + 8, s->stream));
+    double h[10];
+    int rc = d2h(s, h, s->node.red, 80);
+    if (rc) return rc;
+    for (int sp = 0; sp < 2; ++sp) {
+        out[4 * sp + 0] = h[8 + sp];
+        out[4 * sp + 1] = h[0 + sp];
+        out[4 * sp + 2] = h[2 + sp];
+        out[4 * sp + 3] = h[4 + sp];
+    }
+    return CDI_OK;
+}
+
+int cdi_copy_labels(cdi_solver *s, uint8_t *labels)
+{
+    if (!s || !labels) return fail(CDI_E_INVALID, "NULL argument");
+    return d2h(s, labels, s->vox.labels, (uint64_t)s->nvox);
+}
+
+int cdi_copy_fluid_index(cdi_solver *s, int32_t *map, int32_t *fluid)
+{
+    if (!s) return fail(CDI_E_INVALID, "NULL argument");
+    int rc = CDI_OK;
+    if (map && (rc = d2h(s, map, s->vox.map, 4ull * s->nvox)) != CDI_OK) return rc;
+    if (fluid && (rc = d2h(s, fluid, s->vox.fluid, 4ull * s->nf)) != CDI_OK) return rc;
+    return CDI_OK;
+}
+
+int cdi_copy_velocity(cdi_solver *s, float *u)
+{
+    if (!s || !u) return fail(CDI_E_INVALID, "NULL argument");
+    HIPCHK(launch_moments(s->dim, s->fp16, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+                          s->fp16 ? s->node.M[s->mcur] : nullptr, nullptr, s->node.tmp, nullptr, s->stream));
+    return planes_d2h(s, u, s->node.tmp, s->dim);
+}
+
+int cdi_copy_density(cdi_solver *s, float *rho)
+{
+    if (!s || !rho) return fail(CDI_E_INVALID, "NULL argument");
+    HIPCHK(launch_moments(s->dim, s->fp16, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+                          s->fp16 ? s->node.M[s->mcur] : nullptr, s->node.tmp, nullptr, nullptr, s->stream));
+    return planes_d2h(s, rho, s->node.tmp, 1);
+}
+
+int cdi_copy_np_velocity(cdi_solver *s, float *j)
+{
+    if (!s || !j) return fail(CDI_E_INVALID, "NULL argument");
+    int rc = ensure_j(s);
+    if (rc) return rc;
+    return planes_d2h(s, j, s->node.j[s->jcur], s->dim);
+}
+
+int cdi_set_np_velocity(cdi_solver *s, const float *j)
+{
+    if (!s || !j) return fail(CDI_E_INVALID, "NULL argument");
+    int rc = planes_h2d(s, s->node.j[s->jcur], j, s->dim);
+    if (rc) return rc;
+    s->jstate = J_VALID;
+    return CDI_OK;
+}
+
+int cdi_copy_concentration(cdi_solver *s, float *c)
+{
+    if (!s || !c) return fail(CDI_E_INVALID, "NULL argument");
+    return planes_d2h(s, c, s->node.C[s->ccur], 2);
+}
+
+int cdi_set_concentration(cdi_solver *s, const float *c)
+{
+    if (!s || !c) return fail(CDI_E_INVALID, "NULL argument");
+    return planes_h2d(s, s->node.C[s->ccur], c, 2);
+}
+
+int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes)
+{
+    if (!s || !bytes) return fail(CDI_E_INVALID, "NULL argument");
+    *bytes = sizeof(SnapHeader) + s->node.bytes;
+    return CDI_OK;
+}
+
+int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes)
+{
+    if (!s || !host) return fail(CDI_E_INVALID, "NULL argument");
+    if (bytes < sizeof(SnapHeader) + s->node.bytes) return fail(CDI_E_BUFFER, "snapshot buffer too small");
+    SnapHeader h{kSnapMagic, s->node.bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, 0,
+                 s->flow_steps, s->np_steps, s->nf};
+    std::memcpy(host, &h, sizeof h);
+    return d2h(s, (uint8_t *)host + sizeof h, s->node.f, s->node.bytes);
+}
+
+int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
+{
+    if (!s || !host) return fail(CDI_E_INVALID, "NULL argument");
+    SnapHeader h;
+    if (bytes < sizeof h) return fail(CDI_E_BUFFER, "snapshot too small");
+    std::memcpy(&h, host, sizeof h);
+    if (h.magic != kSnapMagic || h.bytes != s->node.bytes || h.nf != s->nf ||
+        bytes < sizeof h + h.bytes)
+        return fail(CDI_E_INVALID, "snapshot does not belong to this solver layout");
+    int rc = h2d(s, s->node.f, (const uint8_t *)host + sizeof h, s->node.bytes);
+    if (rc) return rc;
+    s->parity = h.parity;
+    s->mcur = h.mcur;
+    s->jcur = h.jcur;
+    s->ccur = h.ccur;
+    s->jstate = h.jstate;
+    s->flow_steps = h.flow_steps;
+    s->np_steps = h.np_steps;
+    return CDI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// cdi_internal.h -- lattice tables, kernel argument blocks and launcher
+// declarations shared by the HIP translation units of libcdi.
+//
+// Data layout in device memory (N_f fluid nodes, stride P = N_f rounded up to
+// a whole number of 256-node tiles):
+//   populations  Q planes of P values (structure of arrays), FP32 f - w_i or
+//                FP16 scaled deviations from the emitter's equilibrium
+//   moments      FP16 storage only: float4 (rho - 1, ux, uy, uz) per node,
+//                double buffered (the moments of the previous step belong to
+//                the emitters of the populations now stored)
+//   jbuf         advecting mass flux j = rho u for the ions, d planes of P,
+//                double buffered (fused steps read one and write the other)
+//   conc         2 species x P, double buffered (Jacobi update)
+//   acc          per tile 8 doubles: A_na, A_cl, In_na, In_cl, Out_na, Out_cl
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cdi {
+
+constexpr int kTile = 256;  // fluid nodes per tile (= threads per block)
+
+// D2Q9; directions 1..4 are the faces +x, -x, +y, -y.
+struct D2Q9 {
+    static constexpr int D = 2, Q = 9;
+    static constexpr int ex[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int ey[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+    static constexpr float w[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
+                                   1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+};
+
+// D3Q19; directions 1..6 are the faces +x, -x, +y, -y, +z, -z.
+struct D3Q19 {
+    static constexpr int D = 3, Q = 19;
+    static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr float w[19] = {1.f / 3,  1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18,
+                                    1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36,
+                                    1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+};
+
+// map values of non-fluid voxels
+constexpr int kElectrode = -1;
+constexpr int kInert = -2;
+constexpr int kOutside = -3;  // beyond an open x end
+
+// Nernst-Planck x-end treatments (same numbering as the public enum)
+constexpr int kNpxInletOutlet = 0, kNpxPeriodic = 1, kNpxClosed = 2, kNpxDirichlet = 3;
+
+// step flags
+constexpr int kStoreU = 1;    // write u of the incoming state to ubuf
+constexpr int kResid = 2;     // accumulate |u - ubuf|^2 and |u|^2 per tile
+constexpr int kJFromM = 4;    // FP16 fused: ions read j from the moments buffer
+constexpr int kNee = 8;       // the stored state carries inlet/outlet extrapolation
+                              // (every state after the first step)
+
+struct Grid {
+    int nx, ny, nz;
+    int n_f;         // fluid nodes
+    int P;           // plane stride (multiple of kTile)
+    int periodic_x;  // LBM periodic in x (body-force drive)
+    int inout;       // inlet/outlet planes at x = 0 and x = nx - 1
+    const int *fluid;
+    const int *map;
+    // Tile schedule: XCD-local position -> tile. Tiles are ordered by
+    // (band of rows, z) so the planes above and below a tile were visited
+    // shortly before by the same XCD and are still in its L2.
+    const int *sched;
+};
+
+struct Phys {
+    float omega;       // 1 / tau
+    float fcoef;       // 1 - 1/(2 tau), Guo source prefactor
+    float F[3];        // body-force density
+    int forced;
+    int linear_eq;
+    // Nernst-Planck
+    float D[2], z[2], keff[2];
+    float c0, c_out, u_in;
+    float rho_out;     // outlet density of the flow
+    float dpsi_dx;     // ramp drop per cell (dpsi / nx)
+    int npx;
+    float dt;
+    const float *psi;  // optional field (fluid order), else ramp
+    // FP16 deviation scale
+    float hs, hs_inv;
+};
+
+struct Bufs {
+    void *f;
+    const float4 *Min;
+    float4 *Mout;
+    const float *jin;
+    float *jout;
+    const float *Cin;
+    float *Cout;
+    double *acc;
+    double *resid;
+    float *ubuf;
+    int flags;
+};
+
+// ------------------------------------------------------------ launchers
+// Every launcher enqueues on `stream` and returns hipGetLastError().
+hipError_t launch_init_labels(uint8_t *labels, int nx, int ny, int nz, int walls2d, hipStream_t s);
+hipError_t launch_voxelize(uint8_t *labels, const int64_t *prims, int64_t nprims, int dim, int nx,
+                           int ny, int nz, int walls_y, int buffer_x, hipStream_t s);
+hipError_t launch_compact(const uint8_t *labels, int64_t nvox, int *map, int *fluid, int *blk,
+                          int64_t *nfluid, hipStream_t s);
+int64_t compact_blocks(int64_t nvox);
+
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+
+// One LBM and/or Nernst-Planck step over all fluid nodes.
+//   dim 2/3, fp16 0/1, odd = AA parity of the stored state, lbm/np switches.
+hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p,
+                       const Bufs &b, hipStream_t s);
+// Moments of the stored state: rho (nullable), u (nullable, d planes),
+// j (nullable, d planes).
+hipError_t launch_moments(int dim, int fp16, int odd, int nee, const Grid &g, const Phys &p,
+                          const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s);
+// First-node voxel of every tile (for the host-side tile schedule).
+hipError_t launch_tile_heads(const Grid &g, int *heads, hipStream_t s);
+// j = (1 + drho) u from the FP16 moments buffer.
+hipError_t launch_j_from_m(int dim, const Grid &g, const float4 *M, float *j, hipStream_t s);
+// Deterministic single-block sums: out[k] = sum_t in[t*stride + k], k < width.
+hipError_t launch_reduce_tiles(const double *in, int ntiles, int stride, int width, double *out,
+                               hipStream_t s);
+// FP64 sum of each concentration field (solute mass): out[0..1].
+hipError_t launch_mass(const Grid &g, const float *C, double *part, double *out, hipStream_t s);
+// max over nodes/species of dt * (sum of outflow coefficients); out[0].
+hipError_t launch_stability(int dim, const Grid &g, const Phys &p, const float *j, double *part,
+                            double *out, hipStream_t s);
+
+}  // namespace cdi

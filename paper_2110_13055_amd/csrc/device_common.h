@@ -1,0 +1,190 @@
+// device_common.h -- device helpers shared by the step and auxiliary kernels:
+// neighbour lookup through the fluid index map, the BGK equilibrium, the AA
+// storage rules, the inlet/outlet extrapolation and block reductions.
+//
+// AA storage rules (Bailey et al. 2009). With the stored state at parity 0
+// ("A"), the post-streaming population f_i(x) sits in node x, slot i; a step
+// reads it there, collides, and writes f*_i back into node x, slot opp(i).
+// With the state at parity 1 ("B"), f_i(x) sits in node x - e_i, slot opp(i)
+// when that voxel is fluid, else in node x, slot i (it was reflected); a step
+// reads it there and writes f*_i into node x + e_i, slot i (fluid), or into
+// node x, slot opp(i) (half-way bounce-back off a solid face, the no-flow
+// rule). Each node reads and writes the same set of slots, so a step is
+// race-free in place.
+//
+// FP16 storage keeps, instead of f - w_i, the post-collision deviation from
+// the emitting node's equilibrium, times hs; the emitter's moments
+// (rho - 1, u) are kept in FP32. The emitter of f_i(x) is x - e_i if that
+// voxel is fluid, else x itself (which sent it in direction opp(i)).
+#pragma once
+
+#include "cdi_internal.h"
+
+namespace cdi {
+
+// blockIdx -> tile: workgroups are dealt round-robin over the 8 XCDs, each
+// with its own L2; this keeps consecutive tiles on one XCD so that the y/z
+// neighbours a tile touches were mostly fetched by the same L2.
+__device__ inline int xcd_tile(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int xcd = b & 7, k = b >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// Tile processed by this workgroup: its XCD-local position, through the
+// (band, z) schedule when there is one.
+__device__ inline int block_tile(const Grid &g)
+{
+    const int pos = xcd_tile(blockIdx.x, gridDim.x);
+    return g.sched ? g.sched[pos] : pos;
+}
+
+// map value of the neighbour of (x,y,z) along direction i: fluid index,
+// kElectrode, kInert, or kOutside past an open x end. y and z wrap.
+template <class L>
+__device__ inline int nb_map(const Grid &g, int x, int y, int z, int i, bool periodic_x)
+{
+    int xn = x + L::ex[i];
+    if (xn < 0 || xn >= g.nx) {
+        if (!periodic_x) return kOutside;
+        xn = xn < 0 ? xn + g.nx : xn - g.nx;
+    }
+    int yn = y + L::ey[i];
+    yn = yn < 0 ? yn + g.ny : (yn >= g.ny ? yn - g.ny : yn);
+    int zn = z;
+    if (L::D == 3) {
+        zn = z + L::ez[i];
+        zn = zn < 0 ? zn + g.nz : (zn >= g.nz ? zn - g.nz : zn);
+    }
+    return g.map[((int64_t)zn * g.ny + yn) * g.nx + xn];
+}
+
+// BGK equilibrium minus w_i, from rho - 1 and u: quadratic in u, or its
+// linear (Stokes) part.
+template <class L>
+__device__ inline float feq_bar(int i, float drho, float ux, float uy, float uz, int linear)
+{
+    const float rho = 1.f + drho;
+    const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+    if (linear) return L::w[i] * (drho + 3.f * rho * eu);
+    const float uu = ux * ux + uy * uy + uz * uz;
+    return L::w[i] * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+}
+
+template <int FP16>
+__device__ inline float ld(const void *F, int P, int i, int n)
+{
+    const size_t o = (size_t)i * P + n;
+    if (FP16) return __half2float(reinterpret_cast<const __half *>(F)[o]);
+    return reinterpret_cast<const float *>(F)[o];
+}
+
+template <int FP16>
+__device__ inline void st(void *F, int P, int i, int n, float v)
+{
+    const size_t o = (size_t)i * P + n;
+    if (FP16)
+        reinterpret_cast<__half *>(F)[o] = __float2half_rn(v);
+    else
+        reinterpret_cast<float *>(F)[o] = v;
+}
+
+// Incoming f_i - w_i of node n (nb: map values of n's neighbours; M: the
+// emitters' moments, FP16 only).
+template <class L, int FP16, int ODD>
+__device__ inline float gather(const void *F, int P, const int *nb, int n, int i, const float4 *M,
+                               const Phys &p)
+{
+    const int j = L::opp[i];
+    const bool fl = (i != 0) && nb[j] >= 0;
+    float raw;
+    if (!ODD || i == 0 || !fl)
+        raw = ld<FP16>(F, P, i, n);
+    else
+        raw = ld<FP16>(F, P, j, nb[j]);
+    if (!FP16) return raw;
+    const int e = fl ? nb[j] : n;
+    const int dir = fl ? i : j;
+    const float4 m = M[e];
+    return feq_bar<L>(dir, m.x, m.y, m.z, m.w, p.linear_eq) + raw * p.hs_inv;
+}
+
+// Store the outgoing value of direction i (FP32: f* - w_i; FP16: scaled deviation).
+template <class L, int FP16, int ODD>
+__device__ inline void scatter(void *F, int P, const int *nb, int n, int i, float v)
+{
+    if (!ODD || i == 0)
+        st<FP16>(F, P, L::opp[i], n, v);
+    else if (nb[i] >= 0)
+        st<FP16>(F, P, i, nb[i], v);
+    else
+        st<FP16>(F, P, L::opp[i], n, v);
+}
+
+// Non-equilibrium extrapolation (Guo, Zheng & Shi 2002) for the inlet
+// (velocity u_in) or outlet (density rho_out) node next to the interior node
+// whose post-streaming populations are fc: the boundary takes the target
+// equilibrium plus the interior node's non-equilibrium part.
+template <class L>
+__device__ inline void nee_populations(const Phys &p, bool inlet, const float (&fc)[L::Q],
+                                       float (&fb)[L::Q])
+{
+    float dr = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        dr += fc[i];
+        jx += L::ex[i] * fc[i];
+        jy += L::ey[i] * fc[i];
+        jz += L::ez[i] * fc[i];
+    }
+    const float ri = 1.f / (1.f + dr);
+    const float ux = jx * ri, uy = jy * ri, uz = jz * ri;
+    const float tdr = inlet ? dr : p.rho_out - 1.f;
+    const float tx = inlet ? p.u_in : ux, ty = inlet ? 0.f : uy, tz = inlet ? 0.f : uz;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        fb[i] = feq_bar<L>(i, tdr, tx, ty, tz, p.linear_eq) +
+                (fc[i] - feq_bar<L>(i, dr, ux, uy, uz, p.linear_eq));
+}
+
+// Scharfetter-Gummel flux from P to N with normal drift w:
+// D [B(-Pe) C_P - B(Pe) C_N], B(x) = x / (e^x - 1), Pe = w / D. Written so
+// that the (N -> P) evaluation is the exact negative: both sides form the
+// same two products and subtract them in opposite order.
+__device__ inline float sg_flux(float D, float w, float cp, float cn)
+{
+    const float pe = w / D;
+    const float a = fabsf(pe);
+    const float bp = a == 0.f ? 1.f : a / expm1f(a);  // B(|Pe|)
+    const float bm = bp + a;                          // B(-|Pe|)
+    const float b_neg = pe >= 0.f ? bm : bp;          // B(-Pe)
+    const float b_pos = pe >= 0.f ? bp : bm;          // B(Pe)
+    return D * (__fmul_rn(b_neg, cp) - __fmul_rn(b_pos, cn));
+}
+
+// Sum over the block in a fixed order (wave shuffles, then the waves in
+// order); the result is valid in thread 0. sm holds (blockDim/64) * N doubles.
+template <int N>
+__device__ inline void block_sum(double (&v)[N], double *sm, double (&out)[N])
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) sm[wave * N + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double s = 0;
+            for (int w = 0; w < nw; ++w) s += sm[w * N + k];
+            out[k] = s;
+        }
+    }
+}
+
+}  // namespace cdi

@@ -1,0 +1,226 @@
+// geometry.hip -- voxel labels from primitives and the compacted fluid-node
+// numbering (the paper's image-voxel grid, Sec. 2), plus small fill kernels.
+//
+// Labels: 0 pore, 1 adsorbing electrode, 2 inert wall. A voxel (i,j,k) is
+// solid iff some primitive contains its centre, tested exactly in int64 on
+// 1/256-lattice-unit coordinates (centre of voxel i is 128*(2i+1)).
+// Fluid voxels are numbered in lexicographic order, x fastest; the result is
+// independent of scheduling (a three-pass block scan).
+#include "cdi_internal.h"
+
+namespace cdi {
+
+namespace {
+
+__device__ inline int64_t fdiv256(int64_t a)
+{
+    // floor(a / 256) for any sign
+    return a >= 0 ? a / 256 : -((-a + 255) / 256);
+}
+
+__device__ inline int wrapi(int64_t i, int n)
+{
+    int64_t m = i % n;
+    return (int)(m < 0 ? m + n : m);
+}
+
+__global__ void init_labels_kernel(uint8_t *labels, int nx, int ny, int64_t nvox, int walls2d)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    uint8_t l = 0;
+    if (walls2d) {
+        const int y = (int)((v / nx) % ny);
+        if (y == 0 || y == ny - 1) l = 2;
+    }
+    labels[v] = l;
+}
+
+// One block per primitive; threads sweep its bounding box. Concurrent writes
+// of the value 1 to one byte are benign (same value), and inert walls are
+// never overwritten.
+__global__ void voxelize_kernel(uint8_t *labels, const int64_t *prims, int dim, int nx, int ny,
+                                int nz, int walls_y, int bx)
+{
+    const int64_t *pr = prims + 4 * (int64_t)blockIdx.x;
+    const int64_t r = pr[0], cx = pr[1], cy = pr[2], cz = pr[3];
+    const int64_t i0 = fdiv256(cx - r) - 1, i1 = fdiv256(cx + r) + 1;
+    const int64_t j0 = fdiv256(cy - r) - 1, j1 = fdiv256(cy + r) + 1;
+    int64_t k0 = 0, k1 = 0;
+    if (dim == 3) {
+        k0 = fdiv256(cz - r) - 1;
+        k1 = fdiv256(cz + r) + 1;
+    }
+    const int64_t ni = i1 - i0 + 1, nj = j1 - j0 + 1, nk = k1 - k0 + 1;
+    const int64_t total = ni * nj * nk;
+    const int64_t r2 = r * r;
+    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) {
+        const int64_t i = i0 + t % ni;
+        const int64_t j = j0 + (t / ni) % nj;
+        const int64_t k = k0 + t / (ni * nj);
+        if (i < bx || i >= nx - bx) continue;
+        int jj;
+        if (dim == 2 && walls_y) {
+            if (j < 0 || j >= ny) continue;
+            jj = (int)j;
+        } else {
+            jj = wrapi(j, ny);
+        }
+        const int kk = dim == 3 ? wrapi(k, nz) : 0;
+        const int64_t dx = 128 * (2 * i + 1) - cx;
+        const int64_t dy = 128 * (2 * j + 1) - cy;
+        const int64_t dz = dim == 3 ? 128 * (2 * k + 1) - cz : 0;
+        if (dx * dx + dy * dy + dz * dz <= r2) {
+            uint8_t *l = labels + ((int64_t)kk * ny + jj) * nx + i;
+            if (*l != 2) *l = 1;
+        }
+    }
+}
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;                        // voxels per thread
+constexpr int kScanBlock = kScanThreads * kScanItems; // voxels per block
+
+__device__ inline int block_exclusive_scan(int x, int *sm, int *total)
+{
+    // Hillis-Steele over 256 values in LDS; deterministic.
+    const int t = threadIdx.x;
+    sm[t] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int y = t >= off ? sm[t - off] : 0;
+        __syncthreads();
+        sm[t] += y;
+        __syncthreads();
+    }
+    const int incl = sm[t];
+    *total = sm[kScanThreads - 1];
+    __syncthreads();
+    return incl - x;
+}
+
+__device__ inline int load_flags(const uint8_t *labels, int64_t nvox, int64_t base, uint8_t fl[kScanItems])
+{
+    int cnt = 0;
+    if (base + kScanItems <= nvox && (((uintptr_t)(labels + base)) & 15) == 0) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(labels + base);
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            fl[k] = ((words[k >> 2] >> (8 * (k & 3))) & 0xff) == 0;
+            cnt += fl[k];
+        }
+    } else {
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t v = base + k;
+            fl[k] = (v < nvox) && labels[v] == 0;
+            cnt += fl[k];
+        }
+    }
+    return cnt;
+}
+
+__global__ void count_kernel(const uint8_t *labels, int64_t nvox, int *blk)
+{
+    __shared__ int sm[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint8_t fl[kScanItems];
+    const int cnt = load_flags(labels, nvox, base, fl);
+    int total;
+    block_exclusive_scan(cnt, sm, &total);
+    if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the per-block counts in place; total -> nfluid.
+__global__ void scan_blocks_kernel(int *blk, int64_t nblk, int64_t *nfluid)
+{
+    __shared__ int sm[kScanThreads];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblk; base += kScanThreads) {
+        const int64_t i = base + threadIdx.x;
+        const int x = i < nblk ? blk[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(x, sm, &total);
+        if (i < nblk) blk[i] = (int)(carry + ex);
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *nfluid = carry;
+}
+
+__global__ void scatter_kernel(const uint8_t *labels, int64_t nvox, const int *blk, int *map, int *fluid)
+{
+    __shared__ int sm[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint8_t fl[kScanItems];
+    const int cnt = load_flags(labels, nvox, base, fl);
+    int total;
+    int rank = blk[blockIdx.x] + block_exclusive_scan(cnt, sm, &total);
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t v = base + k;
+        if (v >= nvox) break;
+        if (fl[k]) {
+            map[v] = rank;
+            fluid[rank] = (int)v;
+            ++rank;
+        } else {
+            map[v] = labels[v] == 1 ? kElectrode : kInert;
+        }
+    }
+}
+
+template <class T>
+__global__ void fill_kernel(T *p, T v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+hipError_t fill(T *p, T v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    fill_kernel<T><<<(unsigned)blocks, 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init_labels(uint8_t *labels, int nx, int ny, int nz, int walls2d, hipStream_t s)
+{
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    init_labels_kernel<<<(unsigned)((nvox + 255) / 256), 256, 0, s>>>(labels, nx, ny, nvox, walls2d);
+    return hipGetLastError();
+}
+
+hipError_t launch_voxelize(uint8_t *labels, const int64_t *prims, int64_t nprims, int dim, int nx,
+                           int ny, int nz, int walls_y, int buffer_x, hipStream_t s)
+{
+    if (nprims <= 0) return hipSuccess;
+    voxelize_kernel<<<(unsigned)nprims, 256, 0, s>>>(labels, prims, dim, nx, ny, nz, walls_y, buffer_x);
+    return hipGetLastError();
+}
+
+int64_t compact_blocks(int64_t nvox) { return (nvox + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_compact(const uint8_t *labels, int64_t nvox, int *map, int *fluid, int *blk,
+                          int64_t *nfluid, hipStream_t s)
+{
+    const int64_t nblk = compact_blocks(nvox);
+    count_kernel<<<(unsigned)nblk, kScanThreads, 0, s>>>(labels, nvox, blk);
+    scan_blocks_kernel<<<1, kScanThreads, 0, s>>>(blk, nblk, nfluid);
+    scatter_kernel<<<(unsigned)nblk, kScanThreads, 0, s>>>(labels, nvox, blk, map, fluid);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) { return fill<float>(p, v, n, s); }
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) { return fill<uint32_t>(p, v, n, s); }
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) { return fill<double>(p, v, n, s); }
+
+}  // namespace cdi

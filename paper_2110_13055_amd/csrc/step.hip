@@ -1,0 +1,302 @@
+// step.hip -- the hot path: one lattice Boltzmann step (Eq. 7 with the BGK
+// collision of Eq. 8, half-way bounce-back at solid faces) fused with one
+// explicit finite-volume Nernst-Planck step (Eq. 3) and the adsorption flux
+// of Eq. (6), over the compacted fluid nodes. The AA storage rules and the
+// FP16 deviation format are described in device_common.h.
+//
+// The ions see the mass flux j = rho u. In a fused step the Nernst-Planck
+// part reads the flux of the previous step (jin, or the FP16 moments) for the
+// node and its face neighbours, while the LBM part writes the flux of this
+// step. Face fluxes are Scharfetter-Gummel; the two sides of a face compute
+// exactly opposite values, so solute is conserved to the rounding of the
+// update. Per tile, the adsorbed / inflow / outflow amounts are reduced in
+// FP64 in a fixed order and added to that tile's own accumulator slot.
+//
+// Inlet/outlet planes (x = 0 and x = nx - 1): the node one plane inside owns
+// the post-streaming populations the extrapolation needs, so its thread also
+// advances the boundary node (no separate pass over the scattered planes).
+#include "device_common.h"
+
+namespace cdi {
+
+namespace {
+
+// Moments, residual terms, collision and the AA store of one node whose
+// incoming populations (minus w_i) are f.
+template <class L, int FP16, int ODD, int NP>
+__device__ inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, const int *nb,
+                                const float (&f)[L::Q], double (&res)[2])
+{
+    constexpr int Q = L::Q, D = L::D;
+    float drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += f[i];
+        jx += L::ex[i] * f[i];
+        jy += L::ey[i] * f[i];
+        jz += L::ez[i] * f[i];
+    }
+    if (p.forced) {  // Guo forcing: u = (sum e f + F/2) / rho
+        jx += 0.5f * p.F[0];
+        jy += 0.5f * p.F[1];
+        jz += 0.5f * p.F[2];
+    }
+    const float rinv = 1.f / (1.f + drho);
+    const float ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
+    if (b.flags & kResid) {
+        float px, py, pz;
+        if (FP16) {
+            const float4 m = b.Min[n];
+            px = m.y;
+            py = m.z;
+            pz = m.w;
+        } else {
+            px = b.ubuf[n];
+            py = b.ubuf[P + n];
+            pz = D == 3 ? b.ubuf[2 * P + n] : 0.f;
+        }
+        const double dx = (double)ux - px, dy = (double)uy - py, dz = (double)uz - pz;
+        res[0] += dx * dx + dy * dy + dz * dz;
+        res[1] += (double)ux * ux + (double)uy * uy + (double)uz * uz;
+    }
+    if (!FP16 && (b.flags & kStoreU)) {
+        b.ubuf[n] = ux;
+        b.ubuf[P + n] = uy;
+        if (D == 3) b.ubuf[2 * P + n] = uz;
+    }
+    if (FP16) b.Mout[n] = make_float4(drho, ux, uy, uz);
+    if (NP && !FP16) {
+        b.jout[n] = jx;
+        b.jout[P + n] = jy;
+        if (D == 3) b.jout[2 * P + n] = jz;
+    }
+    const float om = p.omega;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float fe = feq_bar<L>(i, drho, ux, uy, uz, p.linear_eq);
+        float src = 0.f;
+        if (p.forced) {  // Guo, Zheng & Shi (2002) source term
+            const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+            src = p.fcoef * L::w[i] *
+                  ((3.f * (L::ex[i] - ux) + 9.f * eu * L::ex[i]) * p.F[0] +
+                   (3.f * (L::ey[i] - uy) + 9.f * eu * L::ey[i]) * p.F[1] +
+                   (3.f * (L::ez[i] - uz) + 9.f * eu * L::ez[i]) * p.F[2]);
+        }
+        float out;
+        if (FP16)
+            out = ((1.f - om) * (f[i] - fe) + src) * p.hs;
+        else
+            out = f[i] - om * (f[i] - fe) + src;
+        scatter<L, FP16, ODD>(b.f, P, nb, n, i, out);
+    }
+}
+
+template <class L, int FP16, int ODD, int LBM, int NP>
+__global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
+{
+    constexpr int Q = L::Q, D = L::D;
+    const int tile = block_tile(g);
+    const int n = tile * kTile + threadIdx.x;
+    const bool active = n < g.n_f;
+    const int P = g.P;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double res[2] = {0, 0};
+
+    if (active) {
+        const int v = g.fluid[n];
+        const int x = v % g.nx;
+        const int t = v / g.nx;
+        const int y = t % g.ny;
+        const int z = t / g.ny;
+        constexpr bool need_all = LBM && (ODD || FP16);
+        const bool edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
+        int nb[Q];
+        nb[0] = n;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
+            nb[i] = want ? nb_map<L>(g, x, y, z, i, g.periodic_x) : kOutside;
+        }
+
+        if (LBM) {
+            // a boundary node with a fluid interior neighbour is advanced by that neighbour
+            const bool by_partner = edge && ((x == 0 && nb[1] >= 0) || (x == g.nx - 1 && nb[2] >= 0));
+            if (!by_partner) {
+                float f[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) f[i] = gather<L, FP16, ODD>(b.f, P, nb, n, i, b.Min, p);
+                lbm_node<L, FP16, ODD, NP>(p, b, P, n, nb, f, res);
+                const bool inl = edge && x == 1 && nb[2] >= 0;
+                const bool outl = edge && x == g.nx - 2 && nb[1] >= 0;
+                if (inl || outl) {
+                    const int bn = inl ? nb[2] : nb[1];
+                    const int xb = inl ? 0 : g.nx - 1;
+                    int nbb[Q];
+                    nbb[0] = bn;
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) nbb[i] = nb_map<L>(g, xb, y, z, i, false);
+                    float fb[Q];
+                    nee_populations<L>(p, inl, f, fb);
+                    lbm_node<L, FP16, ODD, NP>(p, b, P, bn, nbb, fb, res);
+                }
+            }
+        }
+
+        if (NP) {
+            const float cP[2] = {b.Cin[n], b.Cin[P + n]};
+            float jP[3];
+            const bool jm = FP16 && (b.flags & kJFromM);
+            if (jm) {
+                const float4 m = b.Min[n];
+                const float r = 1.f + m.x;
+                jP[0] = r * m.y;
+                jP[1] = r * m.z;
+                jP[2] = r * m.w;
+            } else {
+                jP[0] = b.jin[n];
+                jP[1] = b.jin[P + n];
+                jP[2] = D == 3 ? b.jin[2 * P + n] : 0.f;
+            }
+            const float psiP = p.psi ? p.psi[n] : 0.f;
+            float out[2] = {0.f, 0.f}, fa[2] = {0.f, 0.f}, fi[2] = {0.f, 0.f}, fo[2] = {0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 2 * D; ++k) {
+                const int i = k + 1;
+                const int axis = k >> 1;
+                const int sgi = (k & 1) ? -1 : 1;
+                const float sg = (float)sgi;
+                const bool xb = axis == 0 && (x + sgi < 0 || x + sgi >= g.nx);
+                if (xb && p.npx != kNpxPeriodic) {
+                    if (p.npx == kNpxClosed) continue;
+                    const float dpsi = p.psi ? 0.f : -sg * p.dpsi_dx;
+                    if (sgi < 0) {  // inlet face: ghost at c0, inflow u_in
+#pragma unroll
+                        for (int s = 0; s < 2; ++s) {
+                            const float w = -p.u_in - p.z[s] * p.D[s] * dpsi;
+                            const float F = sg_flux(p.D[s], w, cP[s], p.c0);
+                            out[s] += F;
+                            fi[s] -= F;
+                        }
+                    } else {  // outlet face
+#pragma unroll
+                        for (int s = 0; s < 2; ++s) {
+                            const float w = jP[0] - p.z[s] * p.D[s] * dpsi;
+                            float F;
+                            if (p.npx == kNpxDirichlet)
+                                F = sg_flux(p.D[s], w, cP[s], p.c_out);
+                            else  // open: drift carries C_P out, or feed c0 in
+                                F = fmaxf(w, 0.f) * cP[s] + fminf(w, 0.f) * p.c0;
+                            out[s] += F;
+                            fo[s] += F;
+                        }
+                    }
+                    continue;
+                }
+                int m = nb[i];
+                if (xb) m = nb_map<L>(g, x, y, z, i, true);  // periodic ions, open flow
+                if (m == kElectrode) {  // adsorbing face, Eq. (6)
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const float F = p.keff[s] * cP[s];
+                        out[s] += F;
+                        fa[s] += F;
+                    }
+                } else if (m >= 0) {
+                    float jN;
+                    if (jm) {
+                        const float4 mm = b.Min[m];
+                        jN = (1.f + mm.x) * (axis == 0 ? mm.y : (axis == 1 ? mm.z : mm.w));
+                    } else {
+                        jN = b.jin[axis * P + m];
+                    }
+                    const float un = 0.5f * (jP[axis] + jN) * sg;
+                    const float dpsi = p.psi ? p.psi[m] - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const float w = un - p.z[s] * p.D[s] * dpsi;
+                        out[s] += sg_flux(p.D[s], w, cP[s], b.Cin[s * P + m]);
+                    }
+                }
+                // inert wall: no flux
+            }
+            b.Cout[n] = cP[0] - p.dt * out[0];
+            b.Cout[P + n] = cP[1] - p.dt * out[1];
+            acc[0] = (double)p.dt * fa[0];
+            acc[1] = (double)p.dt * fa[1];
+            acc[2] = (double)p.dt * fi[0];
+            acc[3] = (double)p.dt * fi[1];
+            acc[4] = (double)p.dt * fo[0];
+            acc[5] = (double)p.dt * fo[1];
+        }
+    }
+
+    __shared__ double sm[(kTile / 64) * 6];
+    if (NP) {
+        double s[6];
+        block_sum<6>(acc, sm, s);
+        if (threadIdx.x == 0) {
+            double *a = b.acc + (size_t)tile * 8;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) a[k] += s[k];
+        }
+        __syncthreads();
+    }
+    if (LBM && (b.flags & kResid)) {
+        double s[2];
+        block_sum<2>(res, sm, s);
+        if (threadIdx.x == 0) {
+            b.resid[2 * (size_t)tile] = s[0];
+            b.resid[2 * (size_t)tile + 1] = s[1];
+        }
+    }
+}
+
+template <class L, int FP16, int ODD, int LBM, int NP>
+void launch_t(const Grid &g, const Phys &p, const Bufs &b, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)(g.P / kTile);
+    step_kernel<L, FP16, ODD, LBM, NP><<<blocks, kTile, 0, s>>>(g, p, b);
+}
+
+template <class L, int FP16, int ODD>
+void launch_mode(int lbm, int np, const Grid &g, const Phys &p, const Bufs &b, hipStream_t s)
+{
+    if (lbm && np)
+        launch_t<L, FP16, ODD, 1, 1>(g, p, b, s);
+    else if (lbm)
+        launch_t<L, FP16, ODD, 1, 0>(g, p, b, s);
+    else
+        launch_t<L, 0, 0, 0, 1>(g, p, b, s);
+}
+
+template <class L>
+void launch_prec(int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p, const Bufs &b,
+                 hipStream_t s)
+{
+    if (fp16) {
+        if (odd)
+            launch_mode<L, 1, 1>(lbm, np, g, p, b, s);
+        else
+            launch_mode<L, 1, 0>(lbm, np, g, p, b, s);
+    } else {
+        if (odd)
+            launch_mode<L, 0, 1>(lbm, np, g, p, b, s);
+        else
+            launch_mode<L, 0, 0>(lbm, np, g, p, b, s);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p,
+                       const Bufs &b, hipStream_t s)
+{
+    if (g.P <= 0) return hipSuccess;
+    if (dim == 2)
+        launch_prec<D2Q9>(fp16, odd, lbm, np, g, p, b, s);
+    else
+        launch_prec<D3Q19>(fp16, odd, lbm, np, g, p, b, s);
+    return hipGetLastError();
+}
+
+}  // namespace cdi

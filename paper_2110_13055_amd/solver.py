@@ -1,0 +1,234 @@
+"""Python binding of the C ABI: torch supplies device memory and the stream,
+libcdi does all of the work.
+
+    geom = Geometry(dim=3, nx=128, ny=128, nz=128, kind=SPHERES, porosity=0.5,
+                    r_min=3, r_max=6, seed=2110)
+    s = Solver(geom, Params(u_in=5e-4, dpsi_vt=20.0))
+    s.flow_to_steady(1e-8)
+    s.np_step(20000)
+    print(s.adsorbed_total())
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class Geometry:
+    dim: int
+    nx: int
+    ny: int
+    nz: int = 1
+    seed: int = 2110
+    kind: int = L.DISKS
+    porosity: float = 0.7
+    r_min: float = 4.0
+    r_max: float = 8.0
+    min_gap: float = 2.0
+    walls_y: int = 1
+    buffer_x: int = 2
+    user_labels: Optional[np.ndarray] = None
+
+    @property
+    def n_vox(self) -> int:
+        return self.nx * self.ny * (1 if self.dim == 2 else self.nz)
+
+    def to_c(self):
+        g = L.CGeometry()
+        g.dim, g.nx, g.ny, g.nz = self.dim, self.nx, self.ny, (1 if self.dim == 2 else self.nz)
+        g.seed, g.kind = self.seed, self.kind
+        g.porosity, g.r_min, g.r_max, g.min_gap = self.porosity, self.r_min, self.r_max, self.min_gap
+        g.walls_y, g.buffer_x = self.walls_y, self.buffer_x
+        keep = None
+        if self.user_labels is not None:
+            keep = np.ascontiguousarray(self.user_labels, dtype=np.uint8).reshape(-1)
+            if keep.size != self.n_vox:
+                raise ValueError("user_labels must hold nx*ny*nz labels")
+            g.user_labels = keep.ctypes.data
+        return g, keep
+
+
+@dataclass
+class Params:
+    tau: float = 1.0
+    drive: int = L.INLET_OUTLET
+    equilibrium: int = L.EQ_QUADRATIC
+    u_in: float = 1e-3
+    rho_out: float = 1.0
+    body_force: tuple = (0.0, 0.0, 0.0)
+    D: tuple = (0.05, 0.076)
+    z: tuple = (1, -1)
+    c0: float = 1.0
+    c_out: float = 0.0
+    Ka: float = 0.0
+    dpsi_vt: float = 0.0
+    psi_field: object = None     # torch float32 CUDA tensor of N_f values, or None
+    np_x_bc: int = L.NPX_INLET_OUTLET
+    np_substeps: int = 1
+    precision: int = L.FP32
+
+    def to_c(self):
+        p = L.CParams()
+        p.tau, p.drive, p.equilibrium = self.tau, self.drive, self.equilibrium
+        p.u_in, p.rho_out = self.u_in, self.rho_out
+        for a in range(3):
+            p.body_force[a] = self.body_force[a]
+        for s in range(2):
+            p.D[s] = self.D[s]
+            p.z[s] = self.z[s]
+        p.c0, p.c_out, p.Ka, p.dpsi_vt = self.c0, self.c_out, self.Ka, self.dpsi_vt
+        p.psi_field = None if self.psi_field is None else self.psi_field.data_ptr()
+        p.np_x_bc, p.np_substeps, p.precision = self.np_x_bc, self.np_substeps, self.precision
+        return p
+
+
+def plan(geom: Geometry, params: Optional[Params] = None) -> L.CPlanInfo:
+    lib = L.load()
+    g, keep = geom.to_c()
+    info = L.CPlanInfo()
+    p = params.to_c() if params is not None else None
+    L.check(lib.cdi_plan(C.byref(g), None if p is None else C.byref(p), C.byref(info)), "cdi_plan")
+    return info
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Solver:
+    """One electrode instance resident on a GPU. Device buffers are torch
+    tensors owned by this object; the library only borrows them."""
+
+    def __init__(self, geom: Geometry, params: Params, device: str = "cuda", stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        self.geom, self.params = geom, params
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._sptr = C.c_void_p(self.stream.cuda_stream)
+        self._g, self._keep = geom.to_c()
+        self._p = params.to_c()
+        self.info_plan = plan(geom, params)
+        self.vox_ws = torch.empty(int(self.info_plan.vox_bytes), dtype=torch.uint8, device=self.device)
+        nf = C.c_int64()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.cdi_build_geometry(C.byref(self._g), C.c_void_p(self.vox_ws.data_ptr()),
+                                                self.vox_ws.numel(), self._sptr, C.byref(nf)),
+                    "cdi_build_geometry")
+        self.n_fluid = nf.value
+        nb = C.c_uint64()
+        L.check(self.lib.cdi_node_bytes(C.byref(self._g), C.byref(self._p), self.n_fluid, C.byref(nb)),
+                "cdi_node_bytes")
+        self.node_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.cdi_flow_init(C.byref(self._g), C.byref(self._p),
+                                           C.c_void_p(self.vox_ws.data_ptr()), self.vox_ws.numel(),
+                                           C.c_void_p(self.node_ws.data_ptr()), self.node_ws.numel(),
+                                           self.n_fluid, self._sptr, C.byref(h)), "cdi_flow_init")
+        self.h = h
+        self.dim = geom.dim
+
+    # -------------------------------------------------------------- lifecycle
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cdi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def footprint_bytes(self) -> int:
+        return self.vox_ws.numel() + self.node_ws.numel()
+
+    def info(self) -> L.CSolverInfo:
+        out = L.CSolverInfo()
+        L.check(self.lib.cdi_get_info(self.h, C.byref(out)), "cdi_get_info")
+        return out
+
+    # -------------------------------------------------------------- stepping
+    def flow_steps(self, n: int):
+        L.check(self.lib.cdi_flow_steps(self.h, n), "cdi_flow_steps")
+
+    def flow_to_steady(self, tol: float = 1e-8, max_steps: int = 10 ** 6, check_every: int = 100,
+                       raise_on_failure: bool = False):
+        steps, res = C.c_int64(), C.c_double()
+        rc = self.lib.cdi_flow_step_to_steady(self.h, tol, max_steps, check_every, C.byref(steps),
+                                              C.byref(res))
+        allow = (L.OK,) if raise_on_failure else (L.OK, L.STAGNATED, L.E_NOT_CONVERGED)
+        L.check(rc, "cdi_flow_step_to_steady", allow)
+        return rc, steps.value, res.value
+
+    def np_step(self, n: int, fused: bool = False):
+        L.check(self.lib.cdi_np_step(self.h, n, 1 if fused else 0), "cdi_np_step")
+
+    # -------------------------------------------------------------- results
+    def adsorbed_total(self) -> np.ndarray:
+        out = (C.c_double * 2)()
+        L.check(self.lib.cdi_adsorbed_total(self.h, out), "cdi_adsorbed_total")
+        return np.array(out[:])
+
+    def mass_balance(self) -> np.ndarray:
+        out = (C.c_double * 8)()
+        L.check(self.lib.cdi_mass_balance(self.h, out), "cdi_mass_balance")
+        return np.array(out[:]).reshape(2, 4)
+
+    def _get(self, fn, shape, dtype):
+        a = np.empty(shape, dtype=dtype)
+        L.check(getattr(self.lib, fn)(self.h, C.c_void_p(a.ctypes.data)), fn)
+        return a
+
+    def labels(self) -> np.ndarray:
+        return self._get("cdi_copy_labels", (self.geom.n_vox,), np.uint8)
+
+    def fluid_index(self):
+        m = np.empty(self.geom.n_vox, dtype=np.int32)
+        f = np.empty(self.n_fluid, dtype=np.int32)
+        L.check(self.lib.cdi_copy_fluid_index(self.h, C.c_void_p(m.ctypes.data), C.c_void_p(f.ctypes.data)),
+                "cdi_copy_fluid_index")
+        return m, f
+
+    def velocity(self) -> np.ndarray:
+        return self._get("cdi_copy_velocity", (self.dim, self.n_fluid), np.float32)
+
+    def density(self) -> np.ndarray:
+        return self._get("cdi_copy_density", (self.n_fluid,), np.float32)
+
+    def np_velocity(self) -> np.ndarray:
+        return self._get("cdi_copy_np_velocity", (self.dim, self.n_fluid), np.float32)
+
+    def concentration(self) -> np.ndarray:
+        return self._get("cdi_copy_concentration", (2, self.n_fluid), np.float32)
+
+    def set_np_velocity(self, j: np.ndarray):
+        a = np.ascontiguousarray(j, dtype=np.float32).reshape(self.dim, self.n_fluid)
+        L.check(self.lib.cdi_set_np_velocity(self.h, C.c_void_p(a.ctypes.data)), "cdi_set_np_velocity")
+
+    def set_concentration(self, c: np.ndarray):
+        a = np.ascontiguousarray(c, dtype=np.float32).reshape(2, self.n_fluid)
+        L.check(self.lib.cdi_set_concentration(self.h, C.c_void_p(a.ctypes.data)), "cdi_set_concentration")
+
+    def snapshot(self) -> bytes:
+        nb = C.c_uint64()
+        L.check(self.lib.cdi_snapshot_bytes(self.h, C.byref(nb)), "cdi_snapshot_bytes")
+        buf = (C.c_uint8 * nb.value)()
+        L.check(self.lib.cdi_snapshot(self.h, buf, nb.value), "cdi_snapshot")
+        return bytes(buf)
+
+    def restore(self, blob: bytes):
+        buf = (C.c_uint8 * len(blob)).from_buffer_copy(blob)
+        L.check(self.lib.cdi_restore(self.h, buf, len(blob)), "cdi_restore")
+
+    def synchronize(self):
+        self.stream.synchronize()
