@@ -218,6 +218,26 @@ int cdi_set_np_velocity(cdi_solver *s, const float *j); /* dim x N_f, prescribe 
 int cdi_copy_concentration(cdi_solver *s, float *c); /* 2 x N_f */
 int cdi_set_concentration(cdi_solver *s, const float *c); /* 2 x N_f */
 
+/* ------------------------------------------------------------ launch tuning
+ * How the step kernel is scheduled on the GPU. Results are bitwise identical
+ * for every tuning (each node's update and each tile's accumulator sum do
+ * not depend on the schedule); only the speed changes. */
+typedef struct {
+    int32_t blocks_per_cu; /* cap on resident step workgroups per compute unit (0 = none) */
+    int32_t band_rows;     /* 3D: rows per band of the tile schedule (0 = plain order) */
+} cdi_tuning;
+
+int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t);
+int cdi_get_tuning(const cdi_solver *s, cdi_tuning *t);
+
+/* Autotuner: snapshots the state to host memory, times each candidate tuning
+ * over `steps` steps (fused_flow as in cdi_np_step) with HIP events on the
+ * solver's stream, restores the state and keeps the fastest. chosen and
+ * ms_per_step (host, nullable) receive the winner and its time per step.
+ * Synchronises. */
+int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *chosen,
+                 double *ms_per_step);
+
 /* Checkpoint: the complete device state (populations, moments, fields,
  * accumulators, counters, AA parity) to and from host memory. */
 int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes);

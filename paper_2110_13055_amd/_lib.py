@@ -63,6 +63,10 @@ class CSolverInfo(C.Structure):
     ]
 
 
+class CTuning(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("band_rows", C.c_int32)]
+
+
 P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
 
 # name -> (restype, argtypes); the list of symbols include/cdi.h declares
@@ -86,6 +90,9 @@ SIGNATURES = {
     "cdi_set_np_velocity": (C.c_int, [P, P]),
     "cdi_copy_concentration": (C.c_int, [P, P]),
     "cdi_set_concentration": (C.c_int, [P, P]),
+    "cdi_set_tuning": (C.c_int, [P, P]),
+    "cdi_get_tuning": (C.c_int, [P, P]),
+    "cdi_autotune": (C.c_int, [P, I32, I32, P, P]),
     "cdi_snapshot_bytes": (C.c_int, [P, P]),
     "cdi_snapshot": (C.c_int, [P, P, U64]),
     "cdi_restore": (C.c_int, [P, P, U64]),

@@ -151,7 +151,7 @@ struct NodeLayout {
     float *tmp;
     double *acc, *resid, *part, *red;
     int *sched;
-    uint64_t bytes;
+    uint64_t state_bytes, bytes;
 };
 
 static NodeLayout node_layout(void *ws, int dim, int fp16, int64_t P, int64_t plane)
@@ -174,6 +174,7 @@ static NodeLayout node_layout(void *ws, int dim, int fp16, int64_t P, int64_t pl
     L.resid = c.take<double>(16ull * ntiles);
     L.part = c.take<double>(16ull * ntiles);
     L.red = c.take<double>(64 * 8);
+    L.state_bytes = c.off;  // everything a checkpoint must carry ends here
     L.sched = c.take<int>(4ull * ntiles);
     L.bytes = c.off;
     return L;
@@ -193,6 +194,7 @@ struct cdi_solver {
     int parity = 0, mcur = 0, jcur = 0, ccur = 0, jstate = J_INVALID;
     int64_t flow_steps = 0, np_steps = 0;
     double ka, keff[2], porosity;
+    cdi_tuning tuning{0, 0};
     Grid g;
     Phys p;
 };
@@ -253,9 +255,14 @@ int ensure_j(cdi_solver *s)
 // XCD (L2 reuse) instead of a whole plane earlier.
 constexpr int kBandRows = 16;
 
-int build_schedule(cdi_solver *s)
+int build_schedule(cdi_solver *s, int band_rows)
 {
     const int T = s->ntiles;
+    if (band_rows <= 0 || s->dim != 3) {
+        s->g.sched = nullptr;
+        s->tuning.band_rows = 0;
+        return CDI_OK;
+    }
     std::vector<int> heads(T);
     HIPCHK(launch_tile_heads(s->g, s->node.sched, s->stream));
     HIPCHK(hipMemcpyAsync(heads.data(), s->node.sched, 4ull * T, hipMemcpyDeviceToHost, s->stream));
@@ -266,13 +273,35 @@ int build_schedule(cdi_solver *s)
     for (int t = 0; t < T; ++t) {
         const int64_t v = heads[t];
         const int64_t y = (v / nx) % ny, z = v / (nx * ny);
-        key[t] = ((y / kBandRows) * s->g.nz + z) * ny + y;
+        key[t] = ((y / band_rows) * s->g.nz + z) * ny + y;
         order[t] = t;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
     HIPCHK(hipMemcpyAsync(s->node.sched, order.data(), 4ull * T, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->g.sched = s->node.sched;
+    s->tuning.band_rows = band_rows;
+    return CDI_OK;
+}
+
+// LDS bytes that leave room for at most k step workgroups per CU.
+int occupancy_pad(int k, int *pad)
+{
+    *pad = 0;
+    if (k <= 0) return CDI_OK;
+    int dev = 0, per_cu = 0, per_block = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+    HIPCHK(hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int static_lds = 1024;  // the step kernel's own reduction scratch, rounded up
+    int want = per_cu / k - static_lds;
+    want = want / 256 * 256;
+    if (want <= 0 || want + static_lds > per_block)
+        return fail(CDI_E_INVALID, "blocks_per_cu %d needs %d bytes of LDS per workgroup (limit %d)", k,
+                    want + static_lds, per_block);
+    // k + 1 workgroups must not fit
+    if ((k + 1) * (want + static_lds) <= per_cu) want += 256;
+    *pad = want;
     return CDI_OK;
 }
 
@@ -458,6 +487,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     g.fluid = V.fluid;
     g.map = V.map;
     g.sched = nullptr;
+    g.lds_pad = 0;
     Phys &p = s->p;
     p.omega = (float)(1.0 / params->tau);
     p.fcoef = (float)(1.0 - 0.5 / params->tau);
@@ -466,6 +496,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     p.linear_eq = params->equilibrium == CDI_EQ_LINEAR;
     for (int k = 0; k < 2; ++k) {
         p.D[k] = (float)params->D[k];
+        p.invD[k] = (float)(1.0 / params->D[k]);
         p.z[k] = (float)params->z[k];
         p.keff[k] = (float)s->keff[k];
     }
@@ -500,7 +531,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     chk(launch_fill_f32(N.C[1], (float)params->c0, 2 * P, st));
     chk(launch_fill_f64(N.acc, 0.0, 8ll * s->ntiles, st));
     chk(launch_fill_f64(N.resid, 0.0, 2ll * s->ntiles, st));
-    if (err == CDI_OK && s->dim == 3) err = build_schedule(s);
+    if (err == CDI_OK && s->dim == 3) err = build_schedule(s, kBandRows);
     if (err != CDI_OK) {
         delete s;
         return err;
@@ -708,18 +739,18 @@ int cdi_set_concentration(cdi_solver *s, const float *c)
 int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes)
 {
     if (!s || !bytes) return fail(CDI_E_INVALID, "NULL argument");
-    *bytes = sizeof(SnapHeader) + s->node.bytes;
+    *bytes = sizeof(SnapHeader) + s->node.state_bytes;
     return CDI_OK;
 }
 
 int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes)
 {
     if (!s || !host) return fail(CDI_E_INVALID, "NULL argument");
-    if (bytes < sizeof(SnapHeader) + s->node.bytes) return fail(CDI_E_BUFFER, "snapshot buffer too small");
-    SnapHeader h{kSnapMagic, s->node.bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, 0,
+    if (bytes < sizeof(SnapHeader) + s->node.state_bytes) return fail(CDI_E_BUFFER, "snapshot buffer too small");
+    SnapHeader h{kSnapMagic, s->node.state_bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, 0,
                  s->flow_steps, s->np_steps, s->nf};
     std::memcpy(host, &h, sizeof h);
-    return d2h(s, (uint8_t *)host + sizeof h, s->node.f, s->node.bytes);
+    return d2h(s, (uint8_t *)host + sizeof h, s->node.f, s->node.state_bytes);
 }
 
 int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
@@ -728,10 +759,10 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
     SnapHeader h;
     if (bytes < sizeof h) return fail(CDI_E_BUFFER, "snapshot too small");
     std::memcpy(&h, host, sizeof h);
-    if (h.magic != kSnapMagic || h.bytes != s->node.bytes || h.nf != s->nf ||
+    if (h.magic != kSnapMagic || h.bytes != s->node.state_bytes || h.nf != s->nf ||
         bytes < sizeof h + h.bytes)
         return fail(CDI_E_INVALID, "snapshot does not belong to this solver layout");
-    int rc = h2d(s, s->node.f, (const uint8_t *)host + sizeof h, s->node.bytes);
+    int rc = h2d(s, s->node.f, (const uint8_t *)host + sizeof h, s->node.state_bytes);
     if (rc) return rc;
     s->parity = h.parity;
     s->mcur = h.mcur;
@@ -740,6 +771,77 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
     s->jstate = h.jstate;
     s->flow_steps = h.flow_steps;
     s->np_steps = h.np_steps;
+    return CDI_OK;
+}
+
+int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t)
+{
+    if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0) return fail(CDI_E_INVALID, "bad tuning");
+    int pad = 0;
+    int rc = occupancy_pad(t->blocks_per_cu, &pad);
+    if (rc) return rc;
+    if (t->band_rows != s->tuning.band_rows || (t->band_rows > 0 && !s->g.sched))
+        if ((rc = build_schedule(s, t->band_rows)) != CDI_OK) return rc;
+    s->g.lds_pad = pad;
+    s->tuning.blocks_per_cu = t->blocks_per_cu;
+    return CDI_OK;
+}
+
+int cdi_get_tuning(const cdi_solver *s, cdi_tuning *t)
+{
+    if (!s || !t) return fail(CDI_E_INVALID, "NULL argument");
+    *t = s->tuning;
+    return CDI_OK;
+}
+
+int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *chosen, double *ms_per_step)
+{
+    if (!s || steps < 2) return fail(CDI_E_INVALID, "autotune needs a solver and steps >= 2");
+    if (steps & 1) ++steps;  // whole AA step pairs
+    uint64_t nb = 0;
+    int rc = cdi_snapshot_bytes(s, &nb);
+    if (rc) return rc;
+    std::vector<uint8_t> snap(nb);
+    if ((rc = cdi_snapshot(s, snap.data(), nb)) != CDI_OK) return rc;
+    const cdi_tuning start = s->tuning;
+    std::vector<cdi_tuning> cands;
+    const int occ[] = {0, 2, 3, 4, 6};
+    const int bands[] = {0, 8, 16, 32};
+    for (int k : occ)
+        for (int r : bands)
+            if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r});
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    cdi_tuning best = start;
+    float best_ms = INFINITY;
+    for (const cdi_tuning &c : cands) {
+        if (cdi_set_tuning(s, &c) != CDI_OK) continue;  // e.g. LDS cap not allowed here
+        if ((rc = cdi_restore(s, snap.data(), nb)) != CDI_OK) break;
+        // one untimed pair, then the timed steps
+        rc = fused_flow ? cdi_np_step(s, 2, 1) : cdi_flow_steps(s, 2);
+        if (rc) break;
+        HIPCHK(hipEventRecord(e0, s->stream));
+        rc = fused_flow ? cdi_np_step(s, steps, 1) : cdi_flow_steps(s, steps);
+        if (rc) break;
+        HIPCHK(hipEventRecord(e1, s->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int rc2 = cdi_set_tuning(s, &best);
+    int rc3 = cdi_restore(s, snap.data(), nb);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (rc3) return rc3;
+    if (chosen) *chosen = best;
+    if (ms_per_step) *ms_per_step = best_ms / steps;
     return CDI_OK;
 }
 

@@ -73,6 +73,9 @@ struct Grid {
     // (band of rows, z) so the planes above and below a tile were visited
     // shortly before by the same XCD and are still in its L2.
     const int *sched;
+    // dynamic LDS reserved per step workgroup: caps the workgroups resident
+    // per CU (and so the working set the L2 must hold); 0 = no cap
+    int lds_pad;
 };
 
 struct Phys {
@@ -82,7 +85,7 @@ struct Phys {
     int forced;
     int linear_eq;
     // Nernst-Planck
-    float D[2], z[2], keff[2];
+    float D[2], invD[2], z[2], keff[2];
     float c0, c_out, u_in;
     float rho_out;     // outlet density of the flow
     float dpsi_dx;     // ramp drop per cell (dpsi / nx)

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
                             const float w = -p.u_in - p.z[s] * p.D[s] * dpsi;
-                            const float F = sg_flux(p.D[s], w, cP[s], p.c0);
+                            const float F = sg_flux(p.D[s], p.invD[s], w, cP[s], p.c0);
                             out[s] += F;
                             fi[s] -= F;
                         }
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
                             const float w = jP[0] - p.z[s] * p.D[s] * dpsi;
                             float F;
                             if (p.npx == kNpxDirichlet)
-                                F = sg_flux(p.D[s], w, cP[s], p.c_out);
+                                F = sg_flux(p.D[s], p.invD[s], w, cP[s], p.c_out);
                             else  // open: drift carries C_P out, or feed c0 in
                                 F = fmaxf(w, 0.f) * cP[s] + fminf(w, 0.f) * p.c0;
                             out[s] += F;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
                         const float w = un - p.z[s] * p.D[s] * dpsi;
-                        out[s] += sg_flux(p.D[s], w, cP[s], b.Cin[s * P + m]);
+                        out[s] += sg_flux(p.D[s], p.invD[s], w, cP[s], b.Cin[s * P + m]);
                     }
                 }
                 // inert wall: no flux
@@ -231,6 +231,8 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
     }
 
     __shared__ double sm[(kTile / 64) * 6];
+    extern __shared__ double lds_pad[];  // sized at launch: occupancy cap only
+    (void)lds_pad;
     if (NP) {
         double s[6];
         block_sum<6>(acc, sm, s);
@@ -255,7 +257,7 @@ template <class L, int FP16, int ODD, int LBM, int NP>
 void launch_t(const Grid &g, const Phys &p, const Bufs &b, hipStream_t s)
 {
     const unsigned blocks = (unsigned)(g.P / kTile);
-    step_kernel<L, FP16, ODD, LBM, NP><<<blocks, kTile, 0, s>>>(g, p, b);
+    step_kernel<L, FP16, ODD, LBM, NP><<<blocks, kTile, (size_t)g.lds_pad, s>>>(g, p, b);
 }
 
 template <class L, int FP16, int ODD>

@@ -219,6 +219,22 @@ class Solver:
         a = np.ascontiguousarray(c, dtype=np.float32).reshape(2, self.n_fluid)
         L.check(self.lib.cdi_set_concentration(self.h, C.c_void_p(a.ctypes.data)), "cdi_set_concentration")
 
+    # -------------------------------------------------------------- tuning
+    def tuning(self):
+        t = L.CTuning()
+        L.check(self.lib.cdi_get_tuning(self.h, C.byref(t)), "cdi_get_tuning")
+        return (t.blocks_per_cu, t.band_rows)
+
+    def set_tuning(self, blocks_per_cu: int = 0, band_rows: int = 0):
+        t = L.CTuning(blocks_per_cu, band_rows)
+        L.check(self.lib.cdi_set_tuning(self.h, C.byref(t)), "cdi_set_tuning")
+
+    def autotune(self, steps: int = 4, fused: bool = True):
+        t, ms = L.CTuning(), C.c_double()
+        L.check(self.lib.cdi_autotune(self.h, steps, 1 if fused else 0, C.byref(t), C.byref(ms)),
+                "cdi_autotune")
+        return (t.blocks_per_cu, t.band_rows), ms.value
+
     def snapshot(self) -> bytes:
         nb = C.c_uint64()
         L.check(self.lib.cdi_snapshot_bytes(self.h, C.byref(nb)), "cdi_snapshot_bytes")

@@ -257,6 +257,32 @@ def test_snapshot_restore_continues_bitwise():
     assert np.array_equal(u1, s.velocity())
 
 
+def test_results_do_not_depend_on_tuning_and_autotune_restores_state():
+    outs = []
+    for occ, band in ((0, 0), (3, 8), (6, 32)):
+        g, p = small3d(seed=13)
+        s = Solver(g, p)
+        s.set_tuning(occ, band)
+        assert s.tuning() == (occ, band)
+        s.flow_steps(21)
+        s.np_step(30, fused=True)
+        outs.append((s.concentration(), s.velocity(), s.adsorbed_total()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    g, p = small3d(seed=13)
+    s = Solver(g, p)
+    s.flow_steps(21)
+    before = (s.concentration(), s.velocity(), s.info().flow_steps)
+    best, ms = s.autotune(steps=4, fused=True)
+    assert ms > 0
+    after = (s.concentration(), s.velocity(), s.info().flow_steps)
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    assert before[2] == after[2]
+    s.np_step(30, fused=True)
+    assert np.array_equal(outs[0][0], s.concentration())
+
+
 def test_two_runs_are_bitwise_identical():
     outs = []
     for _ in range(2):
