@@ -18,8 +18,8 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
     constexpr int Q = L::Q, D = L::D;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.n_f) return;
-    const int v = g.fluid[n];
-    const int x = v % g.nx, t = v / g.nx, y = t % g.ny, z = t / g.ny;
+    int x, y, z;
+    unpack_xyz(g, g.fluid[n], x, y, z);
     int src = n, sx = x;
     bool inlet = false;
     if (nee && g.inout && (x == 0 || x == g.nx - 1)) {
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
     }
 }
 
-__global__ void tile_heads_kernel(Grid g, int *heads)
+__global__ void tile_heads_kernel(Grid g, uint32_t *heads)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t * kTile < g.n_f) heads[t] = g.fluid[t * kTile];
@@ -150,8 +150,8 @@ __global__ __launch_bounds__(kTile) void stability_kernel(Grid g, Phys p, const 
     const int n = blockIdx.x * kTile + threadIdx.x;
     float worst = 0.f;
     if (n < g.n_f) {
-        const int v = g.fluid[n];
-        const int x = v % g.nx, t = v / g.nx, y = t % g.ny, z = t / g.ny;
+        int x, y, z;
+        unpack_xyz(g, g.fluid[n], x, y, z);
         const int P = g.P;
         const float psiP = p.psi ? p.psi[n] : 0.f;
         for (int s = 0; s < 2; ++s) {
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kTile) void stability_kernel(Grid g, Phys p, const 
 
 }  // namespace
 
-hipError_t launch_tile_heads(const Grid &g, int *heads, hipStream_t s)
+hipError_t launch_tile_heads(const Grid &g, uint32_t *heads, hipStream_t s)
 {
     const int tiles = g.P / kTile;
     if (tiles == 0) return hipSuccess;

@@ -63,6 +63,18 @@ int check_geometry(const cdi_geometry *g)
     if (g->nx < 4 || g->ny < 1 || nz < 1) return fail(CDI_E_INVALID, "lattice too small (nx >= 4)");
     const double nvox = (double)g->nx * g->ny * nz;
     if (nvox >= 2147483647.0) return fail(CDI_E_INVALID, "nx*ny*nz must be < 2^31");
+    {
+        int bits = 0;
+        for (int n : {g->nx, g->ny, nz}) {
+            int b = 0;
+            while ((1ll << b) < n) ++b;
+            bits += b;
+        }
+        if (bits > 32) return fail(CDI_E_INVALID, "lattice too large: packed node coordinates need %d bits", bits);
+        // the padded brick enumeration must stay below 2^31 as well
+        const double padded = (double)((g->nx + 15) / 8 * 8) * ((g->ny + 15) / 8 * 8) * ((nz + 7) / 8 * 8);
+        if (padded >= 2147483647.0) return fail(CDI_E_INVALID, "padded lattice must hold < 2^31 voxels");
+    }
     if (g->kind == CDI_USER_LABELS) {
         if (!g->user_labels) return fail(CDI_E_INVALID, "user_labels is NULL");
         return CDI_OK;
@@ -116,29 +128,66 @@ int make_prims(const cdi_geometry *g, std::vector<geomgen_prim> &out, int64_t *n
     return CDI_OK;
 }
 
+// Voxel-level workspace: labels, the public (lexicographic) fluid map and
+// list, and the internal brick-ordered map, node list and permutation.
 struct VoxLayout {
     uint8_t *labels;
     int *map, *fluid, *blk;
-    int64_t *nfluid;
+    int *imap, *lex2int, *blk2;
+    uint32_t *ifluid;
+    int64_t *nfluid, *nfluid2;
     int64_t *prims;
+    Bricks bk;
     uint64_t bytes;
 };
 
-VoxLayout vox_layout(void *ws, int64_t nvox, int64_t nprims)
+int64_t geom_nvox(const cdi_geometry *g) { return (int64_t)g->nx * g->ny * (g->dim == 2 ? 1 : g->nz); }
+
+// bits needed to hold 0 .. n-1
+int coord_bits(int n)
 {
+    int b = 0;
+    while ((1ll << b) < n) ++b;
+    return b;
+}
+
+// Bricks of 8x8x8 voxels in 3D and 16x16 in 2D.
+Bricks make_bricks(const cdi_geometry *g)
+{
+    Bricks k;
+    const int nz = g->dim == 2 ? 1 : g->nz;
+    k.bsx = g->dim == 2 ? 4 : 3;
+    k.bsy = g->dim == 2 ? 4 : 3;
+    k.bsz = g->dim == 2 ? 0 : 3;
+    k.nbx = (g->nx + (1 << k.bsx) - 1) >> k.bsx;
+    k.nby = (g->ny + (1 << k.bsy) - 1) >> k.bsy;
+    k.nbz = (nz + (1 << k.bsz) - 1) >> k.bsz;
+    k.cbx = coord_bits(g->nx);
+    k.cby = coord_bits(g->ny);
+    return k;
+}
+
+VoxLayout vox_layout(void *ws, const cdi_geometry *g, int64_t nprims)
+{
+    const int64_t nvox = geom_nvox(g);
     Carver c(ws);
     VoxLayout L;
+    L.bk = make_bricks(g);
+    const int64_t E = brick_enum_size(L.bk);
     L.labels = c.take<uint8_t>((uint64_t)nvox);
     L.map = c.take<int>(4ull * nvox);
     L.fluid = c.take<int>(4ull * nvox);
     L.blk = c.take<int>(4ull * (uint64_t)compact_blocks(nvox));
+    L.imap = c.take<int>(4ull * E);
+    L.ifluid = c.take<uint32_t>(4ull * nvox);
+    L.lex2int = c.take<int>(4ull * nvox);
+    L.blk2 = c.take<int>(4ull * (uint64_t)compact_blocks(E));
     L.nfluid = c.take<int64_t>(8);
+    L.nfluid2 = c.take<int64_t>(8);
     L.prims = c.take<int64_t>(32ull * (uint64_t)(nprims > 0 ? nprims : 1));
     L.bytes = c.off;
     return L;
 }
-
-int64_t geom_nvox(const cdi_geometry *g) { return (int64_t)g->nx * g->ny * (g->dim == 2 ? 1 : g->nz); }
 
 }  // namespace
 
@@ -149,6 +198,8 @@ struct NodeLayout {
     float *ubuf;
     float *C[2];
     float *tmp;
+    float *xfer;  // lexicographic staging for host copies (4 planes of N_f)
+    float *psi;   // prescribed potential in internal node order
     double *acc, *resid, *part, *red;
     int *sched;
     uint64_t state_bytes, bytes;
@@ -170,6 +221,8 @@ static NodeLayout node_layout(void *ws, int dim, int fp16, int64_t P, int64_t pl
     L.C[0] = c.take<float>(8ull * P);
     L.C[1] = c.take<float>(8ull * P);
     L.tmp = c.take<float>(4ull * (1 + dim) * P);
+    L.xfer = c.take<float>(16ull * P);
+    L.psi = c.take<float>(4ull * P);
     L.acc = c.take<double>(64ull * ntiles);
     L.resid = c.take<double>(16ull * ntiles);
     L.part = c.take<double>(16ull * ntiles);
@@ -263,16 +316,17 @@ int build_schedule(cdi_solver *s, int band_rows)
         s->tuning.band_rows = 0;
         return CDI_OK;
     }
-    std::vector<int> heads(T);
-    HIPCHK(launch_tile_heads(s->g, s->node.sched, s->stream));
+    std::vector<uint32_t> heads(T);
+    HIPCHK(launch_tile_heads(s->g, (uint32_t *)s->node.sched, s->stream));
     HIPCHK(hipMemcpyAsync(heads.data(), s->node.sched, 4ull * T, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     const int64_t nx = s->g.nx, ny = s->g.ny;
     std::vector<int64_t> key(T);
     std::vector<int> order(T);
     for (int t = 0; t < T; ++t) {
-        const int64_t v = heads[t];
-        const int64_t y = (v / nx) % ny, z = v / (nx * ny);
+        const uint32_t c = heads[t];
+        const int64_t y = (c >> s->g.bk.cbx) & ((1u << s->g.bk.cby) - 1);
+        const int64_t z = c >> (s->g.bk.cbx + s->g.bk.cby);
         key[t] = ((y / band_rows) * s->g.nz + z) * ny + y;
         order[t] = t;
     }
@@ -319,21 +373,20 @@ int h2d(cdi_solver *s, void *dst, const void *src, uint64_t bytes)
     return CDI_OK;
 }
 
-// d planes of stride P on the device <-> d planes of N_f on the host
+// d planes of stride P in internal node order on the device <-> d planes of
+// N_f in lexicographic (public) order on the host
 int planes_d2h(cdi_solver *s, float *host, const float *dev, int d)
 {
-    for (int k = 0; k < d; ++k)
-        HIPCHK(hipMemcpyAsync(host + (size_t)k * s->nf, dev + (size_t)k * s->P, 4ull * s->nf,
-                              hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(launch_permute(dev, s->node.xfer, s->vox.lex2int, (int)s->nf, s->P, d, 1, s->stream));
+    HIPCHK(hipMemcpyAsync(host, s->node.xfer, 4ull * s->nf * d, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return CDI_OK;
 }
 
 int planes_h2d(cdi_solver *s, float *dev, const float *host, int d)
 {
-    for (int k = 0; k < d; ++k)
-        HIPCHK(hipMemcpyAsync(dev + (size_t)k * s->P, host + (size_t)k * s->nf, 4ull * s->nf,
-                              hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->node.xfer, host, 4ull * s->nf * d, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(launch_permute(s->node.xfer, dev, s->vox.lex2int, (int)s->nf, s->P, d, 0, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return CDI_OK;
 }
@@ -368,7 +421,7 @@ int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *
     out->n_vox = nvox;
     out->n_prims = nprims;
     out->n_fluid_est = nf_est;
-    out->vox_bytes = vox_layout(nullptr, nvox, nprims).bytes;
+    out->vox_bytes = vox_layout(nullptr, geom, nprims).bytes;
     const int dim = geom->dim;
     const int fp16 = params ? params->precision == CDI_FP16_DEV : 0;
     const int Q = dim == 2 ? 9 : 19;
@@ -388,7 +441,7 @@ int cdi_build_geometry(const cdi_geometry *geom, void *vox_ws, uint64_t vox_ws_b
     std::vector<geomgen_prim> pr;
     if ((rc = make_prims(geom, pr, nullptr)) != CDI_OK) return rc;
     const int64_t nprims = (int64_t)pr.size();
-    VoxLayout L = vox_layout(vox_ws, nvox, nprims);
+    VoxLayout L = vox_layout(vox_ws, geom, nprims);
     if (vox_ws_bytes < L.bytes) return fail(CDI_E_BUFFER, "vox_ws too small: %llu < %llu",
                                             (unsigned long long)vox_ws_bytes, (unsigned long long)L.bytes);
     hipStream_t st = (hipStream_t)stream;
@@ -404,11 +457,16 @@ int cdi_build_geometry(const cdi_geometry *geom, void *vox_ws, uint64_t vox_ws_b
                                geom->walls_y, geom->buffer_x, st));
     }
     HIPCHK(launch_compact(L.labels, nvox, L.map, L.fluid, L.blk, L.nfluid, st));
-    int64_t nf = 0;
-    HIPCHK(hipMemcpyAsync(&nf, L.nfluid, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_compact_bricks(L.labels, L.map, geom->nx, geom->ny, nz, L.bk, L.imap, L.ifluid,
+                                 L.lex2int, L.blk2, L.nfluid2, st));
+    int64_t nf[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&nf[0], L.nfluid, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&nf[1], L.nfluid2, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (n_fluid) *n_fluid = nf;
-    if (nf == 0) return fail(CDI_E_GEOMETRY, "geometry has no fluid voxel");
+    if (nf[0] != nf[1]) return fail(CDI_E_DEVICE, "fluid counts disagree (%lld vs %lld)", (long long)nf[0],
+                                    (long long)nf[1]);
+    if (n_fluid) *n_fluid = nf[0];
+    if (nf[0] == 0) return fail(CDI_E_GEOMETRY, "geometry has no fluid voxel");
     g_err[0] = 0;
     return CDI_OK;
 }
@@ -445,7 +503,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
         nprims = geomgen_sphere_count(geom->nx, geom->ny, geom->nz, geom->buffer_x, geom->porosity,
                                       geom->r_min, geom->r_max);
     }
-    VoxLayout V = vox_layout(vox_ws, nvox, nprims);
+    VoxLayout V = vox_layout(vox_ws, geom, nprims);
     if (vox_ws_bytes < V.bytes) return fail(CDI_E_BUFFER, "vox_ws too small");
     const int fp16 = params->precision == CDI_FP16_DEV;
     const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
@@ -484,8 +542,9 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     g.P = (int)P;
     g.periodic_x = params->drive == CDI_BODY_FORCE;
     g.inout = params->drive == CDI_INLET_OUTLET;
-    g.fluid = V.fluid;
-    g.map = V.map;
+    g.bk = V.bk;
+    g.fluid = V.ifluid;
+    g.map = V.imap;
     g.sched = nullptr;
     g.lds_pad = 0;
     Phys &p = s->p;
@@ -507,7 +566,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     p.dpsi_dx = (float)(params->dpsi_vt / geom->nx);
     p.npx = params->np_x_bc;
     p.dt = (float)(1.0 / params->np_substeps);
-    p.psi = params->psi_field;
+    p.psi = params->psi_field ? N.psi : nullptr;  // filled below in internal order
     p.hs = kHalfScale;
     p.hs_inv = 1.f / kHalfScale;
 
@@ -527,11 +586,13 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     chk(launch_fill_f32(N.j[0], 0.f, (int64_t)s->dim * P, st));
     chk(launch_fill_f32(N.j[1], 0.f, (int64_t)s->dim * P, st));
     chk(launch_fill_f32(N.ubuf, 0.f, (int64_t)s->dim * P, st));
+    if (params->psi_field)
+        chk(launch_permute(params->psi_field, N.psi, V.lex2int, (int)n_fluid, (int)P, 1, 0, st));
     chk(launch_fill_f32(N.C[0], (float)params->c0, 2 * P, st));
     chk(launch_fill_f32(N.C[1], (float)params->c0, 2 * P, st));
     chk(launch_fill_f64(N.acc, 0.0, 8ll * s->ntiles, st));
     chk(launch_fill_f64(N.resid, 0.0, 2ll * s->ntiles, st));
-    if (err == CDI_OK && s->dim == 3) err = build_schedule(s, kBandRows);
+    if (err == CDI_OK) err = build_schedule(s, 0);  // bricks already give locality
     if (err != CDI_OK) {
         delete s;
         return err;

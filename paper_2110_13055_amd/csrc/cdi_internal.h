@@ -61,14 +61,40 @@ constexpr int kJFromM = 4;    // FP16 fused: ions read j from the moments buffer
 constexpr int kNee = 8;       // the stored state carries inlet/outlet extrapolation
                               // (every state after the first step)
 
+// Internal node order: fluid nodes are numbered brick by brick (bricks of
+// 2^bsx x 2^bsy x 2^bsz voxels, bricks in x-fastest order, voxels inside a
+// brick x-fastest), so that a workgroup's nodes and most of their lattice
+// neighbours share a small block of memory. The public numbering (fields
+// handed to the caller, the fluid index map) stays lexicographic.
+struct Bricks {
+    int bsx, bsy, bsz;  // log2 of the brick edge lengths
+    int nbx, nby, nbz;  // bricks along each axis (padded)
+    int cbx, cby;       // bits of x and y in a packed node coordinate
+};
+
+// Packed node coordinates: x | y << cbx | z << (cbx + cby), 32 bits.
+__host__ __device__ inline uint32_t pack_xyz(const Bricks &k, int x, int y, int z)
+{
+    return (uint32_t)x | ((uint32_t)y << k.cbx) | ((uint32_t)z << (k.cbx + k.cby));
+}
+
+__host__ __device__ inline int64_t brick_index(const Bricks &k, int x, int y, int z)
+{
+    const int64_t b = ((int64_t)(z >> k.bsz) * k.nby + (y >> k.bsy)) * k.nbx + (x >> k.bsx);
+    const int l = ((((z & ((1 << k.bsz) - 1)) << k.bsy) | (y & ((1 << k.bsy) - 1))) << k.bsx) |
+                  (x & ((1 << k.bsx) - 1));
+    return (b << (k.bsx + k.bsy + k.bsz)) | l;
+}
+
 struct Grid {
     int nx, ny, nz;
     int n_f;         // fluid nodes
     int P;           // plane stride (multiple of kTile)
     int periodic_x;  // LBM periodic in x (body-force drive)
     int inout;       // inlet/outlet planes at x = 0 and x = nx - 1
-    const int *fluid;
-    const int *map;
+    Bricks bk;
+    const uint32_t *fluid;  // internal node -> packed (x, y, z)
+    const int *map;         // brick-ordered voxel -> internal node, or kElectrode / kInert
     // Tile schedule: XCD-local position -> tile. Tiles are ordered by
     // (band of rows, z) so the planes above and below a tile were visited
     // shortly before by the same XCD and are still in its L2.
@@ -118,6 +144,18 @@ hipError_t launch_voxelize(uint8_t *labels, const int64_t *prims, int64_t nprims
 hipError_t launch_compact(const uint8_t *labels, int64_t nvox, int *map, int *fluid, int *blk,
                           int64_t *nfluid, hipStream_t s);
 int64_t compact_blocks(int64_t nvox);
+// Internal (brick-ordered) numbering of the fluid voxels: imap over the
+// brick enumeration, ifluid[node] = lexicographic voxel, and lex2int[k] =
+// internal node of lexicographic fluid node k (needs the lexicographic map).
+hipError_t launch_compact_bricks(const uint8_t *labels, const int *lexmap, int nx, int ny, int nz,
+                                 const Bricks &bk, int *imap, uint32_t *ifluid, int *lex2int, int *blk,
+                                 int64_t *nfluid, hipStream_t s);
+int64_t brick_enum_size(const Bricks &bk);
+// Reorder d planes between the internal (stride P) and lexicographic (stride
+// n_f) node orders. to_lex: dst[c*n_f + k] = src[c*P + lex2int[k]]; else the
+// inverse scatter.
+hipError_t launch_permute(const float *src, float *dst, const int *lex2int, int n_f, int P, int d,
+                          int to_lex, hipStream_t s);
 
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -131,8 +169,8 @@ hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &
 // j (nullable, d planes).
 hipError_t launch_moments(int dim, int fp16, int odd, int nee, const Grid &g, const Phys &p,
                           const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s);
-// First-node voxel of every tile (for the host-side tile schedule).
-hipError_t launch_tile_heads(const Grid &g, int *heads, hipStream_t s);
+// Packed coordinates of the first node of every tile (host-side tile schedule).
+hipError_t launch_tile_heads(const Grid &g, uint32_t *heads, hipStream_t s);
 // j = (1 + drho) u from the FP16 moments buffer.
 hipError_t launch_j_from_m(int dim, const Grid &g, const float4 *M, float *j, hipStream_t s);
 // Deterministic single-block sums: out[k] = sum_t in[t*stride + k], k < width.

@@ -57,7 +57,64 @@ __device__ inline int nb_map(const Grid &g, int x, int y, int z, int i, bool per
         zn = z + L::ez[i];
         zn = zn < 0 ? zn + g.nz : (zn >= g.nz ? zn - g.nz : zn);
     }
-    return g.map[((int64_t)zn * g.ny + yn) * g.nx + xn];
+    return g.map[brick_index(g.bk, xn, yn, zn)];
+}
+
+__device__ inline void unpack_xyz(const Grid &g, uint32_t c, int &x, int &y, int &z)
+{
+    x = (int)(c & ((1u << g.bk.cbx) - 1));
+    y = (int)((c >> g.bk.cbx) & ((1u << g.bk.cby) - 1));
+    z = (int)(c >> (g.bk.cbx + g.bk.cby));
+}
+
+// Neighbour lookup context of one voxel: for each axis and offset -1/0/+1,
+// the brick part and the in-brick part of the neighbour's brick-ordered
+// index, so that each lattice direction costs a few integer operations.
+struct NbCtx {
+    int bx[3], lx[3];  // bx < 0: beyond an open x end
+    int by[3], ly[3];
+    int bz[3], lz[3];
+};
+
+template <class L>
+__device__ inline void nb_ctx(const Grid &g, int x, int y, int z, bool periodic_x, NbCtx &c)
+{
+    const Bricks &k = g.bk;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int xn = x + d - 1;
+        bool out = false;
+        if (xn < 0 || xn >= g.nx) {
+            out = !periodic_x;
+            xn = xn < 0 ? xn + g.nx : xn - g.nx;
+        }
+        c.bx[d] = out ? -1 : (xn >> k.bsx);
+        c.lx[d] = xn & ((1 << k.bsx) - 1);
+        int yn = y + d - 1;
+        yn = yn < 0 ? yn + g.ny : (yn >= g.ny ? yn - g.ny : yn);
+        c.by[d] = (yn >> k.bsy) * k.nbx;
+        c.ly[d] = (yn & ((1 << k.bsy) - 1)) << k.bsx;
+        if (L::D == 3) {
+            int zn = z + d - 1;
+            zn = zn < 0 ? zn + g.nz : (zn >= g.nz ? zn - g.nz : zn);
+            c.bz[d] = (zn >> k.bsz) * k.nbx * k.nby;
+            c.lz[d] = (zn & ((1 << k.bsz) - 1)) << (k.bsx + k.bsy);
+        } else {
+            c.bz[d] = 0;
+            c.lz[d] = 0;
+        }
+    }
+}
+
+// map value of the neighbour along direction i (see nb_map).
+template <class L>
+__device__ inline int nb_get(const Grid &g, const NbCtx &c, int i)
+{
+    const int dx = L::ex[i] + 1, dy = L::ey[i] + 1, dz = L::ez[i] + 1;
+    if (c.bx[dx] < 0) return kOutside;
+    const int V = g.bk.bsx + g.bk.bsy + g.bk.bsz;
+    const int e = ((c.bx[dx] + c.by[dy] + c.bz[dz]) << V) | (c.lx[dx] | c.ly[dy] | c.lz[dz]);
+    return g.map[e];
 }
 
 // BGK equilibrium minus w_i, from rho - 1 and u: quadratic in u, or its

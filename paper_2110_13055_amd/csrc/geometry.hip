@@ -172,6 +172,95 @@ __global__ void scatter_kernel(const uint8_t *labels, int64_t nvox, const int *b
     }
 }
 
+// Brick enumeration index e -> voxel coordinates; false for padding voxels.
+__device__ inline bool brick_voxel(const Bricks &k, int nx, int ny, int nz, int64_t e, int64_t *v)
+{
+    const int V = k.bsx + k.bsy + k.bsz;
+    const int64_t b = e >> V;
+    const int l = (int)(e & ((1 << V) - 1));
+    const int x = (int)((b % k.nbx) << k.bsx) | (l & ((1 << k.bsx) - 1));
+    const int y = (int)(((b / k.nbx) % k.nby) << k.bsy) | ((l >> k.bsx) & ((1 << k.bsy) - 1));
+    const int z = (int)((b / ((int64_t)k.nbx * k.nby)) << k.bsz) | (l >> (k.bsx + k.bsy));
+    if (x >= nx || y >= ny || z >= nz) return false;
+    *v = ((int64_t)z * ny + y) * nx + x;
+    return true;
+}
+
+__device__ inline int load_brick_flags(const uint8_t *labels, int nx, int ny, int nz, const Bricks &k,
+                                       int64_t E, int64_t base, uint8_t fl[kScanItems],
+                                       int64_t vv[kScanItems])
+{
+    int cnt = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t e = base + i;
+        int64_t v = -1;
+        const bool in = e < E && brick_voxel(k, nx, ny, nz, e, &v);
+        vv[i] = in ? v : -1;
+        fl[i] = in && labels[v] == 0;
+        cnt += fl[i];
+    }
+    return cnt;
+}
+
+__device__ inline uint32_t pack_voxel(const Bricks &k, int nx, int ny, int64_t v)
+{
+    const int x = (int)(v % nx);
+    const int64_t t = v / nx;
+    return pack_xyz(k, x, (int)(t % ny), (int)(t / ny));
+}
+
+__global__ void count_brick_kernel(const uint8_t *labels, int nx, int ny, int nz, Bricks k, int64_t E,
+                                   int *blk)
+{
+    __shared__ int sm[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint8_t fl[kScanItems];
+    int64_t vv[kScanItems];
+    const int cnt = load_brick_flags(labels, nx, ny, nz, k, E, base, fl, vv);
+    int total;
+    block_exclusive_scan(cnt, sm, &total);
+    if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+__global__ void scatter_brick_kernel(const uint8_t *labels, const int *lexmap, int nx, int ny, int nz,
+                                     Bricks k, int64_t E, const int *blk, int *imap, uint32_t *ifluid,
+                                     int *lex2int)
+{
+    __shared__ int sm[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint8_t fl[kScanItems];
+    int64_t vv[kScanItems];
+    const int cnt = load_brick_flags(labels, nx, ny, nz, k, E, base, fl, vv);
+    int total;
+    int rank = blk[blockIdx.x] + block_exclusive_scan(cnt, sm, &total);
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t e = base + i;
+        if (e >= E) break;
+        const int64_t v = vv[i];
+        if (fl[i]) {
+            imap[e] = rank;
+            ifluid[rank] = pack_voxel(k, nx, ny, v);
+            lex2int[lexmap[v]] = rank;
+            ++rank;
+        } else {
+            imap[e] = (v >= 0 && labels[v] == 1) ? kElectrode : kInert;
+        }
+    }
+}
+
+__global__ void permute_kernel(const float *src, float *dst, const int *lex2int, int n_f, int P, int d,
+                               int to_lex)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_f * d) return;
+    const int c = (int)(t / n_f), k = (int)(t % n_f);
+    const int n = lex2int[k];
+    if (to_lex)
+        dst[(size_t)c * n_f + k] = src[(size_t)c * P + n];
+    else
+        dst[(size_t)c * P + n] = src[(size_t)c * n_f + k];
+}
+
 template <class T>
 __global__ void fill_kernel(T *p, T v, int64_t n)
 {
@@ -216,6 +305,33 @@ hipError_t launch_compact(const uint8_t *labels, int64_t nvox, int *map, int *fl
     count_kernel<<<(unsigned)nblk, kScanThreads, 0, s>>>(labels, nvox, blk);
     scan_blocks_kernel<<<1, kScanThreads, 0, s>>>(blk, nblk, nfluid);
     scatter_kernel<<<(unsigned)nblk, kScanThreads, 0, s>>>(labels, nvox, blk, map, fluid);
+    return hipGetLastError();
+}
+
+int64_t brick_enum_size(const Bricks &bk)
+{
+    return ((int64_t)bk.nbx * bk.nby * bk.nbz) << (bk.bsx + bk.bsy + bk.bsz);
+}
+
+hipError_t launch_compact_bricks(const uint8_t *labels, const int *lexmap, int nx, int ny, int nz,
+                                 const Bricks &bk, int *imap, uint32_t *ifluid, int *lex2int, int *blk,
+                                 int64_t *nfluid, hipStream_t s)
+{
+    const int64_t E = brick_enum_size(bk);
+    const int64_t nblk = compact_blocks(E);
+    count_brick_kernel<<<(unsigned)nblk, kScanThreads, 0, s>>>(labels, nx, ny, nz, bk, E, blk);
+    scan_blocks_kernel<<<1, kScanThreads, 0, s>>>(blk, nblk, nfluid);
+    scatter_brick_kernel<<<(unsigned)nblk, kScanThreads, 0, s>>>(labels, lexmap, nx, ny, nz, bk, E, blk,
+                                                                 imap, ifluid, lex2int);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute(const float *src, float *dst, const int *lex2int, int n_f, int P, int d,
+                          int to_lex, hipStream_t s)
+{
+    const int64_t n = (int64_t)n_f * d;
+    if (n <= 0) return hipSuccess;
+    permute_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, lex2int, n_f, P, d, to_lex);
     return hipGetLastError();
 }
 

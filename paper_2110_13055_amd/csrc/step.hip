@@ -103,19 +103,18 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
     double res[2] = {0, 0};
 
     if (active) {
-        const int v = g.fluid[n];
-        const int x = v % g.nx;
-        const int t = v / g.nx;
-        const int y = t % g.ny;
-        const int z = t / g.ny;
+        int x, y, z;
+        unpack_xyz(g, g.fluid[n], x, y, z);
         constexpr bool need_all = LBM && (ODD || FP16);
         const bool edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
+        NbCtx ctx;
+        nb_ctx<L>(g, x, y, z, g.periodic_x, ctx);
         int nb[Q];
         nb[0] = n;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
-            nb[i] = want ? nb_map<L>(g, x, y, z, i, g.periodic_x) : kOutside;
+            nb[i] = want ? nb_get<L>(g, ctx, i) : kOutside;
         }
 
         if (LBM) {
@@ -134,7 +133,7 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
                     int nbb[Q];
                     nbb[0] = bn;
 #pragma unroll
-                    for (int i = 1; i < Q; ++i) nbb[i] = nb_map<L>(g, xb, y, z, i, false);
+                    for (int i = 1; i < Q; ++i) nbb[i] = nb_map<L>(g, xb, y, z, i, false);  // rare path
                     float fb[Q];
                     nee_populations<L>(p, inl, f, fb);
                     lbm_node<L, FP16, ODD, NP>(p, b, P, bn, nbb, fb, res);
