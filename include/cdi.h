@@ -238,6 +238,53 @@ int cdi_get_tuning(const cdi_solver *s, cdi_tuning *t);
 int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *chosen,
                  double *ms_per_step);
 
+/* ------------------------------------------------------------ batches
+ * Many independent electrodes (uneven sizes, own parameters) advanced by one
+ * persistent launch per step. Members must share the device, the stream, the
+ * dimension and the storage precision. Each member's results are bitwise
+ * identical to advancing that member alone with the same sequence of calls
+ * (tile results do not depend on which workgroup computes them). */
+typedef struct cdi_batch cdi_batch;
+
+enum { CDI_MODE_IDLE = 0, CDI_MODE_FLOW = 1, CDI_MODE_IONS = 2, CDI_MODE_FUSED = 3 };
+
+/* Device workspace a batch of these members needs. */
+int cdi_batch_bytes(cdi_solver *const *members, int32_t n, uint64_t *bytes);
+
+/* Group n solvers. ws: device, >= cdi_batch_bytes, 256-byte aligned; it and the
+ * members must outlive the batch. stream: the stream batched work runs on (a
+ * non-default stream enables HIP graph replay); the batch orders itself after
+ * the members' streams on entry and the members' streams after it on exit.
+ * The batch only borrows the members: they stay usable on their own between
+ * batch calls. */
+int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t ws_bytes, void *stream,
+                     cdi_batch **out);
+int cdi_batch_destroy(cdi_batch *b);
+
+/* Advance every member by nsteps in its mode (host array modes[n]):
+ *   FLOW  = cdi_flow_steps, IONS = cdi_np_step(fused 0), FUSED = cdi_np_step(fused 1),
+ *   IDLE  = untouched.
+ * Like cdi_np_step, IONS/FUSED members are checked once for positivity
+ * (UNSTABLE names the first failing member and nothing is stepped). Runs of
+ * identical steps are replayed from a captured HIP graph. FLOW members also get
+ * the residual of their last step (see cdi_batch_residuals) when nsteps >= 2.
+ * Asynchronous except for the positivity check. */
+int cdi_batch_advance(cdi_batch *b, int64_t nsteps, const int32_t *modes);
+
+/* r[k] = |u^t - u^{t-1}| / |u^t| over the last two steps of the last advance
+ * for FLOW members, NaN for the others. Synchronises. */
+int cdi_batch_residuals(cdi_batch *b, double *r);
+
+/* Persistent grid size (0 = 4 workgroups per compute unit) and occupancy cap. */
+int cdi_batch_set_launch(cdi_batch *b, int32_t workgroups, int32_t blocks_per_cu);
+int cdi_batch_get_launch(const cdi_batch *b, int32_t *workgroups, int32_t *blocks_per_cu);
+
+/* Autotuner for the persistent launch: snapshots all members, times candidate
+ * grid sizes over `steps` steps of the given modes, restores every member and
+ * keeps the fastest. Synchronises. */
+int cdi_batch_autotune(cdi_batch *b, int32_t steps, const int32_t *modes, int32_t *workgroups,
+                       double *ms_per_step);
+
 /* Checkpoint: the complete device state (populations, moments, fields,
  * accumulators, counters, AA parity) to and from host memory. */
 int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes);

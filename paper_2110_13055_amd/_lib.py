@@ -18,6 +18,7 @@ INLET_OUTLET, BODY_FORCE = 0, 1
 EQ_QUADRATIC, EQ_LINEAR = 0, 1
 NPX_INLET_OUTLET, NPX_PERIODIC, NPX_CLOSED, NPX_DIRICHLET = 0, 1, 2, 3
 FP32, FP16_DEV = 0, 1
+MODE_IDLE, MODE_FLOW, MODE_IONS, MODE_FUSED = 0, 1, 2, 3
 
 STATUS_NAMES = {
     0: "OK", 1: "STAGNATED", -1: "INVALID", -2: "GEOMETRY", -3: "UNSTABLE", -4: "NOT_CONVERGED",
@@ -93,6 +94,14 @@ SIGNATURES = {
     "cdi_set_tuning": (C.c_int, [P, P]),
     "cdi_get_tuning": (C.c_int, [P, P]),
     "cdi_autotune": (C.c_int, [P, I32, I32, P, P]),
+    "cdi_batch_bytes": (C.c_int, [P, I32, P]),
+    "cdi_batch_create": (C.c_int, [P, I32, P, U64, P, P]),
+    "cdi_batch_destroy": (C.c_int, [P]),
+    "cdi_batch_advance": (C.c_int, [P, I64, P]),
+    "cdi_batch_residuals": (C.c_int, [P, P]),
+    "cdi_batch_set_launch": (C.c_int, [P, I32, I32]),
+    "cdi_batch_get_launch": (C.c_int, [P, P, P]),
+    "cdi_batch_autotune": (C.c_int, [P, I32, P, P, P]),
     "cdi_snapshot_bytes": (C.c_int, [P, P]),
     "cdi_snapshot": (C.c_int, [P, P, U64]),
     "cdi_restore": (C.c_int, [P, P, U64]),

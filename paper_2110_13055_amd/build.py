@@ -22,6 +22,10 @@ HIP_FLAGS = [
     f"--offload-arch={ARCH}",
     # keep packed FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b+c only inside one source expression, so a device function
+    # rounds identically in every kernel it is inlined into (a batched step
+    # must reproduce the single-instance step bit for bit)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -261,7 +261,8 @@ struct SnapHeader {
 };
 constexpr uint64_t kSnapMagic = 0x43444931534e4150ull;
 
-int step_once(cdi_solver *s, int lbm, int np, int flags)
+// Buffers of the next step of s (current double-buffer halves).
+Bufs make_bufs(const cdi_solver *s, int flags)
 {
     Bufs b{};
     b.f = s->node.f;
@@ -277,7 +278,12 @@ int step_once(cdi_solver *s, int lbm, int np, int flags)
     b.resid = s->node.resid;
     b.ubuf = s->node.ubuf;
     b.flags = flags | (s->flow_steps > 0 ? kNee : 0);
-    HIPCHK(launch_step(s->dim, s->fp16, s->parity, lbm, np, s->g, s->p, b, s->stream));
+    return b;
+}
+
+// Host bookkeeping of one completed step (AA parity, buffer halves, counters).
+void advance_state(cdi_solver *s, int lbm, int np)
+{
     if (lbm) {
         s->parity ^= 1;
         if (s->fp16) s->mcur ^= 1;
@@ -285,6 +291,13 @@ int step_once(cdi_solver *s, int lbm, int np, int flags)
         s->flow_steps++;
     }
     if (np) s->ccur ^= 1;
+}
+
+int step_once(cdi_solver *s, int lbm, int np, int flags)
+{
+    const Bufs b = make_bufs(s, flags);
+    HIPCHK(launch_step(s->dim, s->fp16, s->parity, lbm, np, s->g, s->p, b, s->stream));
+    advance_state(s, lbm, np);
     return CDI_OK;
 }
 
@@ -300,6 +313,18 @@ int ensure_j(cdi_solver *s)
     }
     s->jstate = J_VALID;
     return CDI_OK;
+}
+
+int d2h(cdi_solver *s, void *dst, const void *src, uint64_t bytes);
+
+// Positivity bound of the explicit ion update with the current flux field:
+// *worst = max dt * (sum of outflow coefficients). Synchronises.
+int check_stability(cdi_solver *s, double *worst)
+{
+    int rc = ensure_j(s);
+    if (rc) return rc;
+    HIPCHK(launch_stability(s->dim, s->g, s->p, s->node.j[s->jcur], s->node.part, s->node.red, s->stream));
+    return d2h(s, worst, s->node.red, 8);
 }
 
 // Tile schedule for 3D lattices: tiles sorted by (band of kBandRows rows, z,
@@ -692,11 +717,9 @@ int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow)
     if (!s || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
     if (fused_flow && s->params.np_substeps != 1) return fail(CDI_E_INVALID, "fused steps need np_substeps = 1");
     if (nsteps == 0) return CDI_OK;
-    int rc = ensure_j(s);
-    if (rc) return rc;
-    HIPCHK(launch_stability(s->dim, s->g, s->p, s->node.j[s->jcur], s->node.part, s->node.red, s->stream));
     double worst = 0;
-    if ((rc = d2h(s, &worst, s->node.red, 8)) != CDI_OK) return rc;
+    int rc = check_stability(s, &worst);
+    if (rc) return rc;
     if (!(worst <= 1.0))
         return fail(CDI_E_UNSTABLE, "positivity bound violated: dt * sum(outflow coefficients) = %g > 1", worst);
     for (int64_t k = 0; k < nsteps; ++k) {
@@ -902,6 +925,409 @@ int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *c
     if (rc2) return rc2;
     if (rc3) return rc3;
     if (chosen) *chosen = best;
+    if (ms_per_step) *ms_per_step = best_ms / steps;
+    return CDI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+namespace {
+
+// Descriptor slots per batch: 0 first step, 1 odd leftover, 2-3 the two
+// residual steps, 4-5 the step pair replayed from the captured graph. A call
+// synchronises before rewriting any slot, so no slot is rewritten while a
+// kernel of an earlier call may still read it.
+constexpr int kSlots = 6;
+
+}  // namespace
+
+struct cdi_batch {
+    std::vector<cdi_solver *> m;
+    std::vector<int> tile_begin;
+    int n = 0, dim = 0, fp16 = 0, total_tiles = 0, cus = 0;
+    int workgroups_req = 0, blocks_per_cu = 0, lds_pad = 0;
+    hipStream_t stream = nullptr;
+    BatchInst *dinst = nullptr;  // device, kSlots * n
+    int *tile_inst = nullptr;    // device
+    double *dred = nullptr;      // device, 2 per member
+    BatchInst *hstage = nullptr; // pinned host, kSlots * n
+    std::vector<int> resid_valid;
+    hipGraphExec_t exec = nullptr;
+    int exec_wg = -1;
+    hipEvent_t done = nullptr;
+};
+
+namespace {
+
+uint64_t batch_layout(int n, int total_tiles, BatchInst **dinst, int **tile_inst, double **dred, void *ws)
+{
+    Carver c(ws);
+    BatchInst *a = c.take<BatchInst>(sizeof(BatchInst) * (uint64_t)kSlots * n);
+    int *b = c.take<int>(4ull * (uint64_t)total_tiles);
+    double *d = c.take<double>(16ull * n);
+    if (dinst) *dinst = a;
+    if (tile_inst) *tile_inst = b;
+    if (dred) *dred = d;
+    return c.off;
+}
+
+int batch_workgroups(const cdi_batch *b)
+{
+    int wg = b->workgroups_req > 0 ? b->workgroups_req : 4 * b->cus;
+    if (wg > b->total_tiles) wg = b->total_tiles;
+    return wg < 1 ? 1 : wg;
+}
+
+// Flags of member k's step number `idx` of an advance of `nsteps` steps.
+int batch_flags(const cdi_solver *s, int mode, int64_t idx, int64_t nsteps, bool want_resid)
+{
+    int flags = 0;
+    if (mode == kModeFlow && want_resid) {
+        if (idx == nsteps - 2 && !s->fp16) flags |= kStoreU;
+        if (idx == nsteps - 1) flags |= kResid;
+    }
+    if (mode == kModeFused && s->fp16 && idx > 0) flags |= kJFromM;
+    return flags;
+}
+
+void fill_slot(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64_t nsteps, bool want_resid)
+{
+    BatchInst *h = bt->hstage + (size_t)slot * bt->n;
+    for (int k = 0; k < bt->n; ++k) {
+        const cdi_solver *s = bt->m[k];
+        BatchInst &I = h[k];
+        I.g = s->g;
+        I.p = s->p;
+        I.mode = modes[k];
+        I.b = make_bufs(s, batch_flags(s, modes[k], idx, nsteps, want_resid));
+        I.odd = s->parity;
+        I.tile_begin = bt->tile_begin[k];
+        I.ntiles = s->ntiles;
+    }
+}
+
+void advance_members(cdi_batch *bt, const int32_t *modes)
+{
+    for (int k = 0; k < bt->n; ++k) {
+        cdi_solver *s = bt->m[k];
+        switch (modes[k]) {
+        case kModeFlow: advance_state(s, 1, 0); break;
+        case kModeIons: advance_state(s, 0, 1); s->np_steps++; break;
+        case kModeFused: advance_state(s, 1, 1); s->np_steps++; break;
+        default: break;
+        }
+    }
+}
+
+int upload_slot(cdi_batch *bt, int slot)
+{
+    const size_t bytes = sizeof(BatchInst) * (size_t)bt->n;
+    HIPCHK(hipMemcpyAsync(bt->dinst + (size_t)slot * bt->n, bt->hstage + (size_t)slot * bt->n, bytes,
+                          hipMemcpyHostToDevice, bt->stream));
+    return CDI_OK;
+}
+
+int launch_slot(cdi_batch *bt, int slot)
+{
+    HIPCHK(launch_batch(bt->dim, bt->fp16, bt->dinst + (size_t)slot * bt->n, bt->tile_inst, bt->total_tiles,
+                        batch_workgroups(bt), bt->lds_pad, bt->stream));
+    return CDI_OK;
+}
+
+int eager_step(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64_t nsteps, bool want_resid)
+{
+    fill_slot(bt, slot, modes, idx, nsteps, want_resid);
+    int rc = upload_slot(bt, slot);
+    if (rc) return rc;
+    if ((rc = launch_slot(bt, slot)) != CDI_OK) return rc;
+    advance_members(bt, modes);
+    return CDI_OK;
+}
+
+// Graph of one step pair (slots 4 and 5); rebuilt when the launch shape changes.
+int ensure_graph(cdi_batch *bt)
+{
+    const int wg = batch_workgroups(bt);
+    if (bt->exec && bt->exec_wg == wg) return CDI_OK;
+    if (bt->exec) {
+        (void)hipGraphExecDestroy(bt->exec);
+        bt->exec = nullptr;
+    }
+    if (!bt->stream) return CDI_E_INVALID;  // the default stream cannot be captured
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_slot(bt, 4);
+    if (rc == CDI_OK) rc = launch_slot(bt, 5);
+    const hipError_t e = hipStreamEndCapture(bt->stream, &graph);
+    if (rc != CDI_OK) return rc;
+    if (e != hipSuccess) return fail(CDI_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+        bt->exec = nullptr;
+        return fail(CDI_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e2));
+    }
+    bt->exec_wg = wg;
+    return CDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdi_batch_bytes(cdi_solver *const *members, int32_t n, uint64_t *bytes)
+{
+    if (!members || n <= 0 || !bytes) return fail(CDI_E_INVALID, "bad batch arguments");
+    int total = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!members[k]) return fail(CDI_E_INVALID, "member %d is NULL", k);
+        total += members[k]->ntiles;
+    }
+    *bytes = batch_layout(n, total, nullptr, nullptr, nullptr, nullptr);
+    return CDI_OK;
+}
+
+int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t ws_bytes, void *stream,
+                     cdi_batch **out)
+{
+    uint64_t need = 0;
+    int rc = cdi_batch_bytes(members, n, &need);
+    if (rc) return rc;
+    if (!out || !ws || ((uintptr_t)ws % kAlign)) return fail(CDI_E_BUFFER, "batch workspace NULL or misaligned");
+    if (ws_bytes < need) return fail(CDI_E_BUFFER, "batch workspace too small: %llu < %llu",
+                                     (unsigned long long)ws_bytes, (unsigned long long)need);
+    for (int k = 1; k < n; ++k)
+        if (members[k]->dim != members[0]->dim || members[k]->fp16 != members[0]->fp16)
+            return fail(CDI_E_INVALID, "batch members must share dimension and precision");
+    cdi_batch *bt = new (std::nothrow) cdi_batch();
+    if (!bt) return fail(CDI_E_INVALID, "out of host memory");
+    bt->m.assign(members, members + n);
+    bt->n = n;
+    bt->dim = members[0]->dim;
+    bt->fp16 = members[0]->fp16;
+    bt->stream = (hipStream_t)stream;
+    std::vector<int> tiles;
+    for (int k = 0; k < n; ++k) {
+        bt->tile_begin.push_back((int)tiles.size());
+        tiles.insert(tiles.end(), (size_t)members[k]->ntiles, k);
+    }
+    bt->total_tiles = (int)tiles.size();
+    batch_layout(n, bt->total_tiles, &bt->dinst, &bt->tile_inst, &bt->dred, ws);
+    bt->resid_valid.assign(n, 0);
+    int dev = 0;
+    auto cleanup = [&](int code) {
+        if (bt->hstage) (void)hipHostFree(bt->hstage);
+        if (bt->done) (void)hipEventDestroy(bt->done);
+        delete bt;
+        return code;
+    };
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&bt->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return cleanup(fail(CDI_E_DEVICE, "device query failed"));
+    if (hipHostMalloc((void **)&bt->hstage, sizeof(BatchInst) * (size_t)kSlots * n, hipHostMallocDefault) !=
+        hipSuccess)
+        return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
+    if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(CDI_E_DEVICE, "event creation failed"));
+    if (hipMemcpyAsync(bt->tile_inst, tiles.data(), 4ull * tiles.size(), hipMemcpyHostToDevice, bt->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(bt->stream) != hipSuccess)
+        return cleanup(fail(CDI_E_DEVICE, "tile list upload failed"));
+    *out = bt;
+    return CDI_OK;
+}
+
+int cdi_batch_destroy(cdi_batch *bt)
+{
+    if (!bt) return CDI_OK;
+    if (bt->stream) (void)hipStreamSynchronize(bt->stream);
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->hstage) (void)hipHostFree(bt->hstage);
+    if (bt->done) (void)hipEventDestroy(bt->done);
+    delete bt;
+    return CDI_OK;
+}
+
+int cdi_batch_set_launch(cdi_batch *bt, int32_t workgroups, int32_t blocks_per_cu)
+{
+    if (!bt || workgroups < 0 || blocks_per_cu < 0) return fail(CDI_E_INVALID, "bad launch shape");
+    int pad = 0;
+    int rc = occupancy_pad(blocks_per_cu, &pad);
+    if (rc) return rc;
+    bt->workgroups_req = workgroups;
+    bt->blocks_per_cu = blocks_per_cu;
+    bt->lds_pad = pad;
+    if (bt->exec) {
+        (void)hipStreamSynchronize(bt->stream);
+        (void)hipGraphExecDestroy(bt->exec);
+        bt->exec = nullptr;
+        bt->exec_wg = -1;
+    }
+    return CDI_OK;
+}
+
+int cdi_batch_get_launch(const cdi_batch *bt, int32_t *workgroups, int32_t *blocks_per_cu)
+{
+    if (!bt) return fail(CDI_E_INVALID, "NULL batch");
+    if (workgroups) *workgroups = batch_workgroups(bt);
+    if (blocks_per_cu) *blocks_per_cu = bt->blocks_per_cu;
+    return CDI_OK;
+}
+
+int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
+{
+    if (!bt || !modes || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
+    if (nsteps == 0) return CDI_OK;
+    bool any_flow = false, need_first = false;
+    for (int k = 0; k < bt->n; ++k) {
+        const int md = modes[k];
+        cdi_solver *s = bt->m[k];
+        if (md < kModeIdle || md > kModeFused) return fail(CDI_E_INVALID, "bad mode for member %d", k);
+        if ((md == kModeIons || md == kModeFused) && s->params.np_substeps != 1)
+            return fail(CDI_E_INVALID, "member %d: batched ion steps need np_substeps = 1", k);
+        if (md == kModeFlow) any_flow = true;
+        if ((md == kModeFlow || md == kModeFused) && s->flow_steps == 0) need_first = true;
+        if (md == kModeFused && s->fp16) need_first = true;
+    }
+    // order after the members' own streams
+    for (int k = 0; k < bt->n; ++k) HIPCHK(hipStreamSynchronize(bt->m[k]->stream));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    // positivity of the ion updates, as cdi_np_step (the flux field is made valid on the member's stream)
+    for (int k = 0; k < bt->n; ++k) {
+        if (modes[k] != kModeIons && modes[k] != kModeFused) continue;
+        double worst = 0;
+        int rc = check_stability(bt->m[k], &worst);
+        if (rc) return rc;
+        if (!(worst <= 1.0))
+            return fail(CDI_E_UNSTABLE, "member %d: positivity bound violated (%g > 1)", k, worst);
+    }
+    const bool want_resid = any_flow && nsteps >= 2;
+    const int64_t suffix = want_resid ? 2 : 0;
+    int64_t idx = 0;
+    int rc = CDI_OK;
+    if (need_first && nsteps - suffix >= 1) {
+        if ((rc = eager_step(bt, 0, modes, idx, nsteps, want_resid)) != CDI_OK) return rc;
+        ++idx;
+    }
+    const int64_t mid = nsteps - suffix - idx;
+    const int64_t pairs = mid / 2;
+    if (pairs > 0) {
+        // descriptors of the two steps of a pair: the state now and one step on
+        fill_slot(bt, 4, modes, idx, nsteps, want_resid);
+        std::vector<cdi_solver> saved;
+        saved.reserve(bt->n);
+        for (int k = 0; k < bt->n; ++k) saved.push_back(*bt->m[k]);
+        advance_members(bt, modes);
+        fill_slot(bt, 5, modes, idx + 1, nsteps, want_resid);
+        for (int k = 0; k < bt->n; ++k) *bt->m[k] = saved[k];
+        if ((rc = upload_slot(bt, 4)) != CDI_OK) return rc;
+        if ((rc = upload_slot(bt, 5)) != CDI_OK) return rc;
+        if (bt->stream && ensure_graph(bt) == CDI_OK) {
+            for (int64_t q = 0; q < pairs; ++q) HIPCHK(hipGraphLaunch(bt->exec, bt->stream));
+        } else {  // default stream (not capturable): the same pair, launched directly
+            for (int64_t q = 0; q < pairs; ++q) {
+                if ((rc = launch_slot(bt, 4)) != CDI_OK) return rc;
+                if ((rc = launch_slot(bt, 5)) != CDI_OK) return rc;
+            }
+        }
+        for (int64_t q = 0; q < 2 * pairs; ++q) advance_members(bt, modes);
+        idx += 2 * pairs;
+    }
+    // an odd leftover, then the residual steps
+    while (idx < nsteps) {
+        const int slot = (idx == nsteps - 2 && suffix) ? 2 : (idx == nsteps - 1 && suffix) ? 3 : 1;
+        if (slot == 1 && idx != nsteps - suffix - 1) return fail(CDI_E_INVALID, "internal step accounting");
+        if ((rc = eager_step(bt, slot, modes, idx, nsteps, want_resid)) != CDI_OK) return rc;
+        ++idx;
+    }
+    for (int k = 0; k < bt->n; ++k) {
+        cdi_solver *s = bt->m[k];
+        bt->resid_valid[k] = 0;
+        if (modes[k] == kModeFlow) {
+            s->jstate = J_INVALID;
+            if (want_resid) {
+                HIPCHK(launch_reduce_tiles(s->node.resid, s->ntiles, 2, 2, bt->dred + 2 * k, bt->stream));
+                bt->resid_valid[k] = 1;
+            }
+        } else if (modes[k] == kModeFused) {
+            s->jstate = s->fp16 ? J_IN_M : J_VALID;
+        }
+    }
+    // the members' streams wait for the batch
+    HIPCHK(hipEventRecord(bt->done, bt->stream));
+    for (int k = 0; k < bt->n; ++k)
+        if (bt->m[k]->stream != bt->stream) HIPCHK(hipStreamWaitEvent(bt->m[k]->stream, bt->done, 0));
+    return CDI_OK;
+}
+
+int cdi_batch_residuals(cdi_batch *bt, double *r)
+{
+    if (!bt || !r) return fail(CDI_E_INVALID, "NULL argument");
+    std::vector<double> h(2 * (size_t)bt->n);
+    HIPCHK(hipMemcpyAsync(h.data(), bt->dred, 16ull * bt->n, hipMemcpyDeviceToHost, bt->stream));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    for (int k = 0; k < bt->n; ++k)
+        r[k] = bt->resid_valid[k] ? std::sqrt(h[2 * k]) / std::sqrt(h[2 * k + 1]) : NAN;
+    return CDI_OK;
+}
+
+int cdi_batch_autotune(cdi_batch *bt, int32_t steps, const int32_t *modes, int32_t *workgroups,
+                       double *ms_per_step)
+{
+    if (!bt || !modes || steps < 2) return fail(CDI_E_INVALID, "bad arguments");
+    std::vector<std::vector<uint8_t>> snaps(bt->n);
+    int rc = CDI_OK;
+    for (int k = 0; k < bt->n; ++k) {
+        uint64_t nb = 0;
+        if ((rc = cdi_snapshot_bytes(bt->m[k], &nb)) != CDI_OK) return rc;
+        snaps[k].resize(nb);
+        if ((rc = cdi_snapshot(bt->m[k], snaps[k].data(), nb)) != CDI_OK) return rc;
+    }
+    auto restore_all = [&]() {
+        for (int k = 0; k < bt->n; ++k) {
+            int r2 = cdi_restore(bt->m[k], snaps[k].data(), snaps[k].size());
+            if (r2) return r2;
+        }
+        return (int)CDI_OK;
+    };
+    const int start_wg = bt->workgroups_req, start_occ = bt->blocks_per_cu;
+    std::vector<int> cands;
+    for (int mult : {1, 2, 4, 8, 16}) cands.push_back(mult * bt->cus);
+    cands.push_back(bt->total_tiles);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = start_wg;
+    float best_ms = INFINITY;
+    for (int wg : cands) {
+        if (wg > bt->total_tiles) continue;
+        if ((rc = cdi_batch_set_launch(bt, wg, start_occ)) != CDI_OK) break;
+        if ((rc = restore_all()) != CDI_OK) break;
+        if ((rc = cdi_batch_advance(bt, 2, modes)) != CDI_OK) break;  // builds the graph
+        if ((rc = cdi_batch_advance(bt, 2, modes)) != CDI_OK) break;
+        HIPCHK(hipStreamSynchronize(bt->stream));
+        HIPCHK(hipEventRecord(e0, bt->stream));
+        if ((rc = cdi_batch_advance(bt, steps, modes)) != CDI_OK) break;
+        HIPCHK(hipEventRecord(e1, bt->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = wg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int rc2 = cdi_batch_set_launch(bt, best, start_occ);
+    const int rc3 = restore_all();
+    for (int k = 0; k < bt->n; ++k) bt->resid_valid[k] = 0;
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (rc3) return rc3;
+    if (workgroups) *workgroups = best;
     if (ms_per_step) *ms_per_step = best_ms / steps;
     return CDI_OK;
 }

@@ -136,6 +136,18 @@ struct Bufs {
     int flags;
 };
 
+// One instance of a batched launch.
+constexpr int kModeIdle = 0, kModeFlow = 1, kModeIons = 2, kModeFused = 3;
+struct BatchInst {
+    Grid g;
+    Phys p;
+    Bufs b;
+    int mode;        // kMode*
+    int odd;         // AA parity of the instance's stored state
+    int tile_begin;  // first entry of this instance in the concatenated tile list
+    int ntiles;
+};
+
 // ------------------------------------------------------------ launchers
 // Every launcher enqueues on `stream` and returns hipGetLastError().
 hipError_t launch_init_labels(uint8_t *labels, int nx, int ny, int nz, int walls2d, hipStream_t s);
@@ -165,6 +177,10 @@ hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 //   dim 2/3, fp16 0/1, odd = AA parity of the stored state, lbm/np switches.
 hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p,
                        const Bufs &b, hipStream_t s);
+// One step of every instance of a batch in one persistent launch of
+// `workgroups` workgroups (inst and tile_inst in device memory).
+hipError_t launch_batch(int dim, int fp16, const BatchInst *inst, const int *tile_inst, int total_tiles,
+                        int workgroups, int lds_pad, hipStream_t s);
 // Moments of the stored state: rho (nullable), u (nullable, d planes),
 // j (nullable, d planes).
 hipError_t launch_moments(int dim, int fp16, int odd, int nee, const Grid &g, const Phys &p,

@@ -91,11 +91,12 @@ __device__ inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, cons
     }
 }
 
+// One 256-node tile of one instance (all threads of the workgroup call it;
+// sm: (kTile/64)*6 doubles of LDS).
 template <class L, int FP16, int ODD, int LBM, int NP>
-__global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
+__device__ inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, int tile, double *sm)
 {
     constexpr int Q = L::Q, D = L::D;
-    const int tile = block_tile(g);
     const int n = tile * kTile + threadIdx.x;
     const bool active = n < g.n_f;
     const int P = g.P;
@@ -229,9 +230,6 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
         }
     }
 
-    __shared__ double sm[(kTile / 64) * 6];
-    extern __shared__ double lds_pad[];  // sized at launch: occupancy cap only
-    (void)lds_pad;
     if (NP) {
         double s[6];
         block_sum<6>(acc, sm, s);
@@ -248,6 +246,49 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
         if (threadIdx.x == 0) {
             b.resid[2 * (size_t)tile] = s[0];
             b.resid[2 * (size_t)tile + 1] = s[1];
+        }
+        __syncthreads();
+    }
+}
+
+template <class L, int FP16, int ODD, int LBM, int NP>
+__global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
+{
+    __shared__ double sm[(kTile / 64) * 6];
+    extern __shared__ double lds_pad[];  // sized at launch: occupancy cap only
+    (void)lds_pad;
+    step_tile<L, FP16, ODD, LBM, NP>(g, p, b, block_tile(g), sm);
+}
+
+// Many instances in one persistent launch: workgroup w takes tiles w, w + G,
+// w + 2G, ... of the concatenated tile list. Each instance carries its own
+// lattice, parameters, buffers, AA parity and mode, so uneven sizes and
+// different phases (flow, ions, fused) share the launch. Tile results do not
+// depend on which workgroup computes them.
+template <class L, int FP16>
+__global__ __launch_bounds__(kTile) void batch_kernel(const BatchInst *inst, const int *tile_inst,
+                                                      int total_tiles)
+{
+    __shared__ double sm[(kTile / 64) * 6];
+    extern __shared__ double lds_pad[];
+    (void)lds_pad;
+    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        const int k = tile_inst[t];
+        const BatchInst &I = inst[k];
+        const int tile = t - I.tile_begin;
+        const int mode = I.mode, odd = I.odd;
+        if (mode == kModeFlow) {
+            if (odd)
+                step_tile<L, FP16, 1, 1, 0>(I.g, I.p, I.b, tile, sm);
+            else
+                step_tile<L, FP16, 0, 1, 0>(I.g, I.p, I.b, tile, sm);
+        } else if (mode == kModeFused) {
+            if (odd)
+                step_tile<L, FP16, 1, 1, 1>(I.g, I.p, I.b, tile, sm);
+            else
+                step_tile<L, FP16, 0, 1, 1>(I.g, I.p, I.b, tile, sm);
+        } else if (mode == kModeIons) {
+            step_tile<L, 0, 0, 0, 1>(I.g, I.p, I.b, tile, sm);
         }
     }
 }
@@ -288,6 +329,24 @@ void launch_prec(int fp16, int odd, int lbm, int np, const Grid &g, const Phys &
 }
 
 }  // namespace
+
+hipError_t launch_batch(int dim, int fp16, const BatchInst *inst, const int *tile_inst, int total_tiles,
+                        int workgroups, int lds_pad, hipStream_t s)
+{
+    if (total_tiles <= 0 || workgroups <= 0) return hipSuccess;
+    if (dim == 2) {
+        if (fp16)
+            batch_kernel<D2Q9, 1><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+        else
+            batch_kernel<D2Q9, 0><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+    } else {
+        if (fp16)
+            batch_kernel<D3Q19, 1><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+        else
+            batch_kernel<D3Q19, 0><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p,
                        const Bufs &b, hipStream_t s)

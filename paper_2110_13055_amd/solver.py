@@ -248,3 +248,71 @@ class Solver:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+class Batch:
+    """Independent solvers advanced together: one persistent launch per step
+    for all members, step pairs replayed from a captured HIP graph. Each
+    member's results equal those of advancing it alone."""
+
+    def __init__(self, members, stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        self.members = list(members)
+        n = len(self.members)
+        if n == 0:
+            raise ValueError("empty batch")
+        dev = self.members[0].device
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self._arr = (C.c_void_p * n)(*[s.h.value for s in self.members])
+        nb = C.c_uint64()
+        L.check(self.lib.cdi_batch_bytes(self._arr, n, C.byref(nb)), "cdi_batch_bytes")
+        self.ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        L.check(self.lib.cdi_batch_create(self._arr, n, C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                "cdi_batch_create")
+        self.h = h
+        self.n = n
+
+    def _modes(self, modes):
+        if isinstance(modes, int):
+            modes = [modes] * self.n
+        a = (C.c_int32 * self.n)(*[int(m) for m in modes])
+        return a
+
+    def advance(self, nsteps: int, modes):
+        L.check(self.lib.cdi_batch_advance(self.h, nsteps, self._modes(modes)), "cdi_batch_advance")
+
+    def residuals(self) -> np.ndarray:
+        r = np.empty(self.n)
+        L.check(self.lib.cdi_batch_residuals(self.h, C.c_void_p(r.ctypes.data)), "cdi_batch_residuals")
+        return r
+
+    def set_launch(self, workgroups: int = 0, blocks_per_cu: int = 0):
+        L.check(self.lib.cdi_batch_set_launch(self.h, workgroups, blocks_per_cu), "cdi_batch_set_launch")
+
+    def launch(self):
+        wg, occ = C.c_int32(), C.c_int32()
+        L.check(self.lib.cdi_batch_get_launch(self.h, C.byref(wg), C.byref(occ)), "cdi_batch_get_launch")
+        return wg.value, occ.value
+
+    def autotune(self, steps: int, modes):
+        wg, ms = C.c_int32(), C.c_double()
+        L.check(self.lib.cdi_batch_autotune(self.h, steps, self._modes(modes), C.byref(wg), C.byref(ms)),
+                "cdi_batch_autotune")
+        return wg.value, ms.value
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cdi_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

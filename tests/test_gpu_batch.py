@@ -1,0 +1,152 @@
+"""Batched stepping: uneven instances in one persistent launch (graph-replayed
+step pairs) give, member by member, exactly the results of stepping each
+instance alone with the same calls; the batch is also checked against the
+FP64 oracle through one member."""
+import numpy as np
+import pytest
+
+from helpers import oracle_solver, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2110_13055_amd")
+from paper_2110_13055_amd import _lib as L  # noqa: E402
+from paper_2110_13055_amd import Batch, Geometry, Params, Solver  # noqa: E402
+
+FLOW, IONS, FUSED, IDLE = L.MODE_FLOW, L.MODE_IONS, L.MODE_FUSED, L.MODE_IDLE
+
+
+def members(precision=L.FP32, n=5):
+    rng = np.random.default_rng(2110)
+    out = []
+    for k in range(n):
+        edge = int(rng.integers(24, 41))
+        g = Geometry(dim=3, nx=edge, ny=edge, nz=edge, kind=L.SPHERES,
+                     porosity=float(rng.uniform(0.45, 0.75)), r_min=2.0, r_max=4.0, buffer_x=2,
+                     seed=2110 + k)
+        p = Params(u_in=float(rng.uniform(1e-4, 2e-3)), dpsi_vt=float(rng.uniform(4, 40)),
+                   D=(0.05, 0.076), precision=precision)
+        out.append((g, p))
+    return out
+
+
+def state(s):
+    return (s.concentration(), s.velocity(), s.adsorbed_total(), s.mass_balance())
+
+
+def schedule():
+    # (nsteps, modes per member)
+    return [
+        (7, [FLOW, FLOW, FLOW, FLOW, FLOW]),
+        (10, [FLOW, IDLE, FLOW, FLOW, FLOW]),
+        (9, [FUSED, FLOW, IONS, FUSED, IDLE]),
+        (6, [IONS, FUSED, FUSED, IDLE, FLOW]),
+    ]
+
+
+def run_alone(specs):
+    out = []
+    for k, (g, p) in enumerate(specs):
+        s = Solver(g, p)
+        for n, modes in schedule():
+            m = modes[k]
+            if m == FLOW:
+                s.flow_steps(n)
+            elif m == IONS:
+                s.np_step(n, fused=False)
+            elif m == FUSED:
+                s.np_step(n, fused=True)
+        out.append(state(s))
+    return out
+
+
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV])
+def test_batch_equals_members_stepped_alone(precision):
+    specs = members(precision)
+    alone = run_alone(specs)
+    solvers = [Solver(g, p) for g, p in specs]
+    b = Batch(solvers)
+    for n, modes in schedule():
+        b.advance(n, modes)
+    b.synchronize()
+    for k, s in enumerate(solvers):
+        for a, c in zip(alone[k], state(s)):
+            assert np.array_equal(a, c), f"member {k}"
+
+
+def test_batch_on_default_stream_and_launch_shapes_agree():
+    import torch
+    specs = members()
+    ref = None
+    for stream, wg in ((None, 0), (torch.cuda.default_stream(), 0), (None, 7), (None, 100000)):
+        solvers = [Solver(g, p) for g, p in specs]
+        b = Batch(solvers, stream=stream)
+        b.set_launch(wg, 0)
+        for n, modes in schedule():
+            b.advance(n, modes)
+        b.synchronize()
+        got = [state(s) for s in solvers]
+        if ref is None:
+            ref = got
+        else:
+            for r, g in zip(ref, got):
+                for a, c in zip(r, g):
+                    assert np.array_equal(a, c)
+
+
+def test_member_alone_vs_in_the_mix():
+    specs = members()
+    one = Solver(*specs[2])
+    b1 = Batch([one])
+    b1.advance(12, [FLOW])
+    b1.advance(8, [FUSED])
+    solvers = [Solver(g, p) for g, p in specs]
+    bm = Batch(solvers)
+    bm.advance(12, [FLOW] * 5)
+    bm.advance(8, [FUSED, IONS, FUSED, FLOW, FUSED])
+    for a, c in zip(state(one), state(solvers[2])):
+        assert np.array_equal(a, c)
+
+
+def test_batch_residuals_and_oracle_parity():
+    specs = members(n=3)
+    solvers = [Solver(g, p) for g, p in specs]
+    b = Batch(solvers)
+    b.advance(30, [FLOW] * 3)
+    r = b.residuals()
+    assert np.all(np.isfinite(r)) and np.all(r > 0)
+    b.advance(25, [FUSED] * 3)
+    assert np.all(np.isnan(b.residuals()))
+    g, p = specs[1]
+    o = oracle_solver(g, p)
+    o.flow_steps(30)
+    assert o.np_steps(25, fused=True) == 0
+    s = solvers[1]
+    assert rel_l2(s.velocity(), o.velocity()) <= 1e-5
+    assert np.abs(s.concentration() - o.conc()).max() <= 1e-4
+    assert np.all(np.abs(s.adsorbed_total() - o.adsorbed_total()) <= 1e-4 * np.abs(o.adsorbed_total()))
+
+
+def test_batch_autotune_restores_members():
+    specs = members(n=3)
+    solvers = [Solver(g, p) for g, p in specs]
+    b = Batch(solvers)
+    b.advance(4, [FLOW] * 3)
+    before = [state(s) for s in solvers]
+    wg, ms = b.autotune(4, [FUSED] * 3)
+    assert wg > 0 and ms > 0
+    assert b.launch()[0] == wg
+    after = [state(s) for s in solvers]
+    for r, g in zip(before, after):
+        for a, c in zip(r, g):
+            assert np.array_equal(a, c)
+
+
+def test_unstable_member_is_reported():
+    specs = members(n=2)
+    specs[1][1].D = (0.3, 0.3)
+    solvers = [Solver(g, p) for g, p in specs]
+    b = Batch(solvers)
+    with pytest.raises(L.CdiError) as e:
+        b.advance(2, [IONS, IONS])
+    assert e.value.code == L.E_UNSTABLE and "member 1" in str(e.value)
