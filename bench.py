@@ -91,6 +91,63 @@ def gpu_rates(precision: int, steps: int, warmup: int):
     return res
 
 
+def batched_rates(steps: int, n: int = 64):
+    """Batched stepping of n uneven instances (cubes of edge 48-160, own seed,
+    porosity, potential and inlet velocity): the fused step of all instances
+    in one persistent launch per step (graph-replayed, grid size autotuned),
+    against the same steps run instance by instance with the plain solver."""
+    import torch
+    import paper_2110_13055_amd as P
+    out = {"instances": n}
+    for prec, name in ((P.FP32, "fp32"), (P.FP16_DEV, "fp16_dev")):
+        specs = P.batch_instances(n, precision=prec)
+        solvers = [P.Solver(g, p) for g, p in specs]
+        nf = sum(s.n_fluid for s in solvers)
+        out["n_fluid_total"] = nf
+        for s in solvers:
+            s.flow_steps(2)
+        b = P.Batch(solvers)
+        wg, _ = b.autotune(4, [P.MODE_FUSED] * n)
+        b.advance(2, [P.MODE_FUSED] * n)
+        t = time_region(lambda: b.advance(steps, [P.MODE_FUSED] * n), b.stream)
+        out[f"{name}_batched_mlups"] = round(nf * steps / t / 1e6, 1)
+        out[f"{name}_workgroups"] = wg
+        if prec == P.FP32:
+            def seq():
+                for s in solvers:
+                    s.np_step(steps, fused=True)
+            t = time_region(seq, solvers[0].stream)
+            out["fp32_sequential_mlups"] = round(nf * steps / t / 1e6, 1)
+        b.close()
+        del b, solvers
+        torch.cuda.empty_cache()
+    out["speedup_fp32"] = round(out["fp32_batched_mlups"] / out["fp32_sequential_mlups"], 3)
+    return out
+
+
+def serving_run(n_requests: int, precision: int, slots: int):
+    """Serve a fixed Poisson trace (2 requests/s, half 2D 256^2, half 3D
+    64^3-192^3) with a 200 GB admission budget and the given slot count."""
+    import torch
+    import paper_2110_13055_amd as P
+    from paper_2110_13055_amd.serving import GpuExecutor, Server, latency_stats
+    reqs = P.serving_requests(n_requests, precision=precision)
+    ex = GpuExecutor()
+    srv = Server(ex, budget_bytes=200e9, max_slots=slots, round_steps=500)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    ex.close()
+    torch.cuda.empty_cache()
+    st = latency_stats(res, wall)
+    st = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    st.update(failures=[f"{r.rid}: {r.status}" for r in res if r.status != "ok"])
+    st.update(wall_s=round(wall, 2), backlog=srv.backlog, peak_slots=srv.peak_slots,
+              peak_gb=round(srv.peak_bytes / 1e9, 2), rounds=srv.rounds,
+              flow_steps=sum(r.flow_steps for r in res), np_steps=sum(r.np_steps for r in res))
+    return st
+
+
 def cpu_baseline(budget_s: float = 12.0):
     """FP64 reference on the host: fused steps of the seeded 64^3 sub-case."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -118,6 +175,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests in the serving trace (0 skips the serving leg)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this size (a kernel of known "
+                         "traffic, to calibrate HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -129,6 +192,12 @@ def main():
     import torch
     import paper_2110_13055_amd as P
 
+    if args.copy_probe_mib > 0:
+        a = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     r32 = gpu_rates(P.FP32, args.steps, args.warmup)
     r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup)
     nf = r32["n_fluid"]
@@ -170,6 +239,13 @@ def main():
                  "np_gbs": round(BYTES_NP * nf / (r32["np_s"] / K) / 1e9, 1)},
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_batch:
+        out["batched"] = batched_rates(K)
+    if args.serve_requests > 0:
+        sv = {"requests": args.serve_requests, "rate_hz": 2.0, "budget_gb": 200}
+        sv["continuous_batching_fp32"] = serving_run(args.serve_requests, P.FP32, 64)
+        sv["plain_fp32_one_at_a_time"] = serving_run(args.serve_requests, P.FP32, 1)
+        out["serving"] = sv
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

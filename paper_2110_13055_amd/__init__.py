@@ -13,4 +13,4 @@ from ._lib import (  # noqa: F401
     MODE_FLOW, MODE_FUSED, MODE_IDLE, MODE_IONS,
 )
 from .solver import Batch, Geometry, Params, Solver, plan  # noqa: F401
-from .presets import PRESETS, preset  # noqa: F401
+from .presets import PRESETS, batch_instances, preset, serving_requests  # noqa: F401

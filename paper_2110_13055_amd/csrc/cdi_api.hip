@@ -950,34 +950,47 @@ struct cdi_batch {
     int workgroups_req = 0, blocks_per_cu = 0, lds_pad = 0;
     hipStream_t stream = nullptr;
     BatchInst *dinst = nullptr;  // device, kSlots * n
-    int *tile_inst = nullptr;    // device
+    int2 *dtiles = nullptr;      // device, kSlots * total_tiles (instance, tile), grouped by step class
     double *dred = nullptr;      // device, 2 per member
     BatchInst *hstage = nullptr; // pinned host, kSlots * n
+    int2 *htiles = nullptr;      // pinned host, kSlots * total_tiles
+    int cls_begin[kSlots][kClasses + 1] = {};
     std::vector<int> resid_valid;
     hipGraphExec_t exec = nullptr;
-    int exec_wg = -1;
+    std::vector<int> exec_sig;   // launch shape the graph was captured with
     hipEvent_t done = nullptr;
 };
 
 namespace {
 
-uint64_t batch_layout(int n, int total_tiles, BatchInst **dinst, int **tile_inst, double **dred, void *ws)
+uint64_t batch_layout(int n, int total_tiles, BatchInst **dinst, int2 **dtiles, double **dred, void *ws)
 {
     Carver c(ws);
     BatchInst *a = c.take<BatchInst>(sizeof(BatchInst) * (uint64_t)kSlots * n);
-    int *b = c.take<int>(4ull * (uint64_t)total_tiles);
+    int2 *b = c.take<int2>(8ull * (uint64_t)kSlots * total_tiles);
     double *d = c.take<double>(16ull * n);
     if (dinst) *dinst = a;
-    if (tile_inst) *tile_inst = b;
+    if (dtiles) *dtiles = b;
     if (dred) *dred = d;
     return c.off;
 }
 
-int batch_workgroups(const cdi_batch *b)
+// Persistent grid size of a class launch over `count` tiles.
+int batch_workgroups(const cdi_batch *b, int count)
 {
-    int wg = b->workgroups_req > 0 ? b->workgroups_req : 4 * b->cus;
-    if (wg > b->total_tiles) wg = b->total_tiles;
+    int wg = b->workgroups_req > 0 ? b->workgroups_req : 8 * b->cus;
+    if (wg > count) wg = count;
     return wg < 1 ? 1 : wg;
+}
+
+int step_class(int mode, int odd)
+{
+    switch (mode) {
+    case kModeFlow: return odd ? kClassFlowOdd : kClassFlowEven;
+    case kModeFused: return odd ? kClassFusedOdd : kClassFusedEven;
+    case kModeIons: return kClassIons;
+    default: return -1;
+    }
 }
 
 // Flags of member k's step number `idx` of an advance of `nsteps` steps.
@@ -992,19 +1005,30 @@ int batch_flags(const cdi_solver *s, int mode, int64_t idx, int64_t nsteps, bool
     return flags;
 }
 
+// Descriptors of one step and its (instance, tile) list grouped by step class.
 void fill_slot(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64_t nsteps, bool want_resid)
 {
     BatchInst *h = bt->hstage + (size_t)slot * bt->n;
+    int count[kClasses] = {};
     for (int k = 0; k < bt->n; ++k) {
         const cdi_solver *s = bt->m[k];
         BatchInst &I = h[k];
         I.g = s->g;
         I.p = s->p;
-        I.mode = modes[k];
         I.b = make_bufs(s, batch_flags(s, modes[k], idx, nsteps, want_resid));
-        I.odd = s->parity;
-        I.tile_begin = bt->tile_begin[k];
-        I.ntiles = s->ntiles;
+        const int c = step_class(modes[k], s->parity);
+        if (c >= 0) count[c] += s->ntiles;
+    }
+    int *beg = bt->cls_begin[slot];
+    beg[0] = 0;
+    for (int c = 0; c < kClasses; ++c) beg[c + 1] = beg[c] + count[c];
+    int pos[kClasses];
+    for (int c = 0; c < kClasses; ++c) pos[c] = beg[c];
+    int2 *t = bt->htiles + (size_t)slot * bt->total_tiles;
+    for (int k = 0; k < bt->n; ++k) {
+        const int c = step_class(modes[k], bt->m[k]->parity);
+        if (c < 0) continue;
+        for (int q = 0; q < bt->m[k]->ntiles; ++q) t[pos[c]++] = make_int2(k, q);
     }
 }
 
@@ -1026,14 +1050,34 @@ int upload_slot(cdi_batch *bt, int slot)
     const size_t bytes = sizeof(BatchInst) * (size_t)bt->n;
     HIPCHK(hipMemcpyAsync(bt->dinst + (size_t)slot * bt->n, bt->hstage + (size_t)slot * bt->n, bytes,
                           hipMemcpyHostToDevice, bt->stream));
+    const size_t nt = (size_t)bt->cls_begin[slot][kClasses];
+    if (nt)
+        HIPCHK(hipMemcpyAsync(bt->dtiles + (size_t)slot * bt->total_tiles,
+                              bt->htiles + (size_t)slot * bt->total_tiles, 8 * nt, hipMemcpyHostToDevice,
+                              bt->stream));
     return CDI_OK;
 }
 
 int launch_slot(cdi_batch *bt, int slot)
 {
-    HIPCHK(launch_batch(bt->dim, bt->fp16, bt->dinst + (size_t)slot * bt->n, bt->tile_inst, bt->total_tiles,
-                        batch_workgroups(bt), bt->lds_pad, bt->stream));
+    const int *beg = bt->cls_begin[slot];
+    for (int c = 0; c < kClasses; ++c) {
+        const int count = beg[c + 1] - beg[c];
+        if (count <= 0) continue;
+        HIPCHK(launch_batch(bt->dim, bt->fp16, c, bt->dinst + (size_t)slot * bt->n,
+                            bt->dtiles + (size_t)slot * bt->total_tiles + beg[c], count,
+                            batch_workgroups(bt, count), bt->lds_pad, bt->stream));
+    }
     return CDI_OK;
+}
+
+// Launch shape of the step pair in slots 4 and 5.
+std::vector<int> pair_signature(const cdi_batch *bt)
+{
+    std::vector<int> sig{bt->workgroups_req, bt->lds_pad};
+    for (int slot = 4; slot <= 5; ++slot)
+        for (int c = 0; c <= kClasses; ++c) sig.push_back(bt->cls_begin[slot][c]);
+    return sig;
 }
 
 int eager_step(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64_t nsteps, bool want_resid)
@@ -1049,8 +1093,8 @@ int eager_step(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64
 // Graph of one step pair (slots 4 and 5); rebuilt when the launch shape changes.
 int ensure_graph(cdi_batch *bt)
 {
-    const int wg = batch_workgroups(bt);
-    if (bt->exec && bt->exec_wg == wg) return CDI_OK;
+    const std::vector<int> sig = pair_signature(bt);
+    if (bt->exec && bt->exec_sig == sig) return CDI_OK;
     if (bt->exec) {
         (void)hipGraphExecDestroy(bt->exec);
         bt->exec = nullptr;
@@ -1069,7 +1113,7 @@ int ensure_graph(cdi_batch *bt)
         bt->exec = nullptr;
         return fail(CDI_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e2));
     }
-    bt->exec_wg = wg;
+    bt->exec_sig = sig;
     return CDI_OK;
 }
 
@@ -1108,17 +1152,16 @@ int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t w
     bt->dim = members[0]->dim;
     bt->fp16 = members[0]->fp16;
     bt->stream = (hipStream_t)stream;
-    std::vector<int> tiles;
     for (int k = 0; k < n; ++k) {
-        bt->tile_begin.push_back((int)tiles.size());
-        tiles.insert(tiles.end(), (size_t)members[k]->ntiles, k);
+        bt->tile_begin.push_back(bt->total_tiles);
+        bt->total_tiles += members[k]->ntiles;
     }
-    bt->total_tiles = (int)tiles.size();
-    batch_layout(n, bt->total_tiles, &bt->dinst, &bt->tile_inst, &bt->dred, ws);
+    batch_layout(n, bt->total_tiles, &bt->dinst, &bt->dtiles, &bt->dred, ws);
     bt->resid_valid.assign(n, 0);
     int dev = 0;
     auto cleanup = [&](int code) {
         if (bt->hstage) (void)hipHostFree(bt->hstage);
+        if (bt->htiles) (void)hipHostFree(bt->htiles);
         if (bt->done) (void)hipEventDestroy(bt->done);
         delete bt;
         return code;
@@ -1129,12 +1172,11 @@ int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t w
     if (hipHostMalloc((void **)&bt->hstage, sizeof(BatchInst) * (size_t)kSlots * n, hipHostMallocDefault) !=
         hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
+    if (hipHostMalloc((void **)&bt->htiles, 8ull * kSlots * (size_t)bt->total_tiles, hipHostMallocDefault) !=
+        hipSuccess)
+        return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
     if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "event creation failed"));
-    if (hipMemcpyAsync(bt->tile_inst, tiles.data(), 4ull * tiles.size(), hipMemcpyHostToDevice, bt->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(bt->stream) != hipSuccess)
-        return cleanup(fail(CDI_E_DEVICE, "tile list upload failed"));
     *out = bt;
     return CDI_OK;
 }
@@ -1145,6 +1187,7 @@ int cdi_batch_destroy(cdi_batch *bt)
     if (bt->stream) (void)hipStreamSynchronize(bt->stream);
     if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
     if (bt->hstage) (void)hipHostFree(bt->hstage);
+    if (bt->htiles) (void)hipHostFree(bt->htiles);
     if (bt->done) (void)hipEventDestroy(bt->done);
     delete bt;
     return CDI_OK;
@@ -1163,7 +1206,7 @@ int cdi_batch_set_launch(cdi_batch *bt, int32_t workgroups, int32_t blocks_per_c
         (void)hipStreamSynchronize(bt->stream);
         (void)hipGraphExecDestroy(bt->exec);
         bt->exec = nullptr;
-        bt->exec_wg = -1;
+        bt->exec_sig.clear();
     }
     return CDI_OK;
 }
@@ -1171,7 +1214,7 @@ int cdi_batch_set_launch(cdi_batch *bt, int32_t workgroups, int32_t blocks_per_c
 int cdi_batch_get_launch(const cdi_batch *bt, int32_t *workgroups, int32_t *blocks_per_cu)
 {
     if (!bt) return fail(CDI_E_INVALID, "NULL batch");
-    if (workgroups) *workgroups = batch_workgroups(bt);
+    if (workgroups) *workgroups = batch_workgroups(bt, bt->total_tiles);
     if (blocks_per_cu) *blocks_per_cu = bt->blocks_per_cu;
     return CDI_OK;
 }
@@ -1294,7 +1337,7 @@ int cdi_batch_autotune(cdi_batch *bt, int32_t steps, const int32_t *modes, int32
     };
     const int start_wg = bt->workgroups_req, start_occ = bt->blocks_per_cu;
     std::vector<int> cands;
-    for (int mult : {1, 2, 4, 8, 16}) cands.push_back(mult * bt->cus);
+    for (int mult : {2, 3, 4, 5, 6, 8, 12, 16}) cands.push_back(mult * bt->cus);
     cands.push_back(bt->total_tiles);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));

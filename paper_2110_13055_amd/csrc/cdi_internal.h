@@ -142,11 +142,11 @@ struct BatchInst {
     Grid g;
     Phys p;
     Bufs b;
-    int mode;        // kMode*
-    int odd;         // AA parity of the instance's stored state
-    int tile_begin;  // first entry of this instance in the concatenated tile list
-    int ntiles;
 };
+// Step classes of a batched step (kernel variants): LBM only or fused, by AA
+// parity, and ions only.
+constexpr int kClassFlowEven = 0, kClassFlowOdd = 1, kClassFusedEven = 2, kClassFusedOdd = 3,
+              kClassIons = 4, kClasses = 5;
 
 // ------------------------------------------------------------ launchers
 // Every launcher enqueues on `stream` and returns hipGetLastError().
@@ -177,9 +177,10 @@ hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 //   dim 2/3, fp16 0/1, odd = AA parity of the stored state, lbm/np switches.
 hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p,
                        const Bufs &b, hipStream_t s);
-// One step of every instance of a batch in one persistent launch of
-// `workgroups` workgroups (inst and tile_inst in device memory).
-hipError_t launch_batch(int dim, int fp16, const BatchInst *inst, const int *tile_inst, int total_tiles,
+// One step of the instances of one step class in one persistent launch of
+// `workgroups` workgroups over the class's (instance, tile) list (inst and
+// tiles in device memory).
+hipError_t launch_batch(int dim, int fp16, int cls, const BatchInst *inst, const int2 *tiles, int ntiles,
                         int workgroups, int lds_pad, hipStream_t s);
 // Moments of the stored state: rho (nullable), u (nullable, d planes),
 // j (nullable, d planes).

@@ -119,14 +119,20 @@ __device__ inline int nb_get(const Grid &g, const NbCtx &c, int i)
 
 // BGK equilibrium minus w_i, from rho - 1 and u: quadratic in u, or its
 // linear (Stokes) part.
+// Same, from e_i.u for a direction of weight w (i need not be known at compile time).
+__device__ inline float feq_bar_eu(float w, float drho, float eu, float ux, float uy, float uz, int linear)
+{
+    const float rho = 1.f + drho;
+    if (linear) return w * (drho + 3.f * rho * eu);
+    const float uu = ux * ux + uy * uy + uz * uz;
+    return w * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+}
+
 template <class L>
 __device__ inline float feq_bar(int i, float drho, float ux, float uy, float uz, int linear)
 {
-    const float rho = 1.f + drho;
     const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
-    if (linear) return L::w[i] * (drho + 3.f * rho * eu);
-    const float uu = ux * ux + uy * uy + uz * uz;
-    return L::w[i] * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+    return feq_bar_eu(L::w[i], drho, eu, ux, uy, uz, linear);
 }
 
 template <int FP16>
@@ -161,10 +167,12 @@ __device__ inline float gather(const void *F, int P, const int *nb, int n, int i
     else
         raw = ld<FP16>(F, P, j, nb[j]);
     if (!FP16) return raw;
+    // emitter x - e_i sent it along e_i; a reflected one was sent by x along
+    // e_opp(i) = -e_i, which only flips the sign of e.u (w_opp(i) = w_i)
     const int e = fl ? nb[j] : n;
-    const int dir = fl ? i : j;
     const float4 m = M[e];
-    return feq_bar<L>(dir, m.x, m.y, m.z, m.w, p.linear_eq) + raw * p.hs_inv;
+    const float eu = L::ex[i] * m.y + L::ey[i] * m.z + L::ez[i] * m.w;
+    return feq_bar_eu(L::w[i], m.x, fl ? eu : -eu, m.y, m.z, m.w, p.linear_eq) + raw * p.hs_inv;
 }
 
 // Store the outgoing value of direction i (FP32: f* - w_i; FP16: scaled deviation).
@@ -238,9 +246,12 @@ __device__ inline float sg_flux(float D, float invD, float w, float cp, float cn
 template <int N>
 __device__ inline void block_sum(double (&v)[N], double *sm, double (&out)[N])
 {
+    // a wave whose lanes all hold 0 (most waves, for the inlet/outlet and
+    // adsorption amounts) skips the shuffles: its sum is 0 either way
 #pragma unroll
     for (int k = 0; k < N; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        if (__ballot(v[k] != 0.0))
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0)
 #pragma unroll

@@ -260,36 +260,50 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
     step_tile<L, FP16, ODD, LBM, NP>(g, p, b, block_tile(g), sm);
 }
 
-// Many instances in one persistent launch: workgroup w takes tiles w, w + G,
-// w + 2G, ... of the concatenated tile list. Each instance carries its own
-// lattice, parameters, buffers, AA parity and mode, so uneven sizes and
-// different phases (flow, ions, fused) share the launch. Tile results do not
-// depend on which workgroup computes them.
-template <class L, int FP16>
-__global__ __launch_bounds__(kTile) void batch_kernel(const BatchInst *inst, const int *tile_inst,
-                                                      int total_tiles)
+// Many instances in one persistent launch per step class (LBM parity and
+// mode): workgroup w takes entries w, w + G, w + 2G, ... of the class's list
+// of (instance, tile) pairs. Each instance carries its own lattice,
+// parameters and buffers, so uneven sizes share the launch; the descriptor is
+// copied once per tile into registers. Tile results do not depend on which
+// workgroup computes them.
+template <class L, int FP16, int ODD, int LBM, int NP>
+__global__ __launch_bounds__(kTile) void batch_kernel(const BatchInst *__restrict__ inst,
+                                                      const int2 *__restrict__ tiles, int ntiles)
 {
     __shared__ double sm[(kTile / 64) * 6];
     extern __shared__ double lds_pad[];
     (void)lds_pad;
-    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-        const int k = tile_inst[t];
-        const BatchInst &I = inst[k];
-        const int tile = t - I.tile_begin;
-        const int mode = I.mode, odd = I.odd;
-        if (mode == kModeFlow) {
-            if (odd)
-                step_tile<L, FP16, 1, 1, 0>(I.g, I.p, I.b, tile, sm);
-            else
-                step_tile<L, FP16, 0, 1, 0>(I.g, I.p, I.b, tile, sm);
-        } else if (mode == kModeFused) {
-            if (odd)
-                step_tile<L, FP16, 1, 1, 1>(I.g, I.p, I.b, tile, sm);
-            else
-                step_tile<L, FP16, 0, 1, 1>(I.g, I.p, I.b, tile, sm);
-        } else if (mode == kModeIons) {
-            step_tile<L, 0, 0, 0, 1>(I.g, I.p, I.b, tile, sm);
-        }
+    // workgroups are dealt round-robin over the 8 XCDs: each XCD takes one
+    // contiguous eighth of the list, so neighbouring tiles share its L2
+    const int G = (int)gridDim.x, w = (int)blockIdx.x;
+    int lo = 0, hi = ntiles, first = w, stride = G;
+    if (G >= 8) {
+        const int x = w & 7;
+        lo = (int)((int64_t)ntiles * x / 8);
+        hi = (int)((int64_t)ntiles * (x + 1) / 8);
+        first = lo + (w >> 3);
+        stride = (G - x + 7) >> 3;
+    }
+    for (int q = first; q < hi; q += stride) {
+        const int2 e = tiles[q];
+        const Grid g = inst[e.x].g;
+        const Phys p = inst[e.x].p;
+        const Bufs b = inst[e.x].b;
+        step_tile<L, FP16, ODD, LBM, NP>(g, p, b, e.y, sm);
+    }
+}
+
+template <class L, int FP16>
+void launch_batch_t(int cls, const BatchInst *inst, const int2 *tiles, int ntiles, int wg, int pad,
+                    hipStream_t s)
+{
+    const size_t lds = (size_t)pad;
+    switch (cls) {
+    case kClassFlowEven: batch_kernel<L, FP16, 0, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFlowOdd: batch_kernel<L, FP16, 1, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFusedEven: batch_kernel<L, FP16, 0, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFusedOdd: batch_kernel<L, FP16, 1, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    default: batch_kernel<L, 0, 0, 0, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
     }
 }
 
@@ -330,20 +344,21 @@ void launch_prec(int fp16, int odd, int lbm, int np, const Grid &g, const Phys &
 
 }  // namespace
 
-hipError_t launch_batch(int dim, int fp16, const BatchInst *inst, const int *tile_inst, int total_tiles,
+hipError_t launch_batch(int dim, int fp16, int cls, const BatchInst *inst, const int2 *tiles, int ntiles,
                         int workgroups, int lds_pad, hipStream_t s)
 {
-    if (total_tiles <= 0 || workgroups <= 0) return hipSuccess;
+    if (ntiles <= 0 || workgroups <= 0) return hipSuccess;
+    if (cls < 0 || cls >= kClasses) return hipErrorInvalidValue;
     if (dim == 2) {
         if (fp16)
-            batch_kernel<D2Q9, 1><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+            launch_batch_t<D2Q9, 1>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
         else
-            batch_kernel<D2Q9, 0><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+            launch_batch_t<D2Q9, 0>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
     } else {
         if (fp16)
-            batch_kernel<D3Q19, 1><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+            launch_batch_t<D3Q19, 1>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
         else
-            batch_kernel<D3Q19, 0><<<workgroups, kTile, (size_t)lds_pad, s>>>(inst, tile_inst, total_tiles);
+            launch_batch_t<D3Q19, 0>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
     }
     return hipGetLastError();
 }

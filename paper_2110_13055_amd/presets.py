@@ -9,6 +9,8 @@ Da / Pe ratio at its base case (Sec. 4.1).
 """
 from __future__ import annotations
 
+import numpy as np
+
 from . import _lib as L
 from .solver import Geometry, Params
 
@@ -56,3 +58,57 @@ def preset(name: str, precision: int = L.FP32, **overrides):
             setattr(g, k, v)
     extra = {k: v for k, v in spec.items() if k not in ("geom", "params")}
     return g, p, extra
+
+
+def batch_instances(n: int = 64, base_seed: int = BASE_SEED, precision: int = L.FP32,
+                    edge_range=(48, 160)):
+    """Independent 3D electrodes of uneven size for batched stepping: cubes
+    with integer edge uniform on edge_range, overlapping spheres r in [3, 6],
+    porosity U[0.35, 0.75], applied potential U[4, 40] thermal voltages,
+    inlet velocity U[1e-4, 5e-3]; instance k has geometry seed base_seed + k.
+    -> list of (Geometry, Params)."""
+    rng = np.random.default_rng(base_seed)
+    out = []
+    for k in range(n):
+        edge = int(rng.integers(edge_range[0], edge_range[1] + 1))
+        phi = float(rng.uniform(0.35, 0.75))
+        dpsi = float(rng.uniform(4.0, 40.0))
+        u_in = float(rng.uniform(1e-4, 5e-3))
+        g = Geometry(dim=3, nx=edge, ny=edge, nz=edge, kind=L.SPHERES, porosity=phi, r_min=3.0,
+                     r_max=6.0, buffer_x=2, seed=base_seed + k)
+        out.append((g, Params(u_in=u_in, dpsi_vt=dpsi, D=(D_NA, D_CL), precision=precision)))
+    return out
+
+
+def serving_requests(n: int, rate_hz: float = 2.0, base_seed: int = BASE_SEED,
+                     precision: int = L.FP32, np_steps_2d: int = 5000, np_steps_3d: int = 20000,
+                     flow_tol: float = 1e-8, flow_max_steps: int = 20000):
+    """A fixed trace of mixed solve requests with Poisson arrivals: half are
+    2D 256x256 D2Q9 channels (disks r in [4, 8], walls top/bottom, porosity
+    U[0.55, 0.75], the range random sequential addition reaches), half 3D
+    D3Q19 cubes with integer edge U{64..192} (spheres r in [3, 6], porosity
+    U[0.35, 0.75]); potential U[4, 40] thermal voltages and inlet velocity
+    U[1e-4, 5e-3] for both. Request k has geometry seed base_seed + k."""
+    from .serving import Request, poisson_arrivals
+    arrivals = poisson_arrivals(n, rate_hz, base_seed)
+    rng = np.random.default_rng(base_seed + 1)
+    out = []
+    for k in range(n):
+        is3d = bool(rng.integers(0, 2))
+        dpsi = float(rng.uniform(4.0, 40.0))
+        u_in = float(rng.uniform(1e-4, 5e-3))
+        if is3d:
+            edge = int(rng.integers(64, 193))
+            phi = float(rng.uniform(0.35, 0.75))
+            g = Geometry(dim=3, nx=edge, ny=edge, nz=edge, kind=L.SPHERES, porosity=phi, r_min=3.0,
+                         r_max=6.0, buffer_x=2, seed=base_seed + k)
+            nps = np_steps_3d
+        else:
+            phi = float(rng.uniform(0.55, 0.75))
+            g = Geometry(dim=2, nx=256, ny=256, kind=L.DISKS, porosity=phi, r_min=4.0, r_max=8.0,
+                         min_gap=2.0, walls_y=1, buffer_x=2, seed=base_seed + k)
+            nps = np_steps_2d
+        p = Params(u_in=u_in, dpsi_vt=dpsi, D=(D_NA, D_CL), precision=precision)
+        out.append(Request(k, arrivals[k], g, p, flow_tol=flow_tol, flow_max_steps=flow_max_steps,
+                           np_steps=nps))
+    return out
