@@ -32,9 +32,10 @@ WORKLOAD = "spheres3d_512"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per fluid-node update (D3Q19): populations read + write,
 # concentrations read + write (2 species), ion-advecting flux read + write
-# (FP32: j, 3 floats; FP16: the moments rho-1, u as one float4)
-BYTES_FUSED = {"fp32": 19 * 4 * 2 + 16 + 24, "fp16_dev": 19 * 2 * 2 + 16 + 32}
-BYTES_LBM = {"fp32": 19 * 4 * 2, "fp16_dev": 19 * 2 * 2 + 32}
+# (FP32: j, 3 floats; FP16 and moment storage: the moments rho-1, u as one
+# float4, which also carry j)
+BYTES_FUSED = {"fp32": 19 * 4 * 2 + 16 + 24, "fp16_dev": 19 * 2 * 2 + 16 + 32, "moments": 16 + 32}
+BYTES_LBM = {"fp32": 19 * 4 * 2, "fp16_dev": 19 * 2 * 2 + 32, "moments": 32}
 BYTES_NP = 16 + 12  # C read + write, frozen j read
 
 
@@ -99,7 +100,7 @@ def batched_rates(steps: int, n: int = 64):
     import torch
     import paper_2110_13055_amd as P
     out = {"instances": n}
-    for prec, name in ((P.FP32, "fp32"), (P.FP16_DEV, "fp16_dev")):
+    for prec, name in ((P.FP32, "fp32"), (P.FP16_DEV, "fp16_dev"), (P.MOMENTS, "moments")):
         specs = P.batch_instances(n, precision=prec)
         solvers = [P.Solver(g, p) for g, p in specs]
         nf = sum(s.n_fluid for s in solvers)
@@ -121,7 +122,8 @@ def batched_rates(steps: int, n: int = 64):
         b.close()
         del b, solvers
         torch.cuda.empty_cache()
-    out["speedup_fp32"] = round(out["fp32_batched_mlups"] / out["fp32_sequential_mlups"], 3)
+    for name in ("fp32", "fp16_dev", "moments"):
+        out[f"{name}_batched_vs_fp32_sequential"] = round(out[f"{name}_batched_mlups"] / out["fp32_sequential_mlups"], 3)
     return out
 
 
@@ -200,11 +202,21 @@ def main():
         del a, b
     r32 = gpu_rates(P.FP32, args.steps, args.warmup)
     r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup)
+    rmo = gpu_rates(P.MOMENTS, args.steps, args.warmup)
     nf = r32["n_fluid"]
     K = args.steps
 
     def mlups(sec):
         return nf * K / sec / 1e6
+
+    def form(name, r):
+        return {"fused_mlups": round(mlups(r["fused_s"]), 1),
+                "lbm_mlups": round(mlups(r["lbm_s"]), 1),
+                "np_mlups": round(mlups(r["np_s"]), 1),
+                "algorithmic_bytes_per_node": BYTES_FUSED[name],
+                "fused_gbs": round(BYTES_FUSED[name] * nf / (r["fused_s"] / K) / 1e9, 1),
+                "lbm_gbs": round(BYTES_LBM[name] * nf / (r["lbm_s"] / K) / 1e9, 1),
+                "np_gbs": round(BYTES_NP * nf / (r["np_s"] / K) / 1e9, 1)}
 
     ms_step = r32["fused_s"] / K * 1e3
     achieved = BYTES_FUSED["fp32"] * nf / (r32["fused_s"] / K) / 1e9
@@ -228,21 +240,16 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "algorithmic_bytes_per_node": BYTES_FUSED["fp32"]},
-        "fp16_dev": {"fused_mlups": round(mlups(r16["fused_s"]), 1),
-                     "lbm_mlups": round(mlups(r16["lbm_s"]), 1),
-                     "np_mlups": round(mlups(r16["np_s"]), 1),
-                     "fused_gbs": round(BYTES_FUSED["fp16_dev"] * nf / (r16["fused_s"] / K) / 1e9, 1)},
-        "fp32": {"fused_mlups": round(mlups(r32["fused_s"]), 1),
-                 "lbm_mlups": round(mlups(r32["lbm_s"]), 1),
-                 "np_mlups": round(mlups(r32["np_s"]), 1),
-                 "lbm_gbs": round(BYTES_LBM["fp32"] * nf / (r32["lbm_s"] / K) / 1e9, 1),
-                 "np_gbs": round(BYTES_NP * nf / (r32["np_s"] / K) / 1e9, 1)},
+        "fp32": form("fp32", r32),
+        "fp16_dev": form("fp16_dev", r16),
+        "moments": form("moments", rmo),
         "device": torch.cuda.get_device_name(0),
     }
     if not args.no_batch:
         out["batched"] = batched_rates(K)
     if args.serve_requests > 0:
         sv = {"requests": args.serve_requests, "rate_hz": 2.0, "budget_gb": 200}
+        sv["continuous_batching_moments"] = serving_run(args.serve_requests, P.MOMENTS, 64)
         sv["continuous_batching_fp32"] = serving_run(args.serve_requests, P.FP32, 64)
         sv["plain_fp32_one_at_a_time"] = serving_run(args.serve_requests, P.FP32, 1)
         out["serving"] = sv

@@ -52,7 +52,7 @@ enum { CDI_DISKS = 0, CDI_SPHERES = 1, CDI_USER_LABELS = 2 };
 enum { CDI_INLET_OUTLET = 0, CDI_BODY_FORCE = 1 };
 enum { CDI_EQ_QUADRATIC = 0, CDI_EQ_LINEAR = 1 };
 enum { CDI_NPX_INLET_OUTLET = 0, CDI_NPX_PERIODIC = 1, CDI_NPX_CLOSED = 2, CDI_NPX_DIRICHLET = 3 };
-enum { CDI_FP32 = 0, CDI_FP16_DEV = 1 };
+enum { CDI_FP32 = 0, CDI_FP16_DEV = 1, CDI_MOMENTS = 2 };
 
 /*
  * Electrode geometry (Sec. 2: every grid block is one image voxel; Sec. 4-5:
@@ -105,7 +105,13 @@ typedef struct {
  *   precision    CDI_FP32: populations stored as f - w_i in FP32;
  *                CDI_FP16_DEV: post-collision populations stored as FP16
  *                deviations from the local equilibrium, with the
- *                equilibrium's moments kept in FP32; all arithmetic FP32
+ *                equilibrium's moments kept in FP32; all arithmetic FP32;
+ *                CDI_MOMENTS: only the FP32 moments (rho - 1, u) are stored.
+ *                Requires tau = 1 and no body force (else CDI_E_INVALID):
+ *                then the BGK post-collision populations equal the local
+ *                equilibrium (Eq. 8 with f* = f_eq), so the FP16 deviations
+ *                are identically zero and this is CDI_FP16_DEV without them,
+ *                bit for bit
  */
 typedef struct {
     double tau;
@@ -225,6 +231,10 @@ int cdi_set_concentration(cdi_solver *s, const float *c); /* 2 x N_f */
 typedef struct {
     int32_t blocks_per_cu; /* cap on resident step workgroups per compute unit (0 = none) */
     int32_t band_rows;     /* 3D: rows per band of the tile schedule (0 = plain order) */
+    int32_t columns;       /* 3D, 1: tiles of each group of 8 brick layers dealt round-robin over the
+                              8 XCDs, so the 8 layers at one (x, y) are processed together (the
+                              layers above and below a tile meet in the memory-side cache);
+                              takes precedence over band_rows. 0: off */
 } cdi_tuning;
 
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t);

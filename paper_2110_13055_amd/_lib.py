@@ -17,7 +17,7 @@ DISKS, SPHERES, USER_LABELS = 0, 1, 2
 INLET_OUTLET, BODY_FORCE = 0, 1
 EQ_QUADRATIC, EQ_LINEAR = 0, 1
 NPX_INLET_OUTLET, NPX_PERIODIC, NPX_CLOSED, NPX_DIRICHLET = 0, 1, 2, 3
-FP32, FP16_DEV = 0, 1
+FP32, FP16_DEV, MOMENTS = 0, 1, 2
 MODE_IDLE, MODE_FLOW, MODE_IONS, MODE_FUSED = 0, 1, 2, 3
 
 STATUS_NAMES = {
@@ -65,7 +65,7 @@ class CSolverInfo(C.Structure):
 
 
 class CTuning(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int32), ("band_rows", C.c_int32)]
+    _fields_ = [("blocks_per_cu", C.c_int32), ("band_rows", C.c_int32), ("columns", C.c_int32)]
 
 
 P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double

@@ -11,7 +11,7 @@ namespace {
 // Moments of the stored state (what the next step would see), including the
 // inlet/outlet extrapolation for boundary nodes with a fluid interior
 // neighbour. rho, u, j are optional outputs.
-template <class L, int FP16, int ODD>
+template <class L, int ST, int ODD>
 __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, const void *F,
                                                       const float4 *M, float *rho, float *u, float *j)
 {
@@ -33,10 +33,11 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
     int nb[Q];
     nb[0] = src;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) nb[i] = (ODD || FP16) ? nb_map<L>(g, sx, y, z, i, g.periodic_x) : kOutside;
+    for (int i = 1; i < Q; ++i)
+        nb[i] = (ODD || ST != kF32) ? nb_map<L>(g, sx, y, z, i, g.periodic_x) : kOutside;
     float f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = gather<L, FP16, ODD>(F, g.P, nb, src, i, M, p);
+    for (int i = 0; i < Q; ++i) f[i] = gather<L, ST, ODD>(F, g.P, nb, src, i, M, p);
     if (src != n) {
         float fb[Q];
         nee_populations<L>(p, inlet, f, fb);
@@ -207,26 +208,34 @@ hipError_t launch_tile_heads(const Grid &g, uint32_t *heads, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_moments(int dim, int fp16, int odd, int nee, const Grid &g, const Phys &p,
+namespace {
+
+template <class L>
+void launch_moments_l(int st, int odd, unsigned blocks, int nee, const Grid &g, const Phys &p, const void *f,
+                      const float4 *M, float *rho, float *u, float *j, hipStream_t s)
+{
+#define MK(S, O) moments_kernel<L, S, O><<<blocks, 256, 0, s>>>(g, p, nee, f, M, rho, u, j)
+    if (st == kMom)
+        MK(kMom, 0);
+    else if (st == kF16)
+        odd ? MK(kF16, 1) : MK(kF16, 0);
+    else
+        odd ? MK(kF32, 1) : MK(kF32, 0);
+#undef MK
+}
+
+}  // namespace
+
+hipError_t launch_moments(int dim, int st, int odd, int nee, const Grid &g, const Phys &p,
                           const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((g.n_f + 255) / 256);
     if (blocks == 0) return hipSuccess;
-#define MOM(L, H, O) moments_kernel<L, H, O><<<blocks, 256, 0, s>>>(g, p, nee, f, M, rho, u, j)
-    if (dim == 2) {
-        if (fp16) {
-            if (odd) MOM(D2Q9, 1, 1); else MOM(D2Q9, 1, 0);
-        } else {
-            if (odd) MOM(D2Q9, 0, 1); else MOM(D2Q9, 0, 0);
-        }
-    } else {
-        if (fp16) {
-            if (odd) MOM(D3Q19, 1, 1); else MOM(D3Q19, 1, 0);
-        } else {
-            if (odd) MOM(D3Q19, 0, 1); else MOM(D3Q19, 0, 0);
-        }
-    }
-#undef MOM
+    if (st < kF32 || st > kMom) return hipErrorInvalidValue;
+    if (dim == 2)
+        launch_moments_l<D2Q9>(st, odd, blocks, nee, g, p, f, M, rho, u, j, s);
+    else
+        launch_moments_l<D3Q19>(st, odd, blocks, nee, g, p, f, M, rho, u, j, s);
     return hipGetLastError();
 }
 

@@ -97,7 +97,11 @@ int check_params(const cdi_params *p)
         return fail(CDI_E_INVALID, "bad equilibrium");
     if (p->np_x_bc < 0 || p->np_x_bc > 3) return fail(CDI_E_INVALID, "bad np_x_bc");
     if (p->np_substeps < 1) return fail(CDI_E_INVALID, "np_substeps must be >= 1");
-    if (p->precision != CDI_FP32 && p->precision != CDI_FP16_DEV) return fail(CDI_E_INVALID, "bad precision");
+    if (p->precision != CDI_FP32 && p->precision != CDI_FP16_DEV && p->precision != CDI_MOMENTS)
+        return fail(CDI_E_INVALID, "bad precision");
+    if (p->precision == CDI_MOMENTS && (p->tau != 1.0 || p->drive == CDI_BODY_FORCE))
+        return fail(CDI_E_INVALID, "moment storage needs tau = 1 and no body force "
+                                   "(only then is the post-collision state the local equilibrium)");
     if (!(p->D[0] > 0 && p->D[1] > 0)) return fail(CDI_E_INVALID, "diffusivities must be positive");
     return CDI_OK;
 }
@@ -202,19 +206,26 @@ struct NodeLayout {
     float *psi;   // prescribed potential in internal node order
     double *acc, *resid, *part, *red;
     int *sched;
+    void *base;  // start of the state a checkpoint carries (state_bytes from here)
     uint64_t state_bytes, bytes;
 };
 
-static NodeLayout node_layout(void *ws, int dim, int fp16, int64_t P, int64_t plane)
+// Bytes per stored population of a storage kind.
+static int pop_bytes(int st) { return st == kF32 ? 4 : st == kF16 ? 2 : 0; }
+
+static NodeLayout node_layout(void *ws, int dim, int st, int64_t P, int64_t plane)
 {
     const int Q = dim == 2 ? 9 : 19;
     const int64_t ntiles = P / kTile;
+    const bool mb = st != kF32;  // moment buffers
     Carver c(ws);
     NodeLayout L;
-    L.f = c.take<void>((uint64_t)Q * P * (fp16 ? 2 : 4));
-    L.M[0] = c.take<float4>(fp16 ? 16ull * P : 0);
-    L.M[1] = c.take<float4>(fp16 ? 16ull * P : 0);
-    if (!fp16) L.M[0] = L.M[1] = nullptr;
+    L.base = ws;
+    L.f = c.take<void>((uint64_t)Q * P * pop_bytes(st));
+    L.M[0] = c.take<float4>(mb ? 16ull * P : 0);
+    L.M[1] = c.take<float4>(mb ? 16ull * P : 0);
+    if (!mb) L.M[0] = L.M[1] = nullptr;
+    if (st == kMom) L.f = nullptr;
     L.j[0] = c.take<float>(4ull * dim * P);
     L.j[1] = c.take<float>(4ull * dim * P);
     L.ubuf = c.take<float>(4ull * dim * P);
@@ -238,7 +249,9 @@ enum { J_INVALID = 0, J_VALID = 1, J_IN_M = 2 };
 struct cdi_solver {
     cdi_geometry geom;
     cdi_params params;
-    int dim, Q, fp16, inout;
+    int dim, Q, inout;
+    int st;  // storage: kF32, kF16 or kMom
+    int mb;  // moment buffers in use (kF16, kMom): j of a fused step lives in them
     int64_t nvox, nf;
     int P, ntiles;
     hipStream_t stream;
@@ -247,7 +260,7 @@ struct cdi_solver {
     int parity = 0, mcur = 0, jcur = 0, ccur = 0, jstate = J_INVALID;
     int64_t flow_steps = 0, np_steps = 0;
     double ka, keff[2], porosity;
-    cdi_tuning tuning{0, 0};
+    cdi_tuning tuning{0, 0, 0};
     Grid g;
     Phys p;
 };
@@ -266,7 +279,7 @@ Bufs make_bufs(const cdi_solver *s, int flags)
 {
     Bufs b{};
     b.f = s->node.f;
-    if (s->fp16) {
+    if (s->mb) {
         b.Min = s->node.M[s->mcur];
         b.Mout = s->node.M[s->mcur ^ 1];
     }
@@ -286,8 +299,8 @@ void advance_state(cdi_solver *s, int lbm, int np)
 {
     if (lbm) {
         s->parity ^= 1;
-        if (s->fp16) s->mcur ^= 1;
-        if (np && !s->fp16) s->jcur ^= 1;
+        if (s->mb) s->mcur ^= 1;
+        if (np && !s->mb) s->jcur ^= 1;
         s->flow_steps++;
     }
     if (np) s->ccur ^= 1;
@@ -296,7 +309,7 @@ void advance_state(cdi_solver *s, int lbm, int np)
 int step_once(cdi_solver *s, int lbm, int np, int flags)
 {
     const Bufs b = make_bufs(s, flags);
-    HIPCHK(launch_step(s->dim, s->fp16, s->parity, lbm, np, s->g, s->p, b, s->stream));
+    HIPCHK(launch_step(s->dim, s->st, s->parity, lbm, np, s->g, s->p, b, s->stream));
     advance_state(s, lbm, np);
     return CDI_OK;
 }
@@ -307,8 +320,8 @@ int ensure_j(cdi_solver *s)
     if (s->jstate == J_IN_M) {
         HIPCHK(launch_j_from_m(s->dim, s->g, s->node.M[s->mcur], s->node.j[s->jcur], s->stream));
     } else {
-        HIPCHK(launch_moments(s->dim, s->fp16, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
-                              s->fp16 ? s->node.M[s->mcur] : nullptr, nullptr, nullptr,
+        HIPCHK(launch_moments(s->dim, s->st, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+                              s->mb ? s->node.M[s->mcur] : nullptr, nullptr, nullptr,
                               s->node.j[s->jcur], s->stream));
     }
     s->jstate = J_VALID;
@@ -333,33 +346,62 @@ int check_stability(cdi_solver *s, double *worst)
 // XCD (L2 reuse) instead of a whole plane earlier.
 constexpr int kBandRows = 16;
 
-int build_schedule(cdi_solver *s, int band_rows)
+// XCD-local position of workgroup b of nb (as xcd_tile on the device).
+int64_t xcd_position(int64_t b, int64_t nb)
+{
+    const int64_t q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Tile schedule (XCD-local position -> tile) for the tuning's order:
+//  * bands: each XCD walks a contiguous run of (band of band_rows rows, z, y);
+//  * columns: tiles sorted by (group of 8 brick layers, brick row, brick
+//    column, layer in the group) and dealt to workgroups in that order, so
+//    the 8 XCDs work at once on the 8 layers of a group at the same (x, y):
+//    the layers above and below a tile are being fetched by the neighbouring
+//    XCDs and are met in the memory-side cache.
+int build_schedule(cdi_solver *s, int band_rows, int columns)
 {
     const int T = s->ntiles;
-    if (band_rows <= 0 || s->dim != 3) {
+    if (s->dim != 3 || (band_rows <= 0 && !columns)) {
         s->g.sched = nullptr;
         s->tuning.band_rows = 0;
+        s->tuning.columns = 0;
         return CDI_OK;
     }
     std::vector<uint32_t> heads(T);
     HIPCHK(launch_tile_heads(s->g, (uint32_t *)s->node.sched, s->stream));
     HIPCHK(hipMemcpyAsync(heads.data(), s->node.sched, 4ull * T, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    const int64_t nx = s->g.nx, ny = s->g.ny;
+    const Bricks &k = s->g.bk;
+    const int64_t ny = s->g.ny;
     std::vector<int64_t> key(T);
     std::vector<int> order(T);
     for (int t = 0; t < T; ++t) {
         const uint32_t c = heads[t];
-        const int64_t y = (c >> s->g.bk.cbx) & ((1u << s->g.bk.cby) - 1);
-        const int64_t z = c >> (s->g.bk.cbx + s->g.bk.cby);
-        key[t] = ((y / band_rows) * s->g.nz + z) * ny + y;
+        const int64_t x = c & ((1u << k.cbx) - 1);
+        const int64_t y = (c >> k.cbx) & ((1u << k.cby) - 1);
+        const int64_t z = c >> (k.cbx + k.cby);
+        if (columns) {
+            const int64_t bx = x >> k.bsx, by = y >> k.bsy, bz = z >> k.bsz;
+            key[t] = (((bz >> 3) * k.nby + by) * k.nbx + bx) * 8 + (bz & 7);
+        } else {
+            key[t] = ((y / band_rows) * s->g.nz + z) * ny + y;
+        }
         order[t] = t;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
-    HIPCHK(hipMemcpyAsync(s->node.sched, order.data(), 4ull * T, hipMemcpyHostToDevice, s->stream));
+    std::vector<int> sched(T);
+    if (columns) {
+        for (int64_t b = 0; b < T; ++b) sched[xcd_position(b, T)] = order[b];
+    } else {
+        sched = order;
+    }
+    HIPCHK(hipMemcpyAsync(s->node.sched, sched.data(), 4ull * T, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->g.sched = s->node.sched;
-    s->tuning.band_rows = band_rows;
+    s->tuning.band_rows = columns ? 0 : band_rows;
+    s->tuning.columns = columns ? 1 : 0;
     return CDI_OK;
 }
 
@@ -448,10 +490,10 @@ int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *
     out->n_fluid_est = nf_est;
     out->vox_bytes = vox_layout(nullptr, geom, nprims).bytes;
     const int dim = geom->dim;
-    const int fp16 = params ? params->precision == CDI_FP16_DEV : 0;
+    const int st = params ? params->precision : CDI_FP32;
     const int Q = dim == 2 ? 9 : 19;
     out->node_bytes_per_fluid =
-        (uint64_t)Q * (fp16 ? 2 : 4) + (fp16 ? 32 : 0) + 12ull * dim + 16 + 4ull * (1 + dim) + 1;
+        (uint64_t)Q * pop_bytes(st) + (st != kF32 ? 32 : 0) + 12ull * dim + 16 + 4ull * (1 + dim) + 1;
     g_err[0] = 0;
     return CDI_OK;
 }
@@ -530,10 +572,10 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     }
     VoxLayout V = vox_layout(vox_ws, geom, nprims);
     if (vox_ws_bytes < V.bytes) return fail(CDI_E_BUFFER, "vox_ws too small");
-    const int fp16 = params->precision == CDI_FP16_DEV;
+    const int st_kind = params->precision;
     const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
     if (P > 2147483647LL) return fail(CDI_E_INVALID, "too many fluid nodes");
-    NodeLayout N = node_layout(node_ws, geom->dim, fp16, P, (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz));
+    NodeLayout N = node_layout(node_ws, geom->dim, st_kind, P, (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz));
     if (node_ws_bytes < N.bytes) return fail(CDI_E_BUFFER, "node_ws too small: %llu < %llu",
                                              (unsigned long long)node_ws_bytes, (unsigned long long)N.bytes);
     if (params->np_x_bc != CDI_NPX_PERIODIC && params->np_x_bc != CDI_NPX_CLOSED && geom->nx < 2)
@@ -546,7 +588,8 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     s->params = *params;
     s->dim = geom->dim;
     s->Q = geom->dim == 2 ? 9 : 19;
-    s->fp16 = fp16;
+    s->st = st_kind;
+    s->mb = st_kind != kF32;
     s->inout = params->drive == CDI_INLET_OUTLET;
     s->nvox = nvox;
     s->nf = n_fluid;
@@ -600,9 +643,9 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     auto chk = [&](hipError_t e) {
         if (e != hipSuccess && err == CDI_OK) err = fail(CDI_E_DEVICE, "init: %s", hipGetErrorString(e));
     };
-    // rest state: f - w_i = 0 (FP32) / zero deviations and zero moments (FP16)
-    if (fp16) {
-        chk(launch_fill_u32((uint32_t *)N.f, 0u, (int64_t)s->Q * P / 2, st));
+    // rest state: f - w_i = 0 (FP32) / zero deviations and zero moments (FP16, moments)
+    if (s->mb) {
+        if (s->st == kF16) chk(launch_fill_u32((uint32_t *)N.f, 0u, (int64_t)s->Q * P / 2, st));
         chk(launch_fill_f32((float *)N.M[0], 0.f, 4 * P, st));
         chk(launch_fill_f32((float *)N.M[1], 0.f, 4 * P, st));
     } else {
@@ -617,7 +660,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     chk(launch_fill_f32(N.C[1], (float)params->c0, 2 * P, st));
     chk(launch_fill_f64(N.acc, 0.0, 8ll * s->ntiles, st));
     chk(launch_fill_f64(N.resid, 0.0, 2ll * s->ntiles, st));
-    if (err == CDI_OK) err = build_schedule(s, 0);  // bricks already give locality
+    if (err == CDI_OK) err = build_schedule(s, 0, 0);  // bricks already give locality
     if (err != CDI_OK) {
         delete s;
         return err;
@@ -675,7 +718,7 @@ int cdi_flow_step_to_steady(cdi_solver *s, double tol, int64_t max_steps, int32_
     int64_t t = 0;
     for (; t < max_steps; ++t) {
         int flags = 0;
-        if (!s->fp16 && t % K == K - 1) flags |= kStoreU;
+        if (!s->mb && t % K == K - 1) flags |= kStoreU;
         const bool check = t > 0 && t % K == 0;
         if (check) flags |= kResid;
         int rc = step_once(s, 1, 0, flags);
@@ -724,7 +767,7 @@ int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow)
         return fail(CDI_E_UNSTABLE, "positivity bound violated: dt * sum(outflow coefficients) = %g > 1", worst);
     for (int64_t k = 0; k < nsteps; ++k) {
         if (fused_flow) {
-            const int flags = (s->fp16 && k > 0) ? kJFromM : 0;
+            const int flags = (s->mb && k > 0) ? kJFromM : 0;
             if ((rc = step_once(s, 1, 1, flags)) != CDI_OK) return rc;
         } else {
             for (int m = 0; m < s->params.np_substeps; ++m)
@@ -732,7 +775,7 @@ int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow)
         }
         s->np_steps++;
     }
-    if (fused_flow) s->jstate = s->fp16 ? J_IN_M : J_VALID;
+    if (fused_flow) s->jstate = s->mb ? J_IN_M : J_VALID;
     return CDI_OK;
 }
 
@@ -778,16 +821,16 @@ int cdi_copy_fluid_index(cdi_solver *s, int32_t *map, int32_t *fluid)
 int cdi_copy_velocity(cdi_solver *s, float *u)
 {
     if (!s || !u) return fail(CDI_E_INVALID, "NULL argument");
-    HIPCHK(launch_moments(s->dim, s->fp16, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
-                          s->fp16 ? s->node.M[s->mcur] : nullptr, nullptr, s->node.tmp, nullptr, s->stream));
+    HIPCHK(launch_moments(s->dim, s->st, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+                          s->mb ? s->node.M[s->mcur] : nullptr, nullptr, s->node.tmp, nullptr, s->stream));
     return planes_d2h(s, u, s->node.tmp, s->dim);
 }
 
 int cdi_copy_density(cdi_solver *s, float *rho)
 {
     if (!s || !rho) return fail(CDI_E_INVALID, "NULL argument");
-    HIPCHK(launch_moments(s->dim, s->fp16, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
-                          s->fp16 ? s->node.M[s->mcur] : nullptr, s->node.tmp, nullptr, nullptr, s->stream));
+    HIPCHK(launch_moments(s->dim, s->st, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+                          s->mb ? s->node.M[s->mcur] : nullptr, s->node.tmp, nullptr, nullptr, s->stream));
     return planes_d2h(s, rho, s->node.tmp, 1);
 }
 
@@ -834,7 +877,7 @@ int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes)
     SnapHeader h{kSnapMagic, s->node.state_bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, 0,
                  s->flow_steps, s->np_steps, s->nf};
     std::memcpy(host, &h, sizeof h);
-    return d2h(s, (uint8_t *)host + sizeof h, s->node.f, s->node.state_bytes);
+    return d2h(s, (uint8_t *)host + sizeof h, s->node.base, s->node.state_bytes);
 }
 
 int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
@@ -846,7 +889,7 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
     if (h.magic != kSnapMagic || h.bytes != s->node.state_bytes || h.nf != s->nf ||
         bytes < sizeof h + h.bytes)
         return fail(CDI_E_INVALID, "snapshot does not belong to this solver layout");
-    int rc = h2d(s, s->node.f, (const uint8_t *)host + sizeof h, s->node.state_bytes);
+    int rc = h2d(s, s->node.base, (const uint8_t *)host + sizeof h, s->node.state_bytes);
     if (rc) return rc;
     s->parity = h.parity;
     s->mcur = h.mcur;
@@ -860,12 +903,14 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
 
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t)
 {
-    if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0) return fail(CDI_E_INVALID, "bad tuning");
+    if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0 || t->columns < 0 || t->columns > 1)
+        return fail(CDI_E_INVALID, "bad tuning");
     int pad = 0;
     int rc = occupancy_pad(t->blocks_per_cu, &pad);
     if (rc) return rc;
-    if (t->band_rows != s->tuning.band_rows || (t->band_rows > 0 && !s->g.sched))
-        if ((rc = build_schedule(s, t->band_rows)) != CDI_OK) return rc;
+    if (t->band_rows != s->tuning.band_rows || t->columns != s->tuning.columns ||
+        ((t->band_rows > 0 || t->columns) && !s->g.sched))
+        if ((rc = build_schedule(s, t->band_rows, t->columns)) != CDI_OK) return rc;
     s->g.lds_pad = pad;
     s->tuning.blocks_per_cu = t->blocks_per_cu;
     return CDI_OK;
@@ -891,9 +936,11 @@ int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *c
     std::vector<cdi_tuning> cands;
     const int occ[] = {0, 2, 3, 4, 6};
     const int bands[] = {0, 8, 16, 32};
-    for (int k : occ)
+    for (int k : occ) {
         for (int r : bands)
-            if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r});
+            if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r, 0});
+        if (s->dim == 3) cands.push_back(cdi_tuning{k, 0, 1});
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -946,7 +993,7 @@ constexpr int kSlots = 6;
 struct cdi_batch {
     std::vector<cdi_solver *> m;
     std::vector<int> tile_begin;
-    int n = 0, dim = 0, fp16 = 0, total_tiles = 0, cus = 0;
+    int n = 0, dim = 0, st = 0, total_tiles = 0, cus = 0;
     int workgroups_req = 0, blocks_per_cu = 0, lds_pad = 0;
     hipStream_t stream = nullptr;
     BatchInst *dinst = nullptr;  // device, kSlots * n
@@ -998,10 +1045,10 @@ int batch_flags(const cdi_solver *s, int mode, int64_t idx, int64_t nsteps, bool
 {
     int flags = 0;
     if (mode == kModeFlow && want_resid) {
-        if (idx == nsteps - 2 && !s->fp16) flags |= kStoreU;
+        if (idx == nsteps - 2 && !s->mb) flags |= kStoreU;
         if (idx == nsteps - 1) flags |= kResid;
     }
-    if (mode == kModeFused && s->fp16 && idx > 0) flags |= kJFromM;
+    if (mode == kModeFused && s->mb && idx > 0) flags |= kJFromM;
     return flags;
 }
 
@@ -1064,7 +1111,7 @@ int launch_slot(cdi_batch *bt, int slot)
     for (int c = 0; c < kClasses; ++c) {
         const int count = beg[c + 1] - beg[c];
         if (count <= 0) continue;
-        HIPCHK(launch_batch(bt->dim, bt->fp16, c, bt->dinst + (size_t)slot * bt->n,
+        HIPCHK(launch_batch(bt->dim, bt->st, c, bt->dinst + (size_t)slot * bt->n,
                             bt->dtiles + (size_t)slot * bt->total_tiles + beg[c], count,
                             batch_workgroups(bt, count), bt->lds_pad, bt->stream));
     }
@@ -1143,14 +1190,14 @@ int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t w
     if (ws_bytes < need) return fail(CDI_E_BUFFER, "batch workspace too small: %llu < %llu",
                                      (unsigned long long)ws_bytes, (unsigned long long)need);
     for (int k = 1; k < n; ++k)
-        if (members[k]->dim != members[0]->dim || members[k]->fp16 != members[0]->fp16)
+        if (members[k]->dim != members[0]->dim || members[k]->st != members[0]->st)
             return fail(CDI_E_INVALID, "batch members must share dimension and precision");
     cdi_batch *bt = new (std::nothrow) cdi_batch();
     if (!bt) return fail(CDI_E_INVALID, "out of host memory");
     bt->m.assign(members, members + n);
     bt->n = n;
     bt->dim = members[0]->dim;
-    bt->fp16 = members[0]->fp16;
+    bt->st = members[0]->st;
     bt->stream = (hipStream_t)stream;
     for (int k = 0; k < n; ++k) {
         bt->tile_begin.push_back(bt->total_tiles);
@@ -1232,7 +1279,7 @@ int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
             return fail(CDI_E_INVALID, "member %d: batched ion steps need np_substeps = 1", k);
         if (md == kModeFlow) any_flow = true;
         if ((md == kModeFlow || md == kModeFused) && s->flow_steps == 0) need_first = true;
-        if (md == kModeFused && s->fp16) need_first = true;
+        if (md == kModeFused && s->mb) need_first = true;
     }
     // order after the members' own streams
     for (int k = 0; k < bt->n; ++k) HIPCHK(hipStreamSynchronize(bt->m[k]->stream));
@@ -1295,7 +1342,7 @@ int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
                 bt->resid_valid[k] = 1;
             }
         } else if (modes[k] == kModeFused) {
-            s->jstate = s->fp16 ? J_IN_M : J_VALID;
+            s->jstate = s->mb ? J_IN_M : J_VALID;
         }
     }
     // the members' streams wait for the batch

@@ -4,10 +4,11 @@
 // Data layout in device memory (N_f fluid nodes, stride P = N_f rounded up to
 // a whole number of 256-node tiles):
 //   populations  Q planes of P values (structure of arrays), FP32 f - w_i or
-//                FP16 scaled deviations from the emitter's equilibrium
-//   moments      FP16 storage only: float4 (rho - 1, ux, uy, uz) per node,
-//                double buffered (the moments of the previous step belong to
-//                the emitters of the populations now stored)
+//                FP16 scaled deviations from the emitter's equilibrium; none
+//                with moment storage
+//   moments      FP16 and moment storage: float4 (rho - 1, ux, uy, uz) per
+//                node, double buffered (the moments of the previous step
+//                belong to the emitters of the populations now stored)
 //   jbuf         advecting mass flux j = rho u for the ions, d planes of P,
 //                double buffered (fused steps read one and write the other)
 //   conc         2 species x P, double buffered (Jacobi update)
@@ -57,7 +58,7 @@ constexpr int kNpxInletOutlet = 0, kNpxPeriodic = 1, kNpxClosed = 2, kNpxDirichl
 // step flags
 constexpr int kStoreU = 1;    // write u of the incoming state to ubuf
 constexpr int kResid = 2;     // accumulate |u - ubuf|^2 and |u|^2 per tile
-constexpr int kJFromM = 4;    // FP16 fused: ions read j from the moments buffer
+constexpr int kJFromM = 4;    // FP16/moment fused: ions read j from the moments buffer
 constexpr int kNee = 8;       // the stored state carries inlet/outlet extrapolation
                               // (every state after the first step)
 
@@ -136,6 +137,9 @@ struct Bufs {
     int flags;
 };
 
+// Storage of the lattice state (values of cdi_params.precision).
+constexpr int kF32 = 0, kF16 = 1, kMom = 2;
+
 // One instance of a batched launch.
 constexpr int kModeIdle = 0, kModeFlow = 1, kModeIons = 2, kModeFused = 3;
 struct BatchInst {
@@ -174,21 +178,22 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 
 // One LBM and/or Nernst-Planck step over all fluid nodes.
-//   dim 2/3, fp16 0/1, odd = AA parity of the stored state, lbm/np switches.
-hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p,
+//   dim 2/3, st = kF32/kF16/kMom, odd = AA parity of the stored state,
+//   lbm/np switches.
+hipError_t launch_step(int dim, int st, int odd, int lbm, int np, const Grid &g, const Phys &p,
                        const Bufs &b, hipStream_t s);
 // One step of the instances of one step class in one persistent launch of
 // `workgroups` workgroups over the class's (instance, tile) list (inst and
 // tiles in device memory).
-hipError_t launch_batch(int dim, int fp16, int cls, const BatchInst *inst, const int2 *tiles, int ntiles,
+hipError_t launch_batch(int dim, int st, int cls, const BatchInst *inst, const int2 *tiles, int ntiles,
                         int workgroups, int lds_pad, hipStream_t s);
 // Moments of the stored state: rho (nullable), u (nullable, d planes),
 // j (nullable, d planes).
-hipError_t launch_moments(int dim, int fp16, int odd, int nee, const Grid &g, const Phys &p,
+hipError_t launch_moments(int dim, int st, int odd, int nee, const Grid &g, const Phys &p,
                           const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s);
 // Packed coordinates of the first node of every tile (host-side tile schedule).
 hipError_t launch_tile_heads(const Grid &g, uint32_t *heads, hipStream_t s);
-// j = (1 + drho) u from the FP16 moments buffer.
+// j = (1 + drho) u from the moments buffer (FP16 and moment storage).
 hipError_t launch_j_from_m(int dim, const Grid &g, const float4 *M, float *j, hipStream_t s);
 // Deterministic single-block sums: out[k] = sum_t in[t*stride + k], k < width.
 hipError_t launch_reduce_tiles(const double *in, int ntiles, int stride, int width, double *out,

@@ -16,6 +16,12 @@
 // the emitting node's equilibrium, times hs; the emitter's moments
 // (rho - 1, u) are kept in FP32. The emitter of f_i(x) is x - e_i if that
 // voxel is fluid, else x itself (which sent it in direction opp(i)).
+//
+// Moment storage keeps the moments alone: with tau = 1 and no body force the
+// BGK post-collision populations are exactly the equilibrium of the node's
+// moments (the FP16 deviations above are then identically zero), so f_i(x)
+// is the emitter's equilibrium and no population is stored; the AA parity
+// plays no role.
 #pragma once
 
 #include "cdi_internal.h"
@@ -117,9 +123,8 @@ __device__ inline int nb_get(const Grid &g, const NbCtx &c, int i)
     return g.map[e];
 }
 
-// BGK equilibrium minus w_i, from rho - 1 and u: quadratic in u, or its
-// linear (Stokes) part.
-// Same, from e_i.u for a direction of weight w (i need not be known at compile time).
+// BGK equilibrium minus w_i for a direction of weight w, from rho - 1, u and
+// e.u: quadratic in u, or its linear (Stokes) part.
 __device__ inline float feq_bar_eu(float w, float drho, float eu, float ux, float uy, float uz, int linear)
 {
     const float rho = 1.f + drho;
@@ -128,6 +133,7 @@ __device__ inline float feq_bar_eu(float w, float drho, float eu, float ux, floa
     return w * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
 }
 
+// The same for lattice direction i.
 template <class L>
 __device__ inline float feq_bar(int i, float drho, float ux, float uy, float uz, int linear)
 {
@@ -154,37 +160,43 @@ __device__ inline void st(void *F, int P, int i, int n, float v)
 }
 
 // Incoming f_i - w_i of node n (nb: map values of n's neighbours; M: the
-// emitters' moments, FP16 only).
-template <class L, int FP16, int ODD>
+// emitters' moments, FP16 and moment storage; ST: kF32, kF16 or kMom).
+template <class L, int ST, int ODD>
 __device__ inline float gather(const void *F, int P, const int *nb, int n, int i, const float4 *M,
                                const Phys &p)
 {
     const int j = L::opp[i];
     const bool fl = (i != 0) && nb[j] >= 0;
-    float raw;
-    if (!ODD || i == 0 || !fl)
-        raw = ld<FP16>(F, P, i, n);
-    else
-        raw = ld<FP16>(F, P, j, nb[j]);
-    if (!FP16) return raw;
+    float raw = 0.f;
+    if (ST != kMom) {
+        if (!ODD || i == 0 || !fl)
+            raw = ld<ST == kF16>(F, P, i, n);
+        else
+            raw = ld<ST == kF16>(F, P, j, nb[j]);
+    }
+    if (ST == kF32) return raw;
     // emitter x - e_i sent it along e_i; a reflected one was sent by x along
     // e_opp(i) = -e_i, which only flips the sign of e.u (w_opp(i) = w_i)
     const int e = fl ? nb[j] : n;
     const float4 m = M[e];
     const float eu = L::ex[i] * m.y + L::ey[i] * m.z + L::ez[i] * m.w;
-    return feq_bar_eu(L::w[i], m.x, fl ? eu : -eu, m.y, m.z, m.w, p.linear_eq) + raw * p.hs_inv;
+    const float fe = feq_bar_eu(L::w[i], m.x, fl ? eu : -eu, m.y, m.z, m.w, p.linear_eq);
+    return ST == kMom ? fe : fe + raw * p.hs_inv;
 }
 
-// Store the outgoing value of direction i (FP32: f* - w_i; FP16: scaled deviation).
-template <class L, int FP16, int ODD>
+// Store the outgoing value of direction i (FP32: f* - w_i; FP16: scaled
+// deviation; moment storage: nothing).
+template <class L, int ST, int ODD>
 __device__ inline void scatter(void *F, int P, const int *nb, int n, int i, float v)
 {
+    if (ST == kMom) return;
+    constexpr bool H = ST == kF16;
     if (!ODD || i == 0)
-        st<FP16>(F, P, L::opp[i], n, v);
+        st<H>(F, P, L::opp[i], n, v);
     else if (nb[i] >= 0)
-        st<FP16>(F, P, i, nb[i], v);
+        st<H>(F, P, i, nb[i], v);
     else
-        st<FP16>(F, P, L::opp[i], n, v);
+        st<H>(F, P, L::opp[i], n, v);
 }
 
 // Non-equilibrium extrapolation (Guo, Zheng & Shi 2002) for the inlet

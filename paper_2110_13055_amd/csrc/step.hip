@@ -23,8 +23,8 @@ namespace {
 
 // Moments, residual terms, collision and the AA store of one node whose
 // incoming populations (minus w_i) are f.
-template <class L, int FP16, int ODD, int NP>
-__device__ inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, const int *nb,
+template <class L, int ST, int ODD, int NP>
+__device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, const int *nb,
                                 const float (&f)[L::Q], double (&res)[2])
 {
     constexpr int Q = L::Q, D = L::D;
@@ -45,7 +45,7 @@ __device__ inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, cons
     const float ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
     if (b.flags & kResid) {
         float px, py, pz;
-        if (FP16) {
+        if (ST != kF32) {
             const float4 m = b.Min[n];
             px = m.y;
             py = m.z;
@@ -59,17 +59,18 @@ __device__ inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, cons
         res[0] += dx * dx + dy * dy + dz * dz;
         res[1] += (double)ux * ux + (double)uy * uy + (double)uz * uz;
     }
-    if (!FP16 && (b.flags & kStoreU)) {
+    if (ST == kF32 && (b.flags & kStoreU)) {
         b.ubuf[n] = ux;
         b.ubuf[P + n] = uy;
         if (D == 3) b.ubuf[2 * P + n] = uz;
     }
-    if (FP16) b.Mout[n] = make_float4(drho, ux, uy, uz);
-    if (NP && !FP16) {
+    if (ST != kF32) b.Mout[n] = make_float4(drho, ux, uy, uz);
+    if (NP && ST == kF32) {
         b.jout[n] = jx;
         b.jout[P + n] = jy;
         if (D == 3) b.jout[2 * P + n] = jz;
     }
+    if (ST == kMom) return;  // the post-collision state is the equilibrium of Mout
     const float om = p.omega;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -83,18 +84,18 @@ __device__ inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, cons
                    (3.f * (L::ez[i] - uz) + 9.f * eu * L::ez[i]) * p.F[2]);
         }
         float out;
-        if (FP16)
+        if (ST == kF16)
             out = ((1.f - om) * (f[i] - fe) + src) * p.hs;
         else
             out = f[i] - om * (f[i] - fe) + src;
-        scatter<L, FP16, ODD>(b.f, P, nb, n, i, out);
+        scatter<L, ST, ODD>(b.f, P, nb, n, i, out);
     }
 }
 
 // One 256-node tile of one instance (all threads of the workgroup call it;
 // sm: (kTile/64)*6 doubles of LDS).
-template <class L, int FP16, int ODD, int LBM, int NP>
-__device__ inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, int tile, double *sm)
+template <class L, int ST, int ODD, int LBM, int NP>
+__device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, int tile, double *sm)
 {
     constexpr int Q = L::Q, D = L::D;
     const int n = tile * kTile + threadIdx.x;
@@ -106,7 +107,7 @@ __device__ inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, in
     if (active) {
         int x, y, z;
         unpack_xyz(g, g.fluid[n], x, y, z);
-        constexpr bool need_all = LBM && (ODD || FP16);
+        constexpr bool need_all = LBM && (ODD || ST != kF32);
         const bool edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
         NbCtx ctx;
         nb_ctx<L>(g, x, y, z, g.periodic_x, ctx);
@@ -124,8 +125,8 @@ __device__ inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, in
             if (!by_partner) {
                 float f[Q];
 #pragma unroll
-                for (int i = 0; i < Q; ++i) f[i] = gather<L, FP16, ODD>(b.f, P, nb, n, i, b.Min, p);
-                lbm_node<L, FP16, ODD, NP>(p, b, P, n, nb, f, res);
+                for (int i = 0; i < Q; ++i) f[i] = gather<L, ST, ODD>(b.f, P, nb, n, i, b.Min, p);
+                lbm_node<L, ST, ODD, NP>(p, b, P, n, nb, f, res);
                 const bool inl = edge && x == 1 && nb[2] >= 0;
                 const bool outl = edge && x == g.nx - 2 && nb[1] >= 0;
                 if (inl || outl) {
@@ -137,7 +138,7 @@ __device__ inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, in
                     for (int i = 1; i < Q; ++i) nbb[i] = nb_map<L>(g, xb, y, z, i, false);  // rare path
                     float fb[Q];
                     nee_populations<L>(p, inl, f, fb);
-                    lbm_node<L, FP16, ODD, NP>(p, b, P, bn, nbb, fb, res);
+                    lbm_node<L, ST, ODD, NP>(p, b, P, bn, nbb, fb, res);
                 }
             }
         }
@@ -145,7 +146,7 @@ __device__ inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, in
         if (NP) {
             const float cP[2] = {b.Cin[n], b.Cin[P + n]};
             float jP[3];
-            const bool jm = FP16 && (b.flags & kJFromM);
+            const bool jm = ST != kF32 && (b.flags & kJFromM);
             if (jm) {
                 const float4 m = b.Min[n];
                 const float r = 1.f + m.x;
@@ -251,13 +252,13 @@ __device__ inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, in
     }
 }
 
-template <class L, int FP16, int ODD, int LBM, int NP>
+template <class L, int ST, int ODD, int LBM, int NP>
 __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
 {
     __shared__ double sm[(kTile / 64) * 6];
     extern __shared__ double lds_pad[];  // sized at launch: occupancy cap only
     (void)lds_pad;
-    step_tile<L, FP16, ODD, LBM, NP>(g, p, b, block_tile(g), sm);
+    step_tile<L, ST, ODD, LBM, NP>(g, p, b, block_tile(g), sm);
 }
 
 // Many instances in one persistent launch per step class (LBM parity and
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
 // parameters and buffers, so uneven sizes share the launch; the descriptor is
 // copied once per tile into registers. Tile results do not depend on which
 // workgroup computes them.
-template <class L, int FP16, int ODD, int LBM, int NP>
+template <class L, int ST, int ODD, int LBM, int NP>
 __global__ __launch_bounds__(kTile) void batch_kernel(const BatchInst *__restrict__ inst,
                                                       const int2 *__restrict__ tiles, int ntiles)
 {
@@ -289,88 +290,97 @@ __global__ __launch_bounds__(kTile) void batch_kernel(const BatchInst *__restric
         const Grid g = inst[e.x].g;
         const Phys p = inst[e.x].p;
         const Bufs b = inst[e.x].b;
-        step_tile<L, FP16, ODD, LBM, NP>(g, p, b, e.y, sm);
+        step_tile<L, ST, ODD, LBM, NP>(g, p, b, e.y, sm);
     }
 }
 
-template <class L, int FP16>
+template <class L, int ST>
 void launch_batch_t(int cls, const BatchInst *inst, const int2 *tiles, int ntiles, int wg, int pad,
                     hipStream_t s)
 {
     const size_t lds = (size_t)pad;
+    constexpr int O1 = ST == kMom ? 0 : 1;  // moment storage has no AA parity
     switch (cls) {
-    case kClassFlowEven: batch_kernel<L, FP16, 0, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
-    case kClassFlowOdd: batch_kernel<L, FP16, 1, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
-    case kClassFusedEven: batch_kernel<L, FP16, 0, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
-    case kClassFusedOdd: batch_kernel<L, FP16, 1, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
-    default: batch_kernel<L, 0, 0, 0, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFlowEven: batch_kernel<L, ST, 0, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFlowOdd: batch_kernel<L, ST, O1, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFusedEven: batch_kernel<L, ST, 0, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFusedOdd: batch_kernel<L, ST, O1, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    default: batch_kernel<L, kF32, 0, 0, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
     }
 }
 
-template <class L, int FP16, int ODD, int LBM, int NP>
+template <class L, int ST, int ODD, int LBM, int NP>
 void launch_t(const Grid &g, const Phys &p, const Bufs &b, hipStream_t s)
 {
     const unsigned blocks = (unsigned)(g.P / kTile);
-    step_kernel<L, FP16, ODD, LBM, NP><<<blocks, kTile, (size_t)g.lds_pad, s>>>(g, p, b);
+    step_kernel<L, ST, ODD, LBM, NP><<<blocks, kTile, (size_t)g.lds_pad, s>>>(g, p, b);
 }
 
-template <class L, int FP16, int ODD>
+template <class L, int ST, int ODD>
 void launch_mode(int lbm, int np, const Grid &g, const Phys &p, const Bufs &b, hipStream_t s)
 {
     if (lbm && np)
-        launch_t<L, FP16, ODD, 1, 1>(g, p, b, s);
+        launch_t<L, ST, ODD, 1, 1>(g, p, b, s);
     else if (lbm)
-        launch_t<L, FP16, ODD, 1, 0>(g, p, b, s);
+        launch_t<L, ST, ODD, 1, 0>(g, p, b, s);
     else
-        launch_t<L, 0, 0, 0, 1>(g, p, b, s);
+        launch_t<L, kF32, 0, 0, 1>(g, p, b, s);
 }
 
 template <class L>
-void launch_prec(int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p, const Bufs &b,
+void launch_prec(int st, int odd, int lbm, int np, const Grid &g, const Phys &p, const Bufs &b,
                  hipStream_t s)
 {
-    if (fp16) {
+    if (st == kMom) {
+        launch_mode<L, kMom, 0>(lbm, np, g, p, b, s);
+    } else if (st == kF16) {
         if (odd)
-            launch_mode<L, 1, 1>(lbm, np, g, p, b, s);
+            launch_mode<L, kF16, 1>(lbm, np, g, p, b, s);
         else
-            launch_mode<L, 1, 0>(lbm, np, g, p, b, s);
+            launch_mode<L, kF16, 0>(lbm, np, g, p, b, s);
     } else {
         if (odd)
-            launch_mode<L, 0, 1>(lbm, np, g, p, b, s);
+            launch_mode<L, kF32, 1>(lbm, np, g, p, b, s);
         else
-            launch_mode<L, 0, 0>(lbm, np, g, p, b, s);
+            launch_mode<L, kF32, 0>(lbm, np, g, p, b, s);
     }
+}
+
+template <class L>
+void launch_batch_l(int st, int cls, const BatchInst *inst, const int2 *tiles, int ntiles, int wg, int pad,
+                    hipStream_t s)
+{
+    if (st == kMom)
+        launch_batch_t<L, kMom>(cls, inst, tiles, ntiles, wg, pad, s);
+    else if (st == kF16)
+        launch_batch_t<L, kF16>(cls, inst, tiles, ntiles, wg, pad, s);
+    else
+        launch_batch_t<L, kF32>(cls, inst, tiles, ntiles, wg, pad, s);
 }
 
 }  // namespace
 
-hipError_t launch_batch(int dim, int fp16, int cls, const BatchInst *inst, const int2 *tiles, int ntiles,
+hipError_t launch_batch(int dim, int st, int cls, const BatchInst *inst, const int2 *tiles, int ntiles,
                         int workgroups, int lds_pad, hipStream_t s)
 {
     if (ntiles <= 0 || workgroups <= 0) return hipSuccess;
-    if (cls < 0 || cls >= kClasses) return hipErrorInvalidValue;
-    if (dim == 2) {
-        if (fp16)
-            launch_batch_t<D2Q9, 1>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
-        else
-            launch_batch_t<D2Q9, 0>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
-    } else {
-        if (fp16)
-            launch_batch_t<D3Q19, 1>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
-        else
-            launch_batch_t<D3Q19, 0>(cls, inst, tiles, ntiles, workgroups, lds_pad, s);
-    }
+    if (cls < 0 || cls >= kClasses || st < kF32 || st > kMom) return hipErrorInvalidValue;
+    if (dim == 2)
+        launch_batch_l<D2Q9>(st, cls, inst, tiles, ntiles, workgroups, lds_pad, s);
+    else
+        launch_batch_l<D3Q19>(st, cls, inst, tiles, ntiles, workgroups, lds_pad, s);
     return hipGetLastError();
 }
 
-hipError_t launch_step(int dim, int fp16, int odd, int lbm, int np, const Grid &g, const Phys &p,
+hipError_t launch_step(int dim, int st, int odd, int lbm, int np, const Grid &g, const Phys &p,
                        const Bufs &b, hipStream_t s)
 {
     if (g.P <= 0) return hipSuccess;
+    if (st < kF32 || st > kMom) return hipErrorInvalidValue;
     if (dim == 2)
-        launch_prec<D2Q9>(fp16, odd, lbm, np, g, p, b, s);
+        launch_prec<D2Q9>(st, odd, lbm, np, g, p, b, s);
     else
-        launch_prec<D3Q19>(fp16, odd, lbm, np, g, p, b, s);
+        launch_prec<D3Q19>(st, odd, lbm, np, g, p, b, s);
     return hipGetLastError();
 }
 

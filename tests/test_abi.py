@@ -61,6 +61,24 @@ def test_plan_rejects_bad_input():
     assert e.value.code == L.E_GEOMETRY
 
 
+def test_moment_storage_needs_tau_one_and_no_body_force():
+    import paper_2110_13055_amd as P
+    from paper_2110_13055_amd import _lib as L
+    g, p, _ = P.preset("channel2d_128x64", precision=L.MOMENTS)
+    info = P.plan(g, p)
+    f32 = P.plan(g, P.preset("channel2d_128x64")[1])
+    assert info.node_bytes_per_fluid < f32.node_bytes_per_fluid  # no population planes
+    p.tau = 0.8
+    with pytest.raises(L.CdiError) as e:
+        P.plan(g, p)
+    assert e.value.code == L.E_INVALID and "tau = 1" in str(e.value)
+    g, p, _ = P.preset("channel2d_128x64", precision=L.MOMENTS, drive=L.BODY_FORCE,
+                       body_force=(1e-6, 0.0, 0.0))
+    with pytest.raises(L.CdiError) as e:
+        P.plan(g, p)
+    assert e.value.code == L.E_INVALID
+
+
 def test_last_error_is_a_string():
     from paper_2110_13055_amd import _lib as L
     lib = L.load()

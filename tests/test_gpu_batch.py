@@ -60,7 +60,7 @@ def run_alone(specs):
     return out
 
 
-@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV])
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV, L.MOMENTS])
 def test_batch_equals_members_stepped_alone(precision):
     specs = members(precision)
     alone = run_alone(specs)

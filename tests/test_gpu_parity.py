@@ -228,6 +228,45 @@ def test_fp16_dev_parity_tau1(fused):
     _check_np(s, o)
 
 
+def _state(s):
+    return (s.velocity(), s.density(), s.concentration(), s.adsorbed_total(), s.mass_balance())
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_moments_parity_and_bitwise_equal_to_fp16_dev_at_tau1(fused):
+    # at tau = 1 the FP16 deviations are exactly zero: moment storage is the
+    # same computation without them
+    g, p, _ = preset("channel2d_128x64", precision=L.MOMENTS)
+    s, o = _flow_then_np(g, p, 1500, 501, fused)
+    assert rel_l2(s.velocity(), o.velocity()) <= 1e-5
+    _check_np(s, o)
+    g2, p2, _ = preset("channel2d_128x64", precision=L.FP16_DEV)
+    h = Solver(g2, p2)
+    h.flow_steps(1500)
+    h.np_step(501, fused=fused)
+    for a, b in zip(_state(s), _state(h)):
+        assert np.array_equal(a, b)
+
+
+def test_moments_3d_parity_odd_counts_and_residual():
+    g, p = small3d(seed=11, precision=L.MOMENTS)
+    s = Solver(g, p)
+    o = oracle_solver(g, p)
+    s.flow_steps(301)
+    o.flow_steps(301)
+    assert rel_l2(s.velocity(), o.velocity()) <= 1e-5
+    s.np_step(151, fused=True)
+    assert o.np_steps(151, fused=True) == 0
+    _check_np(s, o)
+    h = Solver(*small3d(seed=11, precision=L.FP16_DEV))
+    h.flow_steps(301)
+    h.np_step(151, fused=True)
+    for a, b in zip(_state(s), _state(h)):
+        assert np.array_equal(a, b)
+    rc, steps, r = s.flow_to_steady(tol=1e-30, max_steps=400, check_every=100)
+    assert np.isfinite(r) and r > 0
+
+
 def test_fp16_dev_error_statement_tau_08():
     # away from tau = 1 the stored deviations are (1 - 1/tau) f_neq in FP16
     g, p = small3d(tau=0.8)
@@ -243,8 +282,9 @@ def test_fp16_dev_error_statement_tau_08():
 
 # ------------------------------------------------------------------ systems
 
-def test_snapshot_restore_continues_bitwise():
-    g, p = small3d()
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV, L.MOMENTS])
+def test_snapshot_restore_continues_bitwise(precision):
+    g, p = small3d(precision=precision)
     s = Solver(g, p)
     s.flow_steps(51)
     s.np_step(20, fused=True)
@@ -259,11 +299,11 @@ def test_snapshot_restore_continues_bitwise():
 
 def test_results_do_not_depend_on_tuning_and_autotune_restores_state():
     outs = []
-    for occ, band in ((0, 0), (3, 8), (6, 32)):
+    for occ, band, cols in ((0, 0, 0), (3, 8, 0), (6, 32, 0), (0, 0, 1), (4, 0, 1)):
         g, p = small3d(seed=13)
         s = Solver(g, p)
-        s.set_tuning(occ, band)
-        assert s.tuning() == (occ, band)
+        s.set_tuning(occ, band, cols)
+        assert s.tuning() == (occ, band, cols)
         s.flow_steps(21)
         s.np_step(30, fused=True)
         outs.append((s.concentration(), s.velocity(), s.adsorbed_total()))

@@ -55,7 +55,7 @@ def serve(reqs):
     return srv, res
 
 
-@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV])
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV, L.MOMENTS])
 def test_served_results_alone_equal_mix(precision):
     reqs = trace(precision)
     srv, mix = serve(reqs)
