@@ -63,6 +63,9 @@ int check_geometry(const cdi_geometry *g)
     if (g->nx < 4 || g->ny < 1 || nz < 1) return fail(CDI_E_INVALID, "lattice too small (nx >= 4)");
     const double nvox = (double)g->nx * g->ny * nz;
     if (nvox >= 2147483647.0) return fail(CDI_E_INVALID, "nx*ny*nz must be < 2^31");
+    // the step kernels address the brick-ordered map with 32-bit byte offsets
+    const double bricked = (double)((g->nx + 15) / 8 * 8) * ((g->ny + 15) / 8 * 8) * (g->dim == 2 ? 1 : (nz + 7) / 8 * 8);
+    if (bricked * 4.0 >= 4294967296.0) return fail(CDI_E_INVALID, "lattice too large for one instance (> 2^30 voxels)");
     {
         int bits = 0;
         for (int n : {g->nx, g->ny, nz}) {
@@ -287,9 +290,9 @@ Bufs make_bufs(const cdi_solver *s, int flags)
     b.jout = s->node.j[s->jcur ^ 1];
     b.Cin = s->node.C[s->ccur];
     b.Cout = s->node.C[s->ccur ^ 1];
+    b.ubuf = s->node.ubuf;
     b.acc = s->node.acc;
     b.resid = s->node.resid;
-    b.ubuf = s->node.ubuf;
     b.flags = flags | (s->flow_steps > 0 ? kNee : 0);
     return b;
 }
@@ -574,7 +577,9 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     if (vox_ws_bytes < V.bytes) return fail(CDI_E_BUFFER, "vox_ws too small");
     const int st_kind = params->precision;
     const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
-    if (P > 2147483647LL) return fail(CDI_E_INVALID, "too many fluid nodes");
+    // per-node arrays are addressed with 32-bit byte offsets (16-byte moments)
+    if (P * (st_kind == kF32 ? 4 : 16) > 4294967295LL)
+        return fail(CDI_E_INVALID, "too many fluid nodes for one instance (limit 2^30, 2^28 with moment buffers)");
     NodeLayout N = node_layout(node_ws, geom->dim, st_kind, P, (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz));
     if (node_ws_bytes < N.bytes) return fail(CDI_E_BUFFER, "node_ws too small: %llu < %llu",
                                              (unsigned long long)node_ws_bytes, (unsigned long long)N.bytes);

@@ -123,6 +123,7 @@ struct Phys {
     float hs, hs_inv;
 };
 
+// Buffers of one step; multi-plane fields are P apart (structure of arrays).
 struct Bufs {
     void *f;
     const float4 *Min;

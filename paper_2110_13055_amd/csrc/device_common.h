@@ -28,6 +28,23 @@
 
 namespace cdi {
 
+// Element idx of an array whose base is the same for the whole wave. The
+// address is formed as base + a 32-bit byte offset, which the hardware takes
+// as a scalar base plus one vector offset: no 64-bit address arithmetic per
+// lane, and one offset serves every array indexed by the same node. The host
+// keeps idx * sizeof(T) below 2^32.
+template <class T>
+__device__ __forceinline__ T ldu(const T *base, uint32_t idx)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (uint32_t)sizeof(T));
+}
+
+template <class T>
+__device__ __forceinline__ void stu(T *base, uint32_t idx, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (uint32_t)sizeof(T)) = v;
+}
+
 // blockIdx -> tile: workgroups are dealt round-robin over the 8 XCDs, each
 // with its own L2; this keeps consecutive tiles on one XCD so that the y/z
 // neighbours a tile touches were mostly fetched by the same L2.
@@ -74,18 +91,21 @@ __device__ inline void unpack_xyz(const Grid &g, uint32_t c, int &x, int &y, int
 }
 
 // Neighbour lookup context of one voxel: for each axis and offset -1/0/+1,
-// the brick part and the in-brick part of the neighbour's brick-ordered
-// index, so that each lattice direction costs a few integer operations.
+// that axis's share of the neighbour's brick-ordered index. The brick part
+// (above the in-brick bits) and the in-brick part occupy disjoint bits, so a
+// neighbour's index is the plain sum of its three axis shares: one three-way
+// add per lattice direction. Coordinates wrap on every axis (the index is
+// always in range); xo marks offsets beyond an open x end.
 struct NbCtx {
-    int bx[3], lx[3];  // bx < 0: beyond an open x end
-    int by[3], ly[3];
-    int bz[3], lz[3];
+    uint32_t X[3], Y[3], Z[3];
+    bool xo[3];
 };
 
 template <class L>
 __device__ inline void nb_ctx(const Grid &g, int x, int y, int z, bool periodic_x, NbCtx &c)
 {
     const Bricks &k = g.bk;
+    const int V = k.bsx + k.bsy + k.bsz;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         int xn = x + d - 1;
@@ -94,33 +114,30 @@ __device__ inline void nb_ctx(const Grid &g, int x, int y, int z, bool periodic_
             out = !periodic_x;
             xn = xn < 0 ? xn + g.nx : xn - g.nx;
         }
-        c.bx[d] = out ? -1 : (xn >> k.bsx);
-        c.lx[d] = xn & ((1 << k.bsx) - 1);
+        c.xo[d] = out;
+        c.X[d] = ((uint32_t)(xn >> k.bsx) << V) | (uint32_t)(xn & ((1 << k.bsx) - 1));
         int yn = y + d - 1;
         yn = yn < 0 ? yn + g.ny : (yn >= g.ny ? yn - g.ny : yn);
-        c.by[d] = (yn >> k.bsy) * k.nbx;
-        c.ly[d] = (yn & ((1 << k.bsy) - 1)) << k.bsx;
+        c.Y[d] = ((uint32_t)((yn >> k.bsy) * k.nbx) << V) | ((uint32_t)(yn & ((1 << k.bsy) - 1)) << k.bsx);
         if (L::D == 3) {
             int zn = z + d - 1;
             zn = zn < 0 ? zn + g.nz : (zn >= g.nz ? zn - g.nz : zn);
-            c.bz[d] = (zn >> k.bsz) * k.nbx * k.nby;
-            c.lz[d] = (zn & ((1 << k.bsz) - 1)) << (k.bsx + k.bsy);
+            c.Z[d] = ((uint32_t)((zn >> k.bsz) * k.nbx * k.nby) << V) |
+                     ((uint32_t)(zn & ((1 << k.bsz) - 1)) << (k.bsx + k.bsy));
         } else {
-            c.bz[d] = 0;
-            c.lz[d] = 0;
+            c.Z[d] = 0;
         }
     }
 }
 
-// map value of the neighbour along direction i (see nb_map).
+// map value of the neighbour along direction i (see nb_map). Past an open x
+// end the wrapped voxel is read (always in range) and replaced by kOutside.
 template <class L>
 __device__ inline int nb_get(const Grid &g, const NbCtx &c, int i)
 {
     const int dx = L::ex[i] + 1, dy = L::ey[i] + 1, dz = L::ez[i] + 1;
-    if (c.bx[dx] < 0) return kOutside;
-    const int V = g.bk.bsx + g.bk.bsy + g.bk.bsz;
-    const int e = ((c.bx[dx] + c.by[dy] + c.bz[dz]) << V) | (c.lx[dx] | c.ly[dy] | c.lz[dz]);
-    return g.map[e];
+    const int m = ldu(g.map, c.X[dx] + c.Y[dy] + c.Z[dz]);
+    return (L::ex[i] != 0 && c.xo[dx]) ? kOutside : m;
 }
 
 // BGK equilibrium minus w_i for a direction of weight w, from rho - 1, u and
@@ -141,6 +158,7 @@ __device__ inline float feq_bar(int i, float drho, float ux, float uy, float uz,
     return feq_bar_eu(L::w[i], drho, eu, ux, uy, uz, linear);
 }
 
+// Population plane i of node n (planes P apart).
 template <int FP16>
 __device__ inline float ld(const void *F, int P, int i, int n)
 {
@@ -178,7 +196,7 @@ __device__ inline float gather(const void *F, int P, const int *nb, int n, int i
     // emitter x - e_i sent it along e_i; a reflected one was sent by x along
     // e_opp(i) = -e_i, which only flips the sign of e.u (w_opp(i) = w_i)
     const int e = fl ? nb[j] : n;
-    const float4 m = M[e];
+    const float4 m = ldu(M, (uint32_t)e);
     const float eu = L::ex[i] * m.y + L::ey[i] * m.z + L::ez[i] * m.w;
     const float fe = feq_bar_eu(L::w[i], m.x, fl ? eu : -eu, m.y, m.z, m.w, p.linear_eq);
     return ST == kMom ? fe : fe + raw * p.hs_inv;

@@ -22,7 +22,8 @@ namespace cdi {
 namespace {
 
 // Moments, residual terms, collision and the AA store of one node whose
-// incoming populations (minus w_i) are f.
+// incoming populations (minus w_i) are f; NP: also store the mass flux j for
+// the ions of the next step (FP32; the other storages carry it in Mout).
 template <class L, int ST, int ODD, int NP>
 __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, const int *nb,
                                 const float (&f)[L::Q], double (&res)[2])
@@ -46,7 +47,7 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
     if (b.flags & kResid) {
         float px, py, pz;
         if (ST != kF32) {
-            const float4 m = b.Min[n];
+            const float4 m = ldu(b.Min, (uint32_t)n);
             px = m.y;
             py = m.z;
             pz = m.w;
@@ -64,7 +65,7 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
         b.ubuf[P + n] = uy;
         if (D == 3) b.ubuf[2 * P + n] = uz;
     }
-    if (ST != kF32) b.Mout[n] = make_float4(drho, ux, uy, uz);
+    if (ST != kF32) stu(b.Mout, (uint32_t)n, make_float4(drho, ux, uy, uz));
     if (NP && ST == kF32) {
         b.jout[n] = jx;
         b.jout[P + n] = jy;
@@ -104,22 +105,27 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     double acc[6] = {0, 0, 0, 0, 0, 0};
     double res[2] = {0, 0};
 
+    // coordinates and neighbour map values of the node
+    int x = 0, y = 0, z = 0;
+    int nb[Q];
+    bool edge = false;
     if (active) {
-        int x, y, z;
-        unpack_xyz(g, g.fluid[n], x, y, z);
+        unpack_xyz(g, ldu(g.fluid, (uint32_t)n), x, y, z);
         constexpr bool need_all = LBM && (ODD || ST != kF32);
-        const bool edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
+        edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
         NbCtx ctx;
         nb_ctx<L>(g, x, y, z, g.periodic_x, ctx);
-        int nb[Q];
         nb[0] = n;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
             nb[i] = want ? nb_get<L>(g, ctx, i) : kOutside;
         }
+    }
 
-        if (LBM) {
+    // the flow: collide and stream (and the residual terms on request)
+    {
+        if (LBM && active) {
             // a boundary node with a fluid interior neighbour is advanced by that neighbour
             const bool by_partner = edge && ((x == 0 && nb[1] >= 0) || (x == g.nx - 1 && nb[2] >= 0));
             if (!by_partner) {
@@ -142,13 +148,25 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 }
             }
         }
+    }
+    if (LBM && (b.flags & kResid)) {
+        double s[2];
+        block_sum<2>(res, sm, s);
+        if (threadIdx.x == 0) {
+            b.resid[2 * (size_t)tile] = s[0];
+            b.resid[2 * (size_t)tile + 1] = s[1];
+        }
+        __syncthreads();
+    }
 
-        if (NP) {
+    // the ions: face fluxes of the explicit finite-volume update
+    {
+        if (NP && active) {
             const float cP[2] = {b.Cin[n], b.Cin[P + n]};
             float jP[3];
             const bool jm = ST != kF32 && (b.flags & kJFromM);
             if (jm) {
-                const float4 m = b.Min[n];
+                const float4 m = ldu(b.Min, (uint32_t)n);
                 const float r = 1.f + m.x;
                 jP[0] = r * m.y;
                 jP[1] = r * m.z;
@@ -158,7 +176,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 jP[1] = b.jin[P + n];
                 jP[2] = D == 3 ? b.jin[2 * P + n] : 0.f;
             }
-            const float psiP = p.psi ? p.psi[n] : 0.f;
+            const float psiP = p.psi ? ldu(p.psi, (uint32_t)n) : 0.f;
             float out[2] = {0.f, 0.f}, fa[2] = {0.f, 0.f}, fi[2] = {0.f, 0.f}, fo[2] = {0.f, 0.f};
 #pragma unroll
             for (int k = 0; k < 2 * D; ++k) {
@@ -205,13 +223,13 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 } else if (m >= 0) {
                     float jN;
                     if (jm) {
-                        const float4 mm = b.Min[m];
+                        const float4 mm = ldu(b.Min, (uint32_t)m);
                         jN = (1.f + mm.x) * (axis == 0 ? mm.y : (axis == 1 ? mm.z : mm.w));
                     } else {
                         jN = b.jin[axis * P + m];
                     }
                     const float un = 0.5f * (jP[axis] + jN) * sg;
-                    const float dpsi = p.psi ? p.psi[m] - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
+                    const float dpsi = p.psi ? ldu(p.psi, (uint32_t)m) - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
                         const float w = un - p.z[s] * p.D[s] * dpsi;
@@ -238,15 +256,6 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
             double *a = b.acc + (size_t)tile * 8;
 #pragma unroll
             for (int k = 0; k < 6; ++k) a[k] += s[k];
-        }
-        __syncthreads();
-    }
-    if (LBM && (b.flags & kResid)) {
-        double s[2];
-        block_sum<2>(res, sm, s);
-        if (threadIdx.x == 0) {
-            b.resid[2 * (size_t)tile] = s[0];
-            b.resid[2 * (size_t)tile + 1] = s[1];
         }
         __syncthreads();
     }
@@ -312,8 +321,8 @@ void launch_batch_t(int cls, const BatchInst *inst, const int2 *tiles, int ntile
 template <class L, int ST, int ODD, int LBM, int NP>
 void launch_t(const Grid &g, const Phys &p, const Bufs &b, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)(g.P / kTile);
-    step_kernel<L, ST, ODD, LBM, NP><<<blocks, kTile, (size_t)g.lds_pad, s>>>(g, p, b);
+    const unsigned T = (unsigned)(g.P / kTile);
+    step_kernel<L, ST, ODD, LBM, NP><<<T, kTile, (size_t)g.lds_pad, s>>>(g, p, b);
 }
 
 template <class L, int ST, int ODD>
