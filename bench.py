@@ -19,7 +19,6 @@ bounded sample (the seeded 64^3 sub-case).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,17 +38,11 @@ BYTES_LBM = {"fp32": 19 * 4 * 2, "fp16_dev": 19 * 2 * 2 + 32, "moments": 32}
 BYTES_NP = 16 + 12  # C read + write, frozen j read
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for name in ("step.hip", "device_common.h", "cdi_internal.h"):
-        with open(os.path.join(ROOT, "paper_2110_13055_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kind: str):
-    """HBM bytes per fused-step launch from the committed counter summary, if
-    it was taken on the current kernel source; else None."""
+    """HBM bytes per fused-step launch (mean of the even and odd kernels) from
+    the committed counter summary, if it was taken on the current kernel
+    source; else None."""
+    from paper_2110_13055_amd.profile_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "step_kernel_spheres3d_512_traffic.json")
     if not os.path.exists(path):
         return None
@@ -57,7 +50,8 @@ def measured_traffic(kind: str):
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch", {}).get(kind)
+    v = rec.get("bytes_per_launch", {}).get(kind)
+    return None if v is None else round(v)
 
 
 def time_region(fn, stream):
@@ -174,7 +168,7 @@ def cpu_baseline(budget_s: float = 12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")

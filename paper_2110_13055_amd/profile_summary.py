@@ -1,0 +1,162 @@
+"""Summarise rocprofv3 runs of bench.py into the committed profile record.
+
+    python -m paper_2110_13055_amd.profile_summary \\
+        --trace DIR --fetch DIR --write DIR --bench-log FILE --copy-mib 1024 \\
+        --md OUT.md --json OUT.json [--command TEXT ...]
+
+Inputs are the CSV directories of three rocprofv3 runs of the same bench
+command (``--kernel-trace --stats``, ``--pmc FETCH_SIZE``, ``--pmc
+WRITE_SIZE``, all with ``--output-format csv``) and the bench's own stdout
+(for the fluid-node count). The bench command must include
+``--copy-probe-mib N``: one device-to-device copy of N MiB, whose counter
+readings give the scale from each counter to bytes (a copy reads and writes
+exactly N MiB).
+
+Output: a Markdown table per step-kernel variant (average duration, HBM
+bytes per launch and per fluid node from the counters, achieved GB/s) and a
+JSON record that bench.py reads for ``roofline.traffic`` (ignored once the
+kernel sources change: the record carries their hash).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("step.hip", "device_common.h", "cdi_internal.h")
+STORAGE = {"0": "fp32", "1": "fp16_dev", "2": "moments"}
+
+
+def kernel_source_hash() -> str:
+    """Hash of the step kernel's sources (a profile is valid for these only)."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _variant(name: str):
+    """step_kernel<L, ST, ODD, LBM, NP> -> readable label, or None."""
+    m = re.search(r"step_kernel<cdi::(D2Q9|D3Q19), (\d), (\d), (\d), (\d)>", name)
+    if not m:
+        return None
+    lat, st, odd, lbm, np_ = m.groups()
+    kind = "fused" if lbm == "1" and np_ == "1" else ("lbm" if lbm == "1" else "np")
+    # ion-only steps and moment storage have no AA parity
+    parity = "" if kind == "np" or st == "2" else (" odd" if odd == "1" else " even")
+    return f"{lat} {STORAGE[st]} {kind}{parity}"
+
+
+def _csv(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d, suffix):
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def _counters(d, counter):
+    """Per-variant mean counter value per dispatch, and the copy probe's value."""
+    per = defaultdict(list)
+    copy = None
+    for r in _csv(_find(d, "counter_collection.csv")):
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        if "copyBuffer" in r["Kernel_Name"]:
+            if copy is None or v > copy:
+                copy = v  # the probe is the largest copy of the run
+            continue
+        k = _variant(r["Kernel_Name"])
+        if k:
+            per[k].append(v)
+    return {k: sum(v) / len(v) for k, v in per.items()}, copy
+
+
+def summarise(trace, fetch, write, bench_log, copy_mib, commands=()):
+    stats = {}
+    for r in _csv(_find(trace, "kernel_stats.csv")):
+        k = _variant(r["Name"])
+        if k:
+            stats[k] = (int(r["Calls"]), float(r["AverageNs"]) * 1e-9)
+    n_fluid = None
+    with open(bench_log) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"n_fluid"' in line:
+                n_fluid = json.loads(line)["config"]["n_fluid"]
+    if n_fluid is None:
+        raise ValueError("bench log holds no result line with config.n_fluid")
+    fr, fcopy = _counters(fetch, "FETCH_SIZE")
+    wr, wcopy = _counters(write, "WRITE_SIZE")
+    copy_bytes = copy_mib * 1024.0 * 1024.0
+    fscale = copy_bytes / fcopy  # bytes per counter unit
+    wscale = copy_bytes / wcopy
+    rows = []
+    for k in sorted(stats):
+        calls, dur = stats[k]
+        fb = fr.get(k, float("nan")) * fscale
+        wb = wr.get(k, float("nan")) * wscale
+        rows.append(dict(kernel=k, calls=calls, avg_ms=dur * 1e3, read_bytes=fb, write_bytes=wb,
+                         read_per_node=fb / n_fluid, write_per_node=wb / n_fluid,
+                         gbs=(fb + wb) / dur / 1e9))
+    # bytes per launch of a whole step (even and odd launches alternate)
+    per_launch = {}
+    for st in STORAGE.values():
+        for kind in ("fused", "lbm"):
+            pair = [r for r in rows if r["kernel"].split()[1:3] == [st, kind]]
+            if pair:
+                per_launch.setdefault(st, {})[kind] = sum(r["read_bytes"] + r["write_bytes"]
+                                                         for r in pair) / len(pair)
+    record = dict(kernel_source_hash=kernel_source_hash(), n_fluid=n_fluid,
+                  counter_scale={"FETCH_SIZE": fscale, "WRITE_SIZE": wscale},
+                  bytes_per_launch={st: v.get("fused") for st, v in per_launch.items()},
+                  lbm_bytes_per_launch={st: v.get("lbm") for st, v in per_launch.items()},
+                  kernels=rows, commands=list(commands))
+    md = [f"# Step kernels on the 512^3 electrode ({n_fluid} fluid nodes)", "",
+          f"Kernel source hash: `{record['kernel_source_hash']}`.", "",
+          "Counter scale from the copy probe (one device-to-device copy of "
+          f"{copy_mib} MiB, which reads and writes exactly that much): FETCH_SIZE x {fscale:.1f} B, "
+          f"WRITE_SIZE x {wscale:.1f} B per unit.", "",
+          "| kernel | calls | avg ms | HBM read B/node | HBM write B/node | achieved GB/s |",
+          "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        md.append(f"| {r['kernel']} | {r['calls']} | {r['avg_ms']:.3f} | {r['read_per_node']:.1f} | "
+                  f"{r['write_per_node']:.1f} | {r['gbs']:.0f} |")
+    md += ["", "Commands (repository root; the three runs of the same bench command):", ""]
+    md += [f"    {c}" for c in commands]
+    return record, "\n".join(md) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--bench-log", required=True)
+    ap.add_argument("--copy-mib", type=int, required=True)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--json", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    a = ap.parse_args()
+    rec, md = summarise(a.trace, a.fetch, a.write, a.bench_log, a.copy_mib, a.command)
+    with open(a.json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    with open(a.md, "w") as fh:
+        fh.write(md)
+
+
+if __name__ == "__main__":
+    main()
