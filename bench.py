@@ -66,10 +66,10 @@ def time_region(fn, stream):
     return e0.elapsed_time(e1) / 1e3
 
 
-def gpu_rates(precision: int, steps: int, warmup: int):
+def gpu_rates(precision: int, steps: int, warmup: int, streaming: int):
     import torch
     import paper_2110_13055_amd as P
-    g, p, _ = P.preset(WORKLOAD, precision=precision)
+    g, p, _ = P.preset(WORKLOAD, precision=precision, streaming=streaming)
     s = P.Solver(g, p)
     nf = s.n_fluid
     stream = s.stream
@@ -86,7 +86,7 @@ def gpu_rates(precision: int, steps: int, warmup: int):
     return res
 
 
-def batched_rates(steps: int, n: int = 64):
+def batched_rates(steps: int, streaming: int, n: int = 64):
     """Batched stepping of n uneven instances (cubes of edge 48-160, own seed,
     porosity, potential and inlet velocity): the fused step of all instances
     in one persistent launch per step (graph-replayed, grid size autotuned),
@@ -95,7 +95,7 @@ def batched_rates(steps: int, n: int = 64):
     import paper_2110_13055_amd as P
     out = {"instances": n}
     for prec, name in ((P.FP32, "fp32"), (P.FP16_DEV, "fp16_dev"), (P.MOMENTS, "moments")):
-        specs = P.batch_instances(n, precision=prec)
+        specs = P.batch_instances(n, precision=prec, streaming=streaming)
         solvers = [P.Solver(g, p) for g, p in specs]
         nf = sum(s.n_fluid for s in solvers)
         out["n_fluid_total"] = nf
@@ -121,13 +121,13 @@ def batched_rates(steps: int, n: int = 64):
     return out
 
 
-def serving_run(n_requests: int, precision: int, slots: int):
+def serving_run(n_requests: int, precision: int, slots: int, streaming: int):
     """Serve a fixed Poisson trace (2 requests/s, half 2D 256^2, half 3D
     64^3-192^3) with a 200 GB admission budget and the given slot count."""
     import torch
     import paper_2110_13055_amd as P
     from paper_2110_13055_amd.serving import GpuExecutor, Server, latency_stats
-    reqs = P.serving_requests(n_requests, precision=precision)
+    reqs = P.serving_requests(n_requests, precision=precision, streaming=streaming)
     ex = GpuExecutor()
     srv = Server(ex, budget_bytes=200e9, max_slots=slots, round_steps=500)
     t0 = time.perf_counter()
@@ -171,6 +171,8 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
+    ap.add_argument("--streaming", choices=("pull", "aa"), default="pull",
+                    help="population streaming of the FP32 / FP16 forms")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the serving trace (0 skips the serving leg)")
@@ -194,9 +196,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    r32 = gpu_rates(P.FP32, args.steps, args.warmup)
-    r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup)
-    rmo = gpu_rates(P.MOMENTS, args.steps, args.warmup)
+    strm = P.STREAM_PULL if args.streaming == "pull" else P.STREAM_AA
+    r32 = gpu_rates(P.FP32, args.steps, args.warmup, strm)
+    r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup, strm)
+    rmo = gpu_rates(P.MOMENTS, args.steps, args.warmup, strm)
     nf = r32["n_fluid"]
     K = args.steps
 
@@ -229,7 +232,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "lattice": "D3Q19 512^3", "porosity": 0.4,
-                   "n_fluid": nf, "storage": "fp32", "step": "fused LBM+NP"},
+                   "n_fluid": nf, "storage": "fp32", "streaming": args.streaming,
+                   "step": "fused LBM+NP"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
@@ -240,12 +244,12 @@ def main():
         "device": torch.cuda.get_device_name(0),
     }
     if not args.no_batch:
-        out["batched"] = batched_rates(K)
+        out["batched"] = batched_rates(K, strm)
     if args.serve_requests > 0:
         sv = {"requests": args.serve_requests, "rate_hz": 2.0, "budget_gb": 200}
-        sv["continuous_batching_moments"] = serving_run(args.serve_requests, P.MOMENTS, 64)
-        sv["continuous_batching_fp32"] = serving_run(args.serve_requests, P.FP32, 64)
-        sv["plain_fp32_one_at_a_time"] = serving_run(args.serve_requests, P.FP32, 1)
+        sv["continuous_batching_moments"] = serving_run(args.serve_requests, P.MOMENTS, 64, strm)
+        sv["continuous_batching_fp32"] = serving_run(args.serve_requests, P.FP32, 64, strm)
+        sv["plain_fp32_one_at_a_time"] = serving_run(args.serve_requests, P.FP32, 1, strm)
         out["serving"] = sv
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

@@ -53,6 +53,7 @@ enum { CDI_INLET_OUTLET = 0, CDI_BODY_FORCE = 1 };
 enum { CDI_EQ_QUADRATIC = 0, CDI_EQ_LINEAR = 1 };
 enum { CDI_NPX_INLET_OUTLET = 0, CDI_NPX_PERIODIC = 1, CDI_NPX_CLOSED = 2, CDI_NPX_DIRICHLET = 3 };
 enum { CDI_FP32 = 0, CDI_FP16_DEV = 1, CDI_MOMENTS = 2 };
+enum { CDI_STREAM_AA = 0, CDI_STREAM_PULL = 1 };
 
 /*
  * Electrode geometry (Sec. 2: every grid block is one image voxel; Sec. 4-5:
@@ -112,6 +113,14 @@ typedef struct {
  *                equilibrium (Eq. 8 with f* = f_eq), so the FP16 deviations
  *                are identically zero and this is CDI_FP16_DEV without them,
  *                bit for bit
+ *   streaming    how populations move between steps (FP32 and FP16 storage;
+ *                the results are identical):
+ *                CDI_STREAM_AA: one array updated in place, alternating a
+ *                step that reads and writes each node's own slots with one
+ *                that reads and writes its neighbours' slots;
+ *                CDI_STREAM_PULL: two arrays; every step gathers from the
+ *                neighbours' slots of one and writes the node's own slots of
+ *                the other (twice the population memory, no scattered stores)
  */
 typedef struct {
     double tau;
@@ -126,6 +135,7 @@ typedef struct {
     int32_t np_x_bc;
     int32_t np_substeps;
     int32_t precision;
+    int32_t streaming;
 } cdi_params;
 
 /* Sizes reported by cdi_plan. */
@@ -235,6 +245,9 @@ typedef struct {
                               8 XCDs, so the 8 layers at one (x, y) are processed together (the
                               layers above and below a tile meet in the memory-side cache);
                               takes precedence over band_rows. 0: off */
+    int32_t nbr_list;      /* 1: read each node's neighbours from a list built at init (4 (Q-1) bytes
+                              per node of extra reads) instead of looking them up through the voxel
+                              map after the node's coordinates; 0: map lookups */
 } cdi_tuning;
 
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t);

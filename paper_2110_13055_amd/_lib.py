@@ -18,6 +18,7 @@ INLET_OUTLET, BODY_FORCE = 0, 1
 EQ_QUADRATIC, EQ_LINEAR = 0, 1
 NPX_INLET_OUTLET, NPX_PERIODIC, NPX_CLOSED, NPX_DIRICHLET = 0, 1, 2, 3
 FP32, FP16_DEV, MOMENTS = 0, 1, 2
+STREAM_AA, STREAM_PULL = 0, 1
 MODE_IDLE, MODE_FLOW, MODE_IONS, MODE_FUSED = 0, 1, 2, 3
 
 STATUS_NAMES = {
@@ -44,6 +45,7 @@ class CParams(C.Structure):
         ("c0", C.c_double), ("c_out", C.c_double), ("Ka", C.c_double), ("dpsi_vt", C.c_double),
         ("psi_field", C.c_void_p),
         ("np_x_bc", C.c_int32), ("np_substeps", C.c_int32), ("precision", C.c_int32),
+        ("streaming", C.c_int32),
     ]
 
 
@@ -65,7 +67,8 @@ class CSolverInfo(C.Structure):
 
 
 class CTuning(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int32), ("band_rows", C.c_int32), ("columns", C.c_int32)]
+    _fields_ = [("blocks_per_cu", C.c_int32), ("band_rows", C.c_int32), ("columns", C.c_int32),
+                ("nbr_list", C.c_int32)]
 
 
 P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double

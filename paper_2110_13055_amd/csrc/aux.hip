@@ -72,6 +72,19 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
     }
 }
 
+template <class L>
+__global__ __launch_bounds__(256) void build_nbr_kernel(Grid g, int *nbr)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.n_f) return;
+    int x, y, z;
+    unpack_xyz(g, g.fluid[n], x, y, z);
+    NbCtx c;
+    nb_ctx<L>(g, x, y, z, g.periodic_x, c);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) nbr[(size_t)(i - 1) * g.P + n] = nb_get<L>(g, c, i);
+}
+
 __global__ void tile_heads_kernel(Grid g, uint32_t *heads)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,6 +213,17 @@ __global__ __launch_bounds__(kTile) void stability_kernel(Grid g, Phys p, const 
 
 }  // namespace
 
+hipError_t launch_build_nbr(int dim, const Grid &g, int *nbr, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((g.n_f + 255) / 256);
+    if (blocks == 0) return hipSuccess;
+    if (dim == 2)
+        build_nbr_kernel<D2Q9><<<blocks, 256, 0, s>>>(g, nbr);
+    else
+        build_nbr_kernel<D3Q19><<<blocks, 256, 0, s>>>(g, nbr);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_heads(const Grid &g, uint32_t *heads, hipStream_t s)
 {
     const int tiles = g.P / kTile;
@@ -218,9 +242,9 @@ void launch_moments_l(int st, int odd, unsigned blocks, int nee, const Grid &g, 
     if (st == kMom)
         MK(kMom, 0);
     else if (st == kF16)
-        odd ? MK(kF16, 1) : MK(kF16, 0);
+        odd == kPull ? MK(kF16, kPull) : odd ? MK(kF16, 1) : MK(kF16, 0);
     else
-        odd ? MK(kF32, 1) : MK(kF32, 0);
+        odd == kPull ? MK(kF32, kPull) : odd ? MK(kF32, 1) : MK(kF32, 0);
 #undef MK
 }
 

@@ -102,6 +102,8 @@ int check_params(const cdi_params *p)
     if (p->np_substeps < 1) return fail(CDI_E_INVALID, "np_substeps must be >= 1");
     if (p->precision != CDI_FP32 && p->precision != CDI_FP16_DEV && p->precision != CDI_MOMENTS)
         return fail(CDI_E_INVALID, "bad precision");
+    if (p->streaming != CDI_STREAM_AA && p->streaming != CDI_STREAM_PULL)
+        return fail(CDI_E_INVALID, "bad streaming");
     if (p->precision == CDI_MOMENTS && (p->tau != 1.0 || p->drive == CDI_BODY_FORCE))
         return fail(CDI_E_INVALID, "moment storage needs tau = 1 and no body force "
                                    "(only then is the post-collision state the local equilibrium)");
@@ -200,6 +202,7 @@ VoxLayout vox_layout(void *ws, const cdi_geometry *g, int64_t nprims)
 
 struct NodeLayout {
     void *f;
+    void *f2;    // pull streaming: the second population array
     float4 *M[2];
     float *j[2];
     float *ubuf;
@@ -209,6 +212,7 @@ struct NodeLayout {
     float *psi;   // prescribed potential in internal node order
     double *acc, *resid, *part, *red;
     int *sched;
+    int *nbr;    // neighbour list (Q-1 planes of P), built once
     void *base;  // start of the state a checkpoint carries (state_bytes from here)
     uint64_t state_bytes, bytes;
 };
@@ -216,7 +220,7 @@ struct NodeLayout {
 // Bytes per stored population of a storage kind.
 static int pop_bytes(int st) { return st == kF32 ? 4 : st == kF16 ? 2 : 0; }
 
-static NodeLayout node_layout(void *ws, int dim, int st, int64_t P, int64_t plane)
+static NodeLayout node_layout(void *ws, int dim, int st, int pull, int64_t P, int64_t plane)
 {
     const int Q = dim == 2 ? 9 : 19;
     const int64_t ntiles = P / kTile;
@@ -225,6 +229,8 @@ static NodeLayout node_layout(void *ws, int dim, int st, int64_t P, int64_t plan
     NodeLayout L;
     L.base = ws;
     L.f = c.take<void>((uint64_t)Q * P * pop_bytes(st));
+    L.f2 = c.take<void>(pull ? (uint64_t)Q * P * pop_bytes(st) : 0);
+    if (!pull || st == kMom) L.f2 = nullptr;
     L.M[0] = c.take<float4>(mb ? 16ull * P : 0);
     L.M[1] = c.take<float4>(mb ? 16ull * P : 0);
     if (!mb) L.M[0] = L.M[1] = nullptr;
@@ -243,6 +249,7 @@ static NodeLayout node_layout(void *ws, int dim, int st, int64_t P, int64_t plan
     L.red = c.take<double>(64 * 8);
     L.state_bytes = c.off;  // everything a checkpoint must carry ends here
     L.sched = c.take<int>(4ull * ntiles);
+    L.nbr = c.take<int>(4ull * (Q - 1) * P);
     L.bytes = c.off;
     return L;
 }
@@ -253,17 +260,18 @@ struct cdi_solver {
     cdi_geometry geom;
     cdi_params params;
     int dim, Q, inout;
-    int st;  // storage: kF32, kF16 or kMom
+    int st;    // storage: kF32, kF16 or kMom
+    int pull;  // pull streaming (two population arrays; fcur holds the state)
     int mb;  // moment buffers in use (kF16, kMom): j of a fused step lives in them
     int64_t nvox, nf;
     int P, ntiles;
     hipStream_t stream;
     VoxLayout vox;
     NodeLayout node;
-    int parity = 0, mcur = 0, jcur = 0, ccur = 0, jstate = J_INVALID;
+    int parity = 0, fcur = 0, mcur = 0, jcur = 0, ccur = 0, jstate = J_INVALID;
     int64_t flow_steps = 0, np_steps = 0;
     double ka, keff[2], porosity;
-    cdi_tuning tuning{0, 0, 0};
+    cdi_tuning tuning{0, 0, 0, 0};
     Grid g;
     Phys p;
 };
@@ -272,16 +280,21 @@ namespace {
 
 struct SnapHeader {
     uint64_t magic, bytes;
-    int32_t parity, mcur, jcur, ccur, jstate, pad;
+    int32_t parity, mcur, jcur, ccur, jstate, fcur;
     int64_t flow_steps, np_steps, nf;
 };
 constexpr uint64_t kSnapMagic = 0x43444931534e4150ull;
+
+// Population array holding the state, and the kernels' parity argument.
+void *cur_pops(const cdi_solver *s) { return s->pull && s->fcur ? s->node.f2 : s->node.f; }
+int stream_arg(const cdi_solver *s) { return s->pull ? kPull : s->parity; }
 
 // Buffers of the next step of s (current double-buffer halves).
 Bufs make_bufs(const cdi_solver *s, int flags)
 {
     Bufs b{};
-    b.f = s->node.f;
+    b.f = cur_pops(s);
+    b.f2 = s->pull ? (s->fcur ? s->node.f : s->node.f2) : nullptr;
     if (s->mb) {
         b.Min = s->node.M[s->mcur];
         b.Mout = s->node.M[s->mcur ^ 1];
@@ -302,6 +315,7 @@ void advance_state(cdi_solver *s, int lbm, int np)
 {
     if (lbm) {
         s->parity ^= 1;
+        if (s->pull) s->fcur ^= 1;
         if (s->mb) s->mcur ^= 1;
         if (np && !s->mb) s->jcur ^= 1;
         s->flow_steps++;
@@ -312,7 +326,7 @@ void advance_state(cdi_solver *s, int lbm, int np)
 int step_once(cdi_solver *s, int lbm, int np, int flags)
 {
     const Bufs b = make_bufs(s, flags);
-    HIPCHK(launch_step(s->dim, s->st, s->parity, lbm, np, s->g, s->p, b, s->stream));
+    HIPCHK(launch_step(s->dim, s->st, stream_arg(s), lbm, np, s->g, s->p, b, s->stream));
     advance_state(s, lbm, np);
     return CDI_OK;
 }
@@ -323,7 +337,7 @@ int ensure_j(cdi_solver *s)
     if (s->jstate == J_IN_M) {
         HIPCHK(launch_j_from_m(s->dim, s->g, s->node.M[s->mcur], s->node.j[s->jcur], s->stream));
     } else {
-        HIPCHK(launch_moments(s->dim, s->st, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+        HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
                               s->mb ? s->node.M[s->mcur] : nullptr, nullptr, nullptr,
                               s->node.j[s->jcur], s->stream));
     }
@@ -494,9 +508,10 @@ int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *
     out->vox_bytes = vox_layout(nullptr, geom, nprims).bytes;
     const int dim = geom->dim;
     const int st = params ? params->precision : CDI_FP32;
+    const int pull = params ? params->streaming == CDI_STREAM_PULL : 0;
     const int Q = dim == 2 ? 9 : 19;
-    out->node_bytes_per_fluid =
-        (uint64_t)Q * pop_bytes(st) + (st != kF32 ? 32 : 0) + 12ull * dim + 16 + 4ull * (1 + dim) + 1;
+    out->node_bytes_per_fluid = (uint64_t)Q * pop_bytes(st) * (pull ? 2 : 1) + (st != kF32 ? 32 : 0) +
+                                12ull * dim + 16 + 4ull * (1 + dim) + 4ull * (Q - 1) + 1;
     g_err[0] = 0;
     return CDI_OK;
 }
@@ -548,7 +563,8 @@ int cdi_node_bytes(const cdi_geometry *geom, const cdi_params *params, int64_t n
     if ((rc = check_params(params)) != CDI_OK) return rc;
     if (!bytes || n_fluid <= 0) return fail(CDI_E_INVALID, "bad n_fluid or bytes pointer");
     const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
-    *bytes = node_layout(nullptr, geom->dim, params->precision == CDI_FP16_DEV, P, (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz)).bytes;
+    *bytes = node_layout(nullptr, geom->dim, params->precision, params->streaming == CDI_STREAM_PULL, P,
+                         (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz)).bytes;
     return CDI_OK;
 }
 
@@ -580,7 +596,8 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     // per-node arrays are addressed with 32-bit byte offsets (16-byte moments)
     if (P * (st_kind == kF32 ? 4 : 16) > 4294967295LL)
         return fail(CDI_E_INVALID, "too many fluid nodes for one instance (limit 2^30, 2^28 with moment buffers)");
-    NodeLayout N = node_layout(node_ws, geom->dim, st_kind, P, (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz));
+    NodeLayout N = node_layout(node_ws, geom->dim, st_kind, params->streaming == CDI_STREAM_PULL, P,
+                               (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz));
     if (node_ws_bytes < N.bytes) return fail(CDI_E_BUFFER, "node_ws too small: %llu < %llu",
                                              (unsigned long long)node_ws_bytes, (unsigned long long)N.bytes);
     if (params->np_x_bc != CDI_NPX_PERIODIC && params->np_x_bc != CDI_NPX_CLOSED && geom->nx < 2)
@@ -595,6 +612,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     s->Q = geom->dim == 2 ? 9 : 19;
     s->st = st_kind;
     s->mb = st_kind != kF32;
+    s->pull = params->streaming == CDI_STREAM_PULL && st_kind != kMom;
     s->inout = params->drive == CDI_INLET_OUTLET;
     s->nvox = nvox;
     s->nf = n_fluid;
@@ -619,6 +637,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     g.fluid = V.ifluid;
     g.map = V.imap;
     g.sched = nullptr;
+    g.nbr = nullptr;
     g.lds_pad = 0;
     Phys &p = s->p;
     p.omega = (float)(1.0 / params->tau);
@@ -651,10 +670,12 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     // rest state: f - w_i = 0 (FP32) / zero deviations and zero moments (FP16, moments)
     if (s->mb) {
         if (s->st == kF16) chk(launch_fill_u32((uint32_t *)N.f, 0u, (int64_t)s->Q * P / 2, st));
+        if (s->st == kF16 && s->pull) chk(launch_fill_u32((uint32_t *)N.f2, 0u, (int64_t)s->Q * P / 2, st));
         chk(launch_fill_f32((float *)N.M[0], 0.f, 4 * P, st));
         chk(launch_fill_f32((float *)N.M[1], 0.f, 4 * P, st));
     } else {
         chk(launch_fill_f32((float *)N.f, 0.f, (int64_t)s->Q * P, st));
+        if (s->pull) chk(launch_fill_f32((float *)N.f2, 0.f, (int64_t)s->Q * P, st));
     }
     chk(launch_fill_f32(N.j[0], 0.f, (int64_t)s->dim * P, st));
     chk(launch_fill_f32(N.j[1], 0.f, (int64_t)s->dim * P, st));
@@ -665,6 +686,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     chk(launch_fill_f32(N.C[1], (float)params->c0, 2 * P, st));
     chk(launch_fill_f64(N.acc, 0.0, 8ll * s->ntiles, st));
     chk(launch_fill_f64(N.resid, 0.0, 2ll * s->ntiles, st));
+    chk(launch_build_nbr(s->dim, g, N.nbr, st));
     if (err == CDI_OK) err = build_schedule(s, 0, 0);  // bricks already give locality
     if (err != CDI_OK) {
         delete s;
@@ -826,7 +848,7 @@ int cdi_copy_fluid_index(cdi_solver *s, int32_t *map, int32_t *fluid)
 int cdi_copy_velocity(cdi_solver *s, float *u)
 {
     if (!s || !u) return fail(CDI_E_INVALID, "NULL argument");
-    HIPCHK(launch_moments(s->dim, s->st, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+    HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
                           s->mb ? s->node.M[s->mcur] : nullptr, nullptr, s->node.tmp, nullptr, s->stream));
     return planes_d2h(s, u, s->node.tmp, s->dim);
 }
@@ -834,7 +856,7 @@ int cdi_copy_velocity(cdi_solver *s, float *u)
 int cdi_copy_density(cdi_solver *s, float *rho)
 {
     if (!s || !rho) return fail(CDI_E_INVALID, "NULL argument");
-    HIPCHK(launch_moments(s->dim, s->st, s->parity, s->flow_steps > 0, s->g, s->p, s->node.f,
+    HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
                           s->mb ? s->node.M[s->mcur] : nullptr, s->node.tmp, nullptr, nullptr, s->stream));
     return planes_d2h(s, rho, s->node.tmp, 1);
 }
@@ -879,7 +901,7 @@ int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes)
 {
     if (!s || !host) return fail(CDI_E_INVALID, "NULL argument");
     if (bytes < sizeof(SnapHeader) + s->node.state_bytes) return fail(CDI_E_BUFFER, "snapshot buffer too small");
-    SnapHeader h{kSnapMagic, s->node.state_bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, 0,
+    SnapHeader h{kSnapMagic, s->node.state_bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, s->fcur,
                  s->flow_steps, s->np_steps, s->nf};
     std::memcpy(host, &h, sizeof h);
     return d2h(s, (uint8_t *)host + sizeof h, s->node.base, s->node.state_bytes);
@@ -897,6 +919,7 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
     int rc = h2d(s, s->node.base, (const uint8_t *)host + sizeof h, s->node.state_bytes);
     if (rc) return rc;
     s->parity = h.parity;
+    s->fcur = h.fcur;
     s->mcur = h.mcur;
     s->jcur = h.jcur;
     s->ccur = h.ccur;
@@ -908,7 +931,8 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
 
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t)
 {
-    if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0 || t->columns < 0 || t->columns > 1)
+    if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0 || t->columns < 0 || t->columns > 1 ||
+        t->nbr_list < 0 || t->nbr_list > 1)
         return fail(CDI_E_INVALID, "bad tuning");
     int pad = 0;
     int rc = occupancy_pad(t->blocks_per_cu, &pad);
@@ -917,6 +941,8 @@ int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t)
         ((t->band_rows > 0 || t->columns) && !s->g.sched))
         if ((rc = build_schedule(s, t->band_rows, t->columns)) != CDI_OK) return rc;
     s->g.lds_pad = pad;
+    s->g.nbr = t->nbr_list ? s->node.nbr : nullptr;
+    s->tuning.nbr_list = t->nbr_list;
     s->tuning.blocks_per_cu = t->blocks_per_cu;
     return CDI_OK;
 }
@@ -941,11 +967,12 @@ int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *c
     std::vector<cdi_tuning> cands;
     const int occ[] = {0, 2, 3, 4, 6};
     const int bands[] = {0, 8, 16, 32};
-    for (int k : occ) {
-        for (int r : bands)
-            if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r, 0});
-        if (s->dim == 3) cands.push_back(cdi_tuning{k, 0, 1});
-    }
+    for (int nl : {0, 1})
+        for (int k : occ) {
+            for (int r : bands)
+                if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r, 0, nl});
+            if (s->dim == 3) cands.push_back(cdi_tuning{k, 0, 1, nl});
+        }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1038,8 +1065,8 @@ int batch_workgroups(const cdi_batch *b, int count)
 int step_class(int mode, int odd)
 {
     switch (mode) {
-    case kModeFlow: return odd ? kClassFlowOdd : kClassFlowEven;
-    case kModeFused: return odd ? kClassFusedOdd : kClassFusedEven;
+    case kModeFlow: return odd == kPull ? kClassFlowPull : odd ? kClassFlowOdd : kClassFlowEven;
+    case kModeFused: return odd == kPull ? kClassFusedPull : odd ? kClassFusedOdd : kClassFusedEven;
     case kModeIons: return kClassIons;
     default: return -1;
     }
@@ -1068,7 +1095,7 @@ void fill_slot(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64
         I.g = s->g;
         I.p = s->p;
         I.b = make_bufs(s, batch_flags(s, modes[k], idx, nsteps, want_resid));
-        const int c = step_class(modes[k], s->parity);
+        const int c = step_class(modes[k], stream_arg(s));
         if (c >= 0) count[c] += s->ntiles;
     }
     int *beg = bt->cls_begin[slot];
@@ -1078,7 +1105,7 @@ void fill_slot(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64
     for (int c = 0; c < kClasses; ++c) pos[c] = beg[c];
     int2 *t = bt->htiles + (size_t)slot * bt->total_tiles;
     for (int k = 0; k < bt->n; ++k) {
-        const int c = step_class(modes[k], bt->m[k]->parity);
+        const int c = step_class(modes[k], stream_arg(bt->m[k]));
         if (c < 0) continue;
         for (int q = 0; q < bt->m[k]->ntiles; ++q) t[pos[c]++] = make_int2(k, q);
     }

@@ -100,6 +100,10 @@ struct Grid {
     // (band of rows, z) so the planes above and below a tile were visited
     // shortly before by the same XCD and are still in its L2.
     const int *sched;
+    // Optional neighbour list: map value of the neighbour of node n along
+    // direction i in nbr[(i - 1) * P + n] (i = 1 .. Q-1), so that a step reads
+    // it with the node's other data instead of after its coordinates.
+    const int *nbr;
     // dynamic LDS reserved per step workgroup: caps the workgroups resident
     // per CU (and so the working set the L2 must hold); 0 = no cap
     int lds_pad;
@@ -125,7 +129,8 @@ struct Phys {
 
 // Buffers of one step; multi-plane fields are P apart (structure of arrays).
 struct Bufs {
-    void *f;
+    void *f;        // populations: the array read (and, AA streaming, written)
+    void *f2;       // pull streaming: the array written
     const float4 *Min;
     float4 *Mout;
     const float *jin;
@@ -151,7 +156,10 @@ struct BatchInst {
 // Step classes of a batched step (kernel variants): LBM only or fused, by AA
 // parity, and ions only.
 constexpr int kClassFlowEven = 0, kClassFlowOdd = 1, kClassFusedEven = 2, kClassFusedOdd = 3,
-              kClassIons = 4, kClasses = 5;
+              kClassIons = 4, kClassFlowPull = 5, kClassFusedPull = 6, kClasses = 7;
+
+// Value of the kernels' parity argument for pull streaming (AA uses 0 / 1).
+constexpr int kPull = 2;
 
 // ------------------------------------------------------------ launchers
 // Every launcher enqueues on `stream` and returns hipGetLastError().
@@ -179,8 +187,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 
 // One LBM and/or Nernst-Planck step over all fluid nodes.
-//   dim 2/3, st = kF32/kF16/kMom, odd = AA parity of the stored state,
-//   lbm/np switches.
+//   dim 2/3, st = kF32/kF16/kMom, odd = AA parity of the stored state or
+//   kPull, lbm/np switches.
 hipError_t launch_step(int dim, int st, int odd, int lbm, int np, const Grid &g, const Phys &p,
                        const Bufs &b, hipStream_t s);
 // One step of the instances of one step class in one persistent launch of
@@ -194,6 +202,8 @@ hipError_t launch_moments(int dim, int st, int odd, int nee, const Grid &g, cons
                           const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s);
 // Packed coordinates of the first node of every tile (host-side tile schedule).
 hipError_t launch_tile_heads(const Grid &g, uint32_t *heads, hipStream_t s);
+// Neighbour list of every fluid node (see Grid::nbr), Q-1 planes of P.
+hipError_t launch_build_nbr(int dim, const Grid &g, int *nbr, hipStream_t s);
 // j = (1 + drho) u from the moments buffer (FP16 and moment storage).
 hipError_t launch_j_from_m(int dim, const Grid &g, const float4 *M, float *j, hipStream_t s);
 // Deterministic single-block sums: out[k] = sum_t in[t*stride + k], k < width.

@@ -17,6 +17,11 @@
 // (rho - 1, u) are kept in FP32. The emitter of f_i(x) is x - e_i if that
 // voxel is fluid, else x itself (which sent it in direction opp(i)).
 //
+// Pull streaming (ODD = kPull) keeps two arrays: a step reads f_i(x) from
+// node x - e_i, slot i of the input array when that voxel is fluid, else from
+// node x, slot opp(i) (its own reflected population), and writes f*_i into
+// node x, slot i of the output array.
+//
 // Moment storage keeps the moments alone: with tau = 1 and no body force the
 // BGK post-collision populations are exactly the equilibrium of the node's
 // moments (the FP16 deviations above are then identically zero), so f_i(x)
@@ -187,7 +192,9 @@ __device__ inline float gather(const void *F, int P, const int *nb, int n, int i
     const bool fl = (i != 0) && nb[j] >= 0;
     float raw = 0.f;
     if (ST != kMom) {
-        if (!ODD || i == 0 || !fl)
+        if (ODD == kPull)
+            raw = fl ? ld<ST == kF16>(F, P, i, nb[j]) : ld<ST == kF16>(F, P, j, n);
+        else if (!ODD || i == 0 || !fl)
             raw = ld<ST == kF16>(F, P, i, n);
         else
             raw = ld<ST == kF16>(F, P, j, nb[j]);
@@ -203,13 +210,15 @@ __device__ inline float gather(const void *F, int P, const int *nb, int n, int i
 }
 
 // Store the outgoing value of direction i (FP32: f* - w_i; FP16: scaled
-// deviation; moment storage: nothing).
+// deviation; moment storage: nothing). F: the array written.
 template <class L, int ST, int ODD>
 __device__ inline void scatter(void *F, int P, const int *nb, int n, int i, float v)
 {
     if (ST == kMom) return;
     constexpr bool H = ST == kF16;
-    if (!ODD || i == 0)
+    if (ODD == kPull)
+        st<H>(F, P, i, n, v);
+    else if (!ODD || i == 0)
         st<H>(F, P, L::opp[i], n, v);
     else if (nb[i] >= 0)
         st<H>(F, P, i, nb[i], v);
@@ -243,32 +252,30 @@ __device__ inline void nee_populations(const Phys &p, bool inlet, const float (&
                 (fc[i] - feq_bar<L>(i, dr, ux, uy, uz, p.linear_eq));
 }
 
-// Scharfetter-Gummel flux from P to N with normal drift w:
-// D [B(-Pe) C_P - B(Pe) C_N], B(x) = x / (e^x - 1), Pe = w / D. Written so
-// that the (N -> P) evaluation is the exact negative: both sides form the
-// same two products and subtract them in opposite order.
-// B(a) = a / (e^a - 1) for a >= 0. Below 0.5 its Taylor series in Bernoulli
-// numbers, 1 - a/2 + a^2/12 - a^4/720 + a^6/30240 (next term a^8/1209600 <
-// 4e-9 there); above, the closed form with the hardware exponential
-// (e^a - 1 >= 0.64, so no cancellation).
-__device__ inline float bern_pos(float a)
+// Scharfetter-Gummel flux from P to N with normal drift w, Pe = w / D:
+// D [B(-Pe) C_P - B(Pe) C_N], B(x) = x / (e^x - 1). With Bs(x) = B(x) + x/2 =
+// (x/2) coth(x/2), an even function, this is exactly
+//   D Bs(Pe) (C_P - C_N) + (w/2) (C_P + C_N):
+// a symmetric diffusive part and a central advective part, with no sign
+// cases. Seen from N the operands are C_P - C_N negated, the same C_P + C_N,
+// the same Pe^2 and w/2 negated, so the two cells of a face form exactly
+// opposite values. Bs needs only Pe^2: below |Pe| = 1/2 its series
+// 1 + x^2/12 - x^4/720 + x^6/30240 (next term below 3e-8 there), above the
+// closed form with the hardware exponential (e^|x| - 1 >= 0.64, no
+// cancellation). hw = w / 2, invD2 = 2 / D.
+__device__ inline float sg_flux(float D, float invD2, float hw, float cp, float cn)
 {
-    if (a < 0.5f) {
-        const float a2 = a * a;
-        return 1.f - 0.5f * a + a2 * (1.f / 12.f + a2 * (-1.f / 720.f + a2 * (1.f / 30240.f)));
+    const float pe = hw * invD2;
+    const float x2 = pe * pe;
+    float bs;
+    if (x2 < 0.25f) {
+        bs = fmaf(x2, fmaf(x2, fmaf(x2, 1.f / 30240.f, -1.f / 720.f), 1.f / 12.f), 1.f);
+    } else {
+        const float a = fabsf(pe);
+        const float e = __expf(a);
+        bs = 0.5f * a * (e + 1.f) * __builtin_amdgcn_rcpf(e - 1.f);
     }
-    return a * __builtin_amdgcn_rcpf(__expf(a) - 1.f);
-}
-
-__device__ inline float sg_flux(float D, float invD, float w, float cp, float cn)
-{
-    const float pe = w * invD;
-    const float a = fabsf(pe);
-    const float bp = bern_pos(a);                     // B(|Pe|)
-    const float bm = bp + a;                          // B(-|Pe|)
-    const float b_neg = pe >= 0.f ? bm : bp;          // B(-Pe)
-    const float b_pos = pe >= 0.f ? bp : bm;          // B(Pe)
-    return D * (__fmul_rn(b_neg, cp) - __fmul_rn(b_pos, cn));
+    return fmaf(D * bs, cp - cn, hw * (cp + cn));
 }
 
 // Sum over the block in a fixed order (wave shuffles, then the waves in

@@ -89,7 +89,7 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
             out = ((1.f - om) * (f[i] - fe) + src) * p.hs;
         else
             out = f[i] - om * (f[i] - fe) + src;
-        scatter<L, ST, ODD>(b.f, P, nb, n, i, out);
+        scatter<L, ST, ODD>(ODD == kPull ? b.f2 : b.f, P, nb, n, i, out);
     }
 }
 
@@ -113,13 +113,21 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         unpack_xyz(g, ldu(g.fluid, (uint32_t)n), x, y, z);
         constexpr bool need_all = LBM && (ODD || ST != kF32);
         edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
-        NbCtx ctx;
-        nb_ctx<L>(g, x, y, z, g.periodic_x, ctx);
         nb[0] = n;
+        if (g.nbr) {  // precomputed: independent of the coordinates
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
-            nb[i] = want ? nb_get<L>(g, ctx, i) : kOutside;
+            for (int i = 1; i < Q; ++i) {
+                const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
+                nb[i] = want ? ldu(g.nbr + (size_t)(i - 1) * P, (uint32_t)n) : kOutside;
+            }
+        } else {
+            NbCtx ctx;
+            nb_ctx<L>(g, x, y, z, g.periodic_x, ctx);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
+                nb[i] = want ? nb_get<L>(g, ctx, i) : kOutside;
+            }
         }
     }
 
@@ -177,6 +185,9 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 jP[2] = D == 3 ? b.jin[2 * P + n] : 0.f;
             }
             const float psiP = p.psi ? ldu(p.psi, (uint32_t)n) : 0.f;
+            // per species: 2/D, and (z D)/2 so that half the drift is hw = u/2 - (z D/2) dpsi
+            const float invD2[2] = {2.f * p.invD[0], 2.f * p.invD[1]};
+            const float hzD[2] = {0.5f * p.z[0] * p.D[0], 0.5f * p.z[1] * p.D[1]};
             float out[2] = {0.f, 0.f}, fa[2] = {0.f, 0.f}, fi[2] = {0.f, 0.f}, fo[2] = {0.f, 0.f};
 #pragma unroll
             for (int k = 0; k < 2 * D; ++k) {
@@ -191,20 +202,22 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                     if (sgi < 0) {  // inlet face: ghost at c0, inflow u_in
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
-                            const float w = -p.u_in - p.z[s] * p.D[s] * dpsi;
-                            const float F = sg_flux(p.D[s], p.invD[s], w, cP[s], p.c0);
+                            const float hw = -0.5f * p.u_in - hzD[s] * dpsi;
+                            const float F = sg_flux(p.D[s], invD2[s], hw, cP[s], p.c0);
                             out[s] += F;
                             fi[s] -= F;
                         }
                     } else {  // outlet face
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
-                            const float w = jP[0] - p.z[s] * p.D[s] * dpsi;
+                            const float hw = 0.5f * jP[0] - hzD[s] * dpsi;
                             float F;
-                            if (p.npx == kNpxDirichlet)
-                                F = sg_flux(p.D[s], p.invD[s], w, cP[s], p.c_out);
-                            else  // open: drift carries C_P out, or feed c0 in
+                            if (p.npx == kNpxDirichlet) {
+                                F = sg_flux(p.D[s], invD2[s], hw, cP[s], p.c_out);
+                            } else {  // open: drift carries C_P out, or feed c0 in
+                                const float w = 2.f * hw;
                                 F = fmaxf(w, 0.f) * cP[s] + fminf(w, 0.f) * p.c0;
+                            }
                             out[s] += F;
                             fo[s] += F;
                         }
@@ -228,12 +241,15 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                     } else {
                         jN = b.jin[axis * P + m];
                     }
-                    const float un = 0.5f * (jP[axis] + jN) * sg;
-                    const float dpsi = p.psi ? ldu(p.psi, (uint32_t)m) - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
+                    // half the face-normal drift: advection by the mean flux of the
+                    // two cells, migration down the potential difference
+                    const float hun = 0.25f * (jP[axis] + jN) * sg;
+                    const bool mig = p.psi || axis == 0;  // the ramp has no y/z gradient
+                    const float dpsi = p.psi ? ldu(p.psi, (uint32_t)m) - psiP : -sg * p.dpsi_dx;
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
-                        const float w = un - p.z[s] * p.D[s] * dpsi;
-                        out[s] += sg_flux(p.D[s], p.invD[s], w, cP[s], b.Cin[s * P + m]);
+                        const float hw = mig ? hun - hzD[s] * dpsi : hun;
+                        out[s] += sg_flux(p.D[s], invD2[s], hw, cP[s], b.Cin[s * P + m]);
                     }
                 }
                 // inert wall: no flux
@@ -308,12 +324,15 @@ void launch_batch_t(int cls, const BatchInst *inst, const int2 *tiles, int ntile
                     hipStream_t s)
 {
     const size_t lds = (size_t)pad;
-    constexpr int O1 = ST == kMom ? 0 : 1;  // moment storage has no AA parity
+    constexpr int O1 = ST == kMom ? 0 : 1;      // moment storage has no AA parity
+    constexpr int OP = ST == kMom ? 0 : kPull;  // nor streaming of populations
     switch (cls) {
     case kClassFlowEven: batch_kernel<L, ST, 0, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
     case kClassFlowOdd: batch_kernel<L, ST, O1, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFlowPull: batch_kernel<L, ST, OP, 1, 0><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
     case kClassFusedEven: batch_kernel<L, ST, 0, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
     case kClassFusedOdd: batch_kernel<L, ST, O1, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
+    case kClassFusedPull: batch_kernel<L, ST, OP, 1, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
     default: batch_kernel<L, kF32, 0, 0, 1><<<wg, kTile, lds, s>>>(inst, tiles, ntiles); break;
     }
 }
@@ -343,12 +362,16 @@ void launch_prec(int st, int odd, int lbm, int np, const Grid &g, const Phys &p,
     if (st == kMom) {
         launch_mode<L, kMom, 0>(lbm, np, g, p, b, s);
     } else if (st == kF16) {
-        if (odd)
+        if (odd == kPull)
+            launch_mode<L, kF16, kPull>(lbm, np, g, p, b, s);
+        else if (odd)
             launch_mode<L, kF16, 1>(lbm, np, g, p, b, s);
         else
             launch_mode<L, kF16, 0>(lbm, np, g, p, b, s);
     } else {
-        if (odd)
+        if (odd == kPull)
+            launch_mode<L, kF32, kPull>(lbm, np, g, p, b, s);
+        else if (odd)
             launch_mode<L, kF32, 1>(lbm, np, g, p, b, s);
         else
             launch_mode<L, kF32, 0>(lbm, np, g, p, b, s);

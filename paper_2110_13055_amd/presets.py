@@ -61,7 +61,7 @@ def preset(name: str, precision: int = L.FP32, **overrides):
 
 
 def batch_instances(n: int = 64, base_seed: int = BASE_SEED, precision: int = L.FP32,
-                    edge_range=(48, 160)):
+                    edge_range=(48, 160), streaming: int = L.STREAM_AA):
     """Independent 3D electrodes of uneven size for batched stepping: cubes
     with integer edge uniform on edge_range, overlapping spheres r in [3, 6],
     porosity U[0.35, 0.75], applied potential U[4, 40] thermal voltages,
@@ -76,13 +76,15 @@ def batch_instances(n: int = 64, base_seed: int = BASE_SEED, precision: int = L.
         u_in = float(rng.uniform(1e-4, 5e-3))
         g = Geometry(dim=3, nx=edge, ny=edge, nz=edge, kind=L.SPHERES, porosity=phi, r_min=3.0,
                      r_max=6.0, buffer_x=2, seed=base_seed + k)
-        out.append((g, Params(u_in=u_in, dpsi_vt=dpsi, D=(D_NA, D_CL), precision=precision)))
+        out.append((g, Params(u_in=u_in, dpsi_vt=dpsi, D=(D_NA, D_CL), precision=precision,
+                              streaming=streaming)))
     return out
 
 
 def serving_requests(n: int, rate_hz: float = 2.0, base_seed: int = BASE_SEED,
                      precision: int = L.FP32, np_steps_2d: int = 5000, np_steps_3d: int = 20000,
-                     flow_tol: float = 1e-8, flow_max_steps: int = 20000):
+                     flow_tol: float = 1e-8, flow_max_steps: int = 20000,
+                     streaming: int = L.STREAM_AA):
     """A fixed trace of mixed solve requests with Poisson arrivals: half are
     2D 256x256 D2Q9 channels (disks r in [4, 8], walls top/bottom, porosity
     U[0.55, 0.75], the range random sequential addition reaches), half 3D
@@ -108,7 +110,7 @@ def serving_requests(n: int, rate_hz: float = 2.0, base_seed: int = BASE_SEED,
             g = Geometry(dim=2, nx=256, ny=256, kind=L.DISKS, porosity=phi, r_min=4.0, r_max=8.0,
                          min_gap=2.0, walls_y=1, buffer_x=2, seed=base_seed + k)
             nps = np_steps_2d
-        p = Params(u_in=u_in, dpsi_vt=dpsi, D=(D_NA, D_CL), precision=precision)
+        p = Params(u_in=u_in, dpsi_vt=dpsi, D=(D_NA, D_CL), precision=precision, streaming=streaming)
         out.append(Request(k, arrivals[k], g, p, flow_tol=flow_tol, flow_max_steps=flow_max_steps,
                            np_steps=nps))
     return out

@@ -72,6 +72,7 @@ class Params:
     np_x_bc: int = L.NPX_INLET_OUTLET
     np_substeps: int = 1
     precision: int = L.FP32
+    streaming: int = L.STREAM_AA
 
     def to_c(self):
         p = L.CParams()
@@ -85,6 +86,7 @@ class Params:
         p.c0, p.c_out, p.Ka, p.dpsi_vt = self.c0, self.c_out, self.Ka, self.dpsi_vt
         p.psi_field = None if self.psi_field is None else self.psi_field.data_ptr()
         p.np_x_bc, p.np_substeps, p.precision = self.np_x_bc, self.np_substeps, self.precision
+        p.streaming = self.streaming
         return p
 
 
@@ -223,17 +225,17 @@ class Solver:
     def tuning(self):
         t = L.CTuning()
         L.check(self.lib.cdi_get_tuning(self.h, C.byref(t)), "cdi_get_tuning")
-        return (t.blocks_per_cu, t.band_rows, t.columns)
+        return (t.blocks_per_cu, t.band_rows, t.columns, t.nbr_list)
 
-    def set_tuning(self, blocks_per_cu: int = 0, band_rows: int = 0, columns: int = 0):
-        t = L.CTuning(blocks_per_cu, band_rows, columns)
+    def set_tuning(self, blocks_per_cu: int = 0, band_rows: int = 0, columns: int = 0, nbr_list: int = 0):
+        t = L.CTuning(blocks_per_cu, band_rows, columns, nbr_list)
         L.check(self.lib.cdi_set_tuning(self.h, C.byref(t)), "cdi_set_tuning")
 
     def autotune(self, steps: int = 4, fused: bool = True):
         t, ms = L.CTuning(), C.c_double()
         L.check(self.lib.cdi_autotune(self.h, steps, 1 if fused else 0, C.byref(t), C.byref(ms)),
                 "cdi_autotune")
-        return (t.blocks_per_cu, t.band_rows, t.columns), ms.value
+        return (t.blocks_per_cu, t.band_rows, t.columns, t.nbr_list), ms.value
 
     def snapshot(self) -> bytes:
         nb = C.c_uint64()

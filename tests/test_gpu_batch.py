@@ -74,6 +74,22 @@ def test_batch_equals_members_stepped_alone(precision):
             assert np.array_equal(a, c), f"member {k}"
 
 
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV])
+def test_batch_mixing_aa_and_pull_members(precision):
+    specs = members(precision)
+    for k, (g, p) in enumerate(specs):
+        p.streaming = L.STREAM_PULL if k % 2 else L.STREAM_AA
+    alone = run_alone(specs)
+    solvers = [Solver(g, p) for g, p in specs]
+    b = Batch(solvers)
+    for n, modes in schedule():
+        b.advance(n, modes)
+    b.synchronize()
+    for k, s in enumerate(solvers):
+        for a, c in zip(alone[k], state(s)):
+            assert np.array_equal(a, c), f"member {k}"
+
+
 def test_batch_on_default_stream_and_launch_shapes_agree():
     import torch
     specs = members()

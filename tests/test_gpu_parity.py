@@ -68,9 +68,10 @@ def test_all_solid_geometry_is_rejected():
 
 # ------------------------------------------------------------------ flow
 
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL])
 @pytest.mark.parametrize("steps", [1, 2, 301, 2000])
-def test_flow_parity_2d_channel(steps):
-    g, p, _ = preset("channel2d_128x64")
+def test_flow_parity_2d_channel(steps, streaming):
+    g, p, _ = preset("channel2d_128x64", streaming=streaming)
     s = Solver(g, p)
     o = oracle_solver(g, p)
     s.flow_steps(steps)
@@ -79,9 +80,10 @@ def test_flow_parity_2d_channel(steps):
     assert np.abs(s.density() - o.density()).max() <= 1e-6
 
 
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL])
 @pytest.mark.parametrize("steps", [3, 200])
-def test_flow_parity_3d_spheres(steps):
-    g, p = small3d()
+def test_flow_parity_3d_spheres(steps, streaming):
+    g, p = small3d(streaming=streaming)
     s = Solver(g, p)
     o = oracle_solver(g, p)
     s.flow_steps(steps)
@@ -154,18 +156,20 @@ def _check_np(s, o, c0=1.0):
     assert np.all(np.abs(a - ao) <= 1e-4 * np.abs(ao))
 
 
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL])
 @pytest.mark.parametrize("fused", [False, True])
-def test_np_parity_2d(fused):
-    g, p, _ = preset("channel2d_128x64")
+def test_np_parity_2d(fused, streaming):
+    g, p, _ = preset("channel2d_128x64", streaming=streaming)
     s, o = _flow_then_np(g, p, 1500, 1001, fused)
     _check_np(s, o)
     if fused:
         assert rel_l2(s.velocity(), o.velocity()) <= 1e-5
 
 
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL])
 @pytest.mark.parametrize("fused", [False, True])
-def test_np_parity_3d(fused):
-    g, p = small3d()
+def test_np_parity_3d(fused, streaming):
+    g, p = small3d(streaming=streaming)
     s, o = _flow_then_np(g, p, 200, 151, fused)
     _check_np(s, o)
 
@@ -220,9 +224,10 @@ def test_unstable_np_is_rejected():
 
 # ------------------------------------------------------------------ FP16 deviations
 
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL])
 @pytest.mark.parametrize("fused", [False, True])
-def test_fp16_dev_parity_tau1(fused):
-    g, p, _ = preset("channel2d_128x64", precision=L.FP16_DEV)
+def test_fp16_dev_parity_tau1(fused, streaming):
+    g, p, _ = preset("channel2d_128x64", precision=L.FP16_DEV, streaming=streaming)
     s, o = _flow_then_np(g, p, 1500, 501, fused)
     assert rel_l2(s.velocity(), o.velocity()) <= 1e-5
     _check_np(s, o)
@@ -267,9 +272,10 @@ def test_moments_3d_parity_odd_counts_and_residual():
     assert np.isfinite(r) and r > 0
 
 
-def test_fp16_dev_error_statement_tau_08():
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL])
+def test_fp16_dev_error_statement_tau_08(streaming):
     # away from tau = 1 the stored deviations are (1 - 1/tau) f_neq in FP16
-    g, p = small3d(tau=0.8)
+    g, p = small3d(tau=0.8, streaming=streaming)
     p.precision = L.FP16_DEV
     s = Solver(g, p)
     o = oracle_solver(g, p)
@@ -282,9 +288,11 @@ def test_fp16_dev_error_statement_tau_08():
 
 # ------------------------------------------------------------------ systems
 
-@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV, L.MOMENTS])
-def test_snapshot_restore_continues_bitwise(precision):
-    g, p = small3d(precision=precision)
+@pytest.mark.parametrize("precision,streaming", [(L.FP32, L.STREAM_AA), (L.FP16_DEV, L.STREAM_AA),
+                                                  (L.MOMENTS, L.STREAM_AA), (L.FP32, L.STREAM_PULL),
+                                                  (L.FP16_DEV, L.STREAM_PULL)])
+def test_snapshot_restore_continues_bitwise(precision, streaming):
+    g, p = small3d(precision=precision, streaming=streaming)
     s = Solver(g, p)
     s.flow_steps(51)
     s.np_step(20, fused=True)
@@ -299,11 +307,12 @@ def test_snapshot_restore_continues_bitwise(precision):
 
 def test_results_do_not_depend_on_tuning_and_autotune_restores_state():
     outs = []
-    for occ, band, cols in ((0, 0, 0), (3, 8, 0), (6, 32, 0), (0, 0, 1), (4, 0, 1)):
+    for occ, band, cols, nl in ((0, 0, 0, 0), (3, 8, 0, 0), (6, 32, 0, 1), (0, 0, 1, 0), (4, 0, 1, 1),
+                                (0, 0, 0, 1)):
         g, p = small3d(seed=13)
         s = Solver(g, p)
-        s.set_tuning(occ, band, cols)
-        assert s.tuning() == (occ, band, cols)
+        s.set_tuning(occ, band, cols, nl)
+        assert s.tuning() == (occ, band, cols, nl)
         s.flow_steps(21)
         s.np_step(30, fused=True)
         outs.append((s.concentration(), s.velocity(), s.adsorbed_total()))
@@ -321,6 +330,20 @@ def test_results_do_not_depend_on_tuning_and_autotune_restores_state():
     assert before[2] == after[2]
     s.np_step(30, fused=True)
     assert np.array_equal(outs[0][0], s.concentration())
+
+
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV])
+def test_pull_and_aa_streaming_agree(precision):
+    # the two schemes move the same stored values to the same nodes and run
+    # the same arithmetic on them, so the results agree bit for bit
+    out = []
+    for streaming in (L.STREAM_AA, L.STREAM_PULL):
+        g, p = small3d(seed=5, precision=precision, streaming=streaming)
+        s = Solver(g, p)
+        s.flow_steps(77)
+        s.np_step(41, fused=True)
+        out.append((s.velocity(), s.concentration()))
+    assert np.array_equal(out[1][0], out[0][0]) and np.array_equal(out[1][1], out[0][1])
 
 
 def test_two_runs_are_bitwise_identical():
