@@ -48,8 +48,11 @@ def _variant(name: str):
         return None
     lat, st, odd, lbm, np_ = m.groups()
     kind = "fused" if lbm == "1" and np_ == "1" else ("lbm" if lbm == "1" else "np")
-    # ion-only steps and moment storage have no AA parity
-    parity = "" if kind == "np" or st == "2" else (" odd" if odd == "1" else " even")
+    # ion-only steps and moment storage have no AA parity; 2 = pull streaming
+    if kind == "np" or st == "2":
+        parity = ""
+    else:
+        parity = {"0": " even", "1": " odd", "2": " pull"}[odd]
     return f"{lat} {STORAGE[st]} {kind}{parity}"
 
 
@@ -111,7 +114,8 @@ def summarise(trace, fetch, write, bench_log, copy_mib, commands=()):
         rows.append(dict(kernel=k, calls=calls, avg_ms=dur * 1e3, read_bytes=fb, write_bytes=wb,
                          read_per_node=fb / n_fluid, write_per_node=wb / n_fluid,
                          gbs=(fb + wb) / dur / 1e9))
-    # bytes per launch of a whole step (even and odd launches alternate)
+    # bytes per launch of a whole step (the mean of the kernels one step can
+    # be: AA even and odd alternate; pull and moment storage use one)
     per_launch = {}
     for st in STORAGE.values():
         for kind in ("fused", "lbm"):
