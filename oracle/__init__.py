@@ -22,4 +22,7 @@ from .oracle import (  # noqa: F401
     DRIVE_BODY_FORCE,
     EQ_QUADRATIC,
     EQ_LINEAR,
+    PSIX_DIRICHLET,
+    PSIX_NEUMANN,
+    PSIX_PERIODIC,
 )

@@ -269,10 +269,12 @@ oracle_solver *oracle_create(const oracle_cfg *cfg, const uint8_t *labels, const
             s->psi[v] = cfg->dpsi * (1.0 - (x + 0.5) / c->nx);
         }
     }
-    /* Adsorption constant: given, or the paper's Da/Pe ratio of its base case
-     * (Da = 4.28e-3 at Pe = 1.03e-2) times the mean pore velocity u_in/phi. */
+    /* Adsorption constant: given; zero selects the paper's Da/Pe ratio of its
+     * base case (Da = 4.28e-3 at Pe = 1.03e-2) times the mean pore velocity
+     * u_in/phi; negative selects none (a blocking electrode, as the charged
+     * wall of the electromigration check of Sec. 3). */
     const double phi = (double)s->nf / (double)nv;
-    s->ka = cfg->Ka > 0 ? cfg->Ka : (4.28e-3 / 1.03e-2) * cfg->u_in / phi;
+    s->ka = cfg->Ka > 0 ? cfg->Ka : cfg->Ka < 0 ? 0.0 : (4.28e-3 / 1.03e-2) * cfg->u_in / phi;
     /* Robin law D dC/dn = Ka C (Eq. 6) across half a cell: the wall value is
      * eliminated, giving the face flux k_eff * C_P. */
     for (int sp = 0; sp < 2; ++sp) s->keff[sp] = s->ka * cfg->D[sp] / (cfg->D[sp] + 0.5 * s->ka);
@@ -726,4 +728,206 @@ void oracle_adsorbed_total(const oracle_solver *s, double out[2])
 {
     out[0] = s->acc[0][0];
     out[1] = s->acc[1][0];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Electric potential, Eq. (4)-(5), in thermal voltages psi~ = e psi / k_BT. */
+/* ------------------------------------------------------------------------ */
+/*
+ * Finite volumes on the fluid voxels, one unknown per cell centre. The flux
+ * of grad psi through a face between two fluid cells is psi_N - psi_P. At a
+ * face shared with an electrode voxel the paper's Dirichlet condition holds
+ * on the face itself, half a cell from the centre: flux 2 (psi_e - psi_P).
+ * Inert walls carry no field (zero normal derivative). Each x end is either
+ * a Dirichlet face (value psi_x[end], half a cell away), a zero-field face,
+ * or periodic (both ends). With psi~ and the Debye length lambda_D of a
+ * symmetric electrolyte at c0 (lambda_D^2 = eps_r eps_0 k_B T / (2 e F c0),
+ * the length of Eq. (10)), Eq. (4) with the charge of Eq. (5) reads
+ *   lap psi~ = -(kappa2 / (2 c0)) sum_i z_i C_i,  kappa2 = (h / lambda_D)^2,
+ * so a cell balances sum(face fluxes) + (kappa2 / (2 c0)) sum_i z_i C_i = 0.
+ * Written as A psi = b with A symmetric positive definite when at least one
+ * Dirichlet face exists: A_PP = sum of face coefficients (1 per fluid face,
+ * 2 per Dirichlet face), A_PN = -1, b_P = source + sum 2 psi_face. Solved by
+ * conjugate gradients (Hestenes-Stiefel) with the diagonal as preconditioner.
+ */
+static int pot_face(const oracle_solver *s, const oracle_potential *pc, int64_t v, int axis, int sgn,
+                    int64_t *vn, double *value)
+{
+    const oracle_cfg *c = &s->cfg;
+    int x, y, z;
+    vox_xyz(s, v, &x, &y, &z);
+    int off[3] = {0, 0, 0};
+    off[axis] = sgn;
+    if (axis == 0 && (x + sgn < 0 || x + sgn >= c->nx) && pc->x_bc[0] != ORACLE_PSIX_PERIODIC) {
+        const int end = x + sgn < 0 ? 0 : 1;
+        if (pc->x_bc[end] == ORACLE_PSIX_NEUMANN) return 0;
+        *value = pc->psi_x[end];
+        return 2;
+    }
+    const int64_t n = neighbour(s, v, off[0], off[1], off[2], 1);
+    if (s->labels[n] == 0) {
+        *vn = n;
+        return 1;
+    }
+    if (s->labels[n] == 1) {
+        *value = pc->psi_electrode;
+        return 2;
+    }
+    return 0; /* inert wall */
+}
+
+/* q = A p over the fluid cells (p, q: nvox arrays, fluid entries used). */
+static void pot_apply(const oracle_solver *s, const oracle_potential *pc, const double *p, double *q)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        double acc = 0;
+        for (int axis = 0; axis < s->cfg.dim; ++axis)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                int64_t vn = -1;
+                double val = 0;
+                const int kind = pot_face(s, pc, v, axis, sgn, &vn, &val);
+                if (kind == 1) acc += p[v] - p[vn];
+                else if (kind == 2) acc += 2.0 * p[v];
+            }
+        q[v] = acc;
+    }
+}
+
+/* Sum over fluid cells of a[v] * b[v] in fixed chunks (same order for any
+ * thread count). */
+static double pot_dot(const oracle_solver *s, const double *a, const double *b)
+{
+    const int64_t nchunks = (s->nf + CHUNK - 1) / CHUNK;
+    double *part = (double *)calloc((size_t)(nchunks > 0 ? nchunks : 1), sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        const int64_t n1 = (ch + 1) * CHUNK < s->nf ? (ch + 1) * CHUNK : s->nf;
+        double t = 0;
+        for (int64_t n = ch * CHUNK; n < n1; ++n) t += a[s->fluid[n]] * b[s->fluid[n]];
+        part[ch] = t;
+    }
+    double t = 0;
+    for (int64_t ch = 0; ch < nchunks; ++ch) t += part[ch];
+    free(part);
+    return t;
+}
+
+int oracle_solve_potential(oracle_solver *s, const oracle_potential *pc, int *iters, double *relres)
+{
+    if (!s || !pc || pc->max_iter < 0 || !(pc->tol >= 0)) return ORACLE_E_INVALID;
+    if ((pc->x_bc[0] == ORACLE_PSIX_PERIODIC) != (pc->x_bc[1] == ORACLE_PSIX_PERIODIC))
+        return ORACLE_E_INVALID;
+    const oracle_cfg *c = &s->cfg;
+    const int64_t nv = s->nvox;
+    double *x = (double *)calloc((size_t)nv, sizeof(double));
+    double *r = (double *)calloc((size_t)nv, sizeof(double));
+    double *zv = (double *)calloc((size_t)nv, sizeof(double));
+    double *p = (double *)calloc((size_t)nv, sizeof(double));
+    double *q = (double *)calloc((size_t)nv, sizeof(double));
+    double *dg = (double *)calloc((size_t)nv, sizeof(double));
+    if (!x || !r || !zv || !p || !q || !dg) {
+        free(x), free(r), free(zv), free(p), free(q), free(dg);
+        return ORACLE_E_INVALID;
+    }
+    /* right-hand side and diagonal */
+    int64_t n_dirichlet = 0;
+    const double src = pc->kappa2 / (2.0 * c->c0);
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        double b = src * (c->z[0] * s->C[v] + c->z[1] * s->C[nv + v]);
+        double d = 0;
+        for (int axis = 0; axis < c->dim; ++axis)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                int64_t vn = -1;
+                double val = 0;
+                const int kind = pot_face(s, pc, v, axis, sgn, &vn, &val);
+                if (kind == 1) d += 1.0;
+                else if (kind == 2) {
+                    d += 2.0;
+                    b += 2.0 * val;
+                    ++n_dirichlet;
+                }
+            }
+        r[v] = b; /* x0 = 0 */
+        dg[v] = d;
+    }
+    int rc = ORACLE_OK;
+    int k = 0;
+    double rel = 0;
+    if (n_dirichlet == 0) {
+        rc = ORACLE_E_INVALID; /* the potential would be defined up to a constant only */
+    } else {
+        const double bnorm = sqrt(pot_dot(s, r, r));
+        for (int64_t n = 0; n < s->nf; ++n) {
+            const int64_t v = s->fluid[n];
+            zv[v] = dg[v] > 0 ? r[v] / dg[v] : 0.0;
+            p[v] = zv[v];
+        }
+        double rz = pot_dot(s, r, zv);
+        double rr = bnorm * bnorm;
+        rel = bnorm > 0 ? 1.0 : 0.0;
+        while (bnorm > 0 && sqrt(rr) > pc->tol * bnorm) {
+            if (k >= pc->max_iter) {
+                rc = ORACLE_E_NOT_CONVERGED;
+                break;
+            }
+            pot_apply(s, pc, p, q);
+            const double alpha = rz / pot_dot(s, p, q);
+            for (int64_t n = 0; n < s->nf; ++n) {
+                const int64_t v = s->fluid[n];
+                x[v] += alpha * p[v];
+                r[v] -= alpha * q[v];
+                zv[v] = dg[v] > 0 ? r[v] / dg[v] : 0.0;
+            }
+            const double rz_new = pot_dot(s, r, zv);
+            rr = pot_dot(s, r, r);
+            const double beta = rz_new / rz;
+            rz = rz_new;
+            for (int64_t n = 0; n < s->nf; ++n) {
+                const int64_t v = s->fluid[n];
+                p[v] = zv[v] + beta * p[v];
+            }
+            ++k;
+            if (!isfinite(rr)) {
+                rc = ORACLE_E_DIVERGED;
+                break;
+            }
+        }
+        if (bnorm > 0) rel = sqrt(rr) / bnorm;
+        if (rc == ORACLE_OK || rc == ORACLE_E_NOT_CONVERGED) {
+            for (int64_t n = 0; n < s->nf; ++n) s->psi[s->fluid[n]] = x[s->fluid[n]];
+            s->psi_is_field = 1;
+        }
+    }
+    if (iters) *iters = k;
+    if (relres) *relres = rel;
+    free(x), free(r), free(zv), free(p), free(q), free(dg);
+    return rc;
+}
+
+void oracle_get_potential(const oracle_solver *s, double *psi)
+{
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        psi[n] = s->psi[v]; /* the ramp's values when no field was set or solved */
+    }
+}
+
+/* Coupled Poisson-Nernst-Planck: before every `every`-th ion step the
+ * potential is solved afresh from the concentrations the step starts from
+ * (Eq. 4-5), then the step runs on it (Eq. 3): an explicit, lagged coupling. */
+int oracle_np_steps_coupled(oracle_solver *s, int64_t n, int fused, const oracle_potential *pc, int every)
+{
+    if (!s || !pc || every < 1 || n < 0) return ORACLE_E_INVALID;
+    for (int64_t k = 0; k < n; ++k) {
+        if (k % every == 0) {
+            const int rc = oracle_solve_potential(s, pc, NULL, NULL);
+            if (rc != ORACLE_OK) return rc;
+        }
+        const int rc = oracle_np_steps(s, 1, fused);
+        if (rc != ORACLE_OK) return rc;
+    }
+    return ORACLE_OK;
 }

@@ -14,7 +14,9 @@
  *     moments of the LBM paragraph (rho = sum f, u = sum e f / rho,
  *     nu = (tau - 1/2)/3), bounce-back at solid faces (no-flow paragraph);
  *   - the Nernst-Planck equation, Eq. (3), for Na+ and Cl- with a prescribed
- *     potential, and the adsorption law of Eq. (6) as a flux at electrode faces.
+ *     potential, and the adsorption law of Eq. (6) as a flux at electrode faces;
+ *   - the potential itself from Poisson's equation, Eq. (4), with the charge
+ *     of Eq. (5) and Dirichlet values on the electrode surface.
  * Everything is plain loops over the dense voxel grid in double precision,
  * using a two-lattice push scheme. Readings of what the paper leaves open
  * (time scheme, face fluxes, boundary treatments) are stated where used.
@@ -50,7 +52,7 @@ typedef struct {
     int z[2];                /* valences */
     double c0;               /* inlet / initial concentration */
     double c_out;            /* outlet ghost concentration (NPX_DIRICHLET only) */
-    double Ka;               /* adsorption constant; <= 0: derive 0.4155*u_in/phi */
+    double Ka;               /* adsorption constant; 0: derive 0.4155*u_in/phi; < 0: none */
     double dpsi;             /* potential drop (thermal voltages) inlet minus outlet */
     int np_x_bc;             /* ORACLE_NPX_* */
     int np_substeps;         /* sub-steps per NP step (>= 1) */
@@ -123,6 +125,32 @@ void oracle_balance(const oracle_solver *s, double *out);
 void oracle_adsorbed_total(const oracle_solver *s, double out[2]);
 int64_t oracle_flow_step_count(const oracle_solver *s);
 int64_t oracle_np_step_count(const oracle_solver *s);
+
+/* ---- electric potential, Eq. (4)-(5) ---- */
+/* x-end faces of the potential problem. */
+enum { ORACLE_PSIX_DIRICHLET = 0, ORACLE_PSIX_NEUMANN = 1, ORACLE_PSIX_PERIODIC = 2 };
+
+typedef struct {
+    double psi_electrode;  /* psi~ on every electrode face (Dirichlet, half a cell away) */
+    int x_bc[2];           /* ORACLE_PSIX_* of the x = 0 and x = nx faces (periodic: both) */
+    double psi_x[2];       /* Dirichlet values of those faces */
+    double kappa2;         /* (h / lambda_D)^2; the charge term is kappa2 / (2 c0) sum z_i C_i */
+    double tol;            /* stop at |b - A psi|_2 <= tol |b|_2 */
+    int max_iter;
+} oracle_potential;
+
+/* Solve the discrete Poisson problem for the current concentrations (kappa2
+ * = 0: Laplace) by Jacobi-preconditioned conjugate gradients from zero and
+ * make the result the potential of the Nernst-Planck steps. iters / relres
+ * (nullable) receive the iterations and the final relative residual.
+ * ORACLE_E_INVALID without any Dirichlet face (singular problem). */
+int oracle_solve_potential(oracle_solver *s, const oracle_potential *pc, int *iters, double *relres);
+/* n ion steps (fused as in oracle_np_steps), the potential solved afresh
+ * from the current concentrations before every `every`-th step. */
+int oracle_np_steps_coupled(oracle_solver *s, int64_t n, int fused, const oracle_potential *pc, int every);
+/* Potential in use per fluid node (compacted order): the ramp, the given
+ * field or the solved one. */
+void oracle_get_potential(const oracle_solver *s, double *psi);
 
 /* Threads the OpenMP loops use (1 if built without OpenMP). */
 int oracle_threads(void);

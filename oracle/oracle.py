@@ -20,6 +20,7 @@ EQ_QUADRATIC, EQ_LINEAR = 0, 1
 NPX_INLET_OUTLET, NPX_PERIODIC, NPX_CLOSED, NPX_DIRICHLET = 0, 1, 2, 3
 
 OK, E_INVALID, E_UNSTABLE, E_NOT_CONVERGED, E_DIVERGED = 0, -1, -3, -4, -5
+PSIX_DIRICHLET, PSIX_NEUMANN, PSIX_PERIODIC = 0, 1, 2
 
 
 def build() -> str:
@@ -38,6 +39,11 @@ class _Cfg(C.Structure):
         ("c0", C.c_double), ("c_out", C.c_double), ("Ka", C.c_double), ("dpsi", C.c_double),
         ("np_x_bc", C.c_int), ("np_substeps", C.c_int),
     ]
+
+
+class _Potential(C.Structure):
+    _fields_ = [("psi_electrode", C.c_double), ("x_bc", C.c_int * 2), ("psi_x", C.c_double * 2),
+                ("kappa2", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int)]
 
 
 class _Prim(C.Structure):
@@ -79,6 +85,9 @@ def library():
             "oracle_flow_step_count": (I64, [P]),
             "oracle_np_step_count": (I64, [P]),
             "oracle_threads": (I, []),
+            "oracle_solve_potential": (I, [P, P, P, P]),
+            "oracle_get_potential": (None, [P, P]),
+            "oracle_np_steps_coupled": (I, [P, I64, I, P, I]),
             "geomgen_disks": (I, [I, I, I, I, C.c_uint64, D, D, D, D, P, P, P]),
             "geomgen_spheres": (I, [I, I, I, I, C.c_uint64, D, D, D, P, P]),
             "geomgen_sphere_count": (I64, [I, I, I, I, D, D, D]),
@@ -285,6 +294,36 @@ class OracleSolver:
         a = np.empty(2)
         self.lib.oracle_adsorbed_total(self.h, _ptr(a))
         return a
+
+    def solve_potential(self, psi_electrode=0.0, x_bc=(PSIX_NEUMANN, PSIX_NEUMANN), psi_x=(0.0, 0.0),
+                        kappa2=0.0, tol=1e-13, max_iter=100000):
+        """Poisson solve of Eq. (4)-(5) for the current concentrations; the
+        result becomes the potential of later ion steps. Returns (rc, iters,
+        relative residual)."""
+        pc = _Potential()
+        pc.psi_electrode = psi_electrode
+        pc.x_bc[0], pc.x_bc[1] = x_bc
+        pc.psi_x[0], pc.psi_x[1] = psi_x
+        pc.kappa2, pc.tol, pc.max_iter = kappa2, tol, max_iter
+        it, rel = C.c_int(), C.c_double()
+        rc = self.lib.oracle_solve_potential(self.h, C.byref(pc), C.byref(it), C.byref(rel))
+        return rc, it.value, rel.value
+
+    def np_steps_coupled(self, n: int, every: int = 1, fused: bool = False, psi_electrode=0.0,
+                         x_bc=(PSIX_NEUMANN, PSIX_NEUMANN), psi_x=(0.0, 0.0), kappa2=0.0, tol=1e-13,
+                         max_iter=100000) -> int:
+        """n ion steps with the potential re-solved every `every` steps."""
+        pc = _Potential()
+        pc.psi_electrode = psi_electrode
+        pc.x_bc[0], pc.x_bc[1] = x_bc
+        pc.psi_x[0], pc.psi_x[1] = psi_x
+        pc.kappa2, pc.tol, pc.max_iter = kappa2, tol, max_iter
+        return int(self.lib.oracle_np_steps_coupled(self.h, n, int(fused), C.byref(pc), every))
+
+    def potential(self) -> np.ndarray:
+        p = np.empty(self.nf)
+        self.lib.oracle_get_potential(self.h, _ptr(p))
+        return p
 
     @property
     def flow_step_count(self) -> int:
