@@ -86,6 +86,54 @@ def gpu_rates(precision: int, steps: int, warmup: int, streaming: int):
     return res
 
 
+def potential_rates(coupled_steps: int = 10):
+    """The potential (Poisson, Eq. 4-5) on the bench electrode. Static solve:
+    Laplace with the electrode at -20 thermal voltages, the inlet face at 0
+    and a field-free outlet, Jacobi-PCG from zero to a relative residual of
+    1e-8. Coupled: fused LBM + ion steps with the potential re-solved from the
+    current charge (electrode at -4, kappa2 = 0.5, warm start, 1e-6) before
+    every step.
+    Algorithmic bytes of one CG iteration per fluid node: spmv reads p, the
+    packed coordinates and the voxel map (4 B per voxel) and writes q; axpy
+    reads x, r, p, q and the diagonal byte and writes x, r; dir reads r, the
+    diagonal and p and writes p."""
+    import torch
+    import paper_2110_13055_amd as P
+    g, p, _ = P.preset(WORKLOAD)
+    s = P.Solver(g, p)
+    nf, nvox = s.n_fluid, g.n_vox
+    per_iter = 8 + 8 + 4 + 4.0 * nvox / nf + 49 + 25
+    out = {"algorithmic_bytes_per_node_iter": round(per_iter, 1)}
+    pot = P.Potential(psi_electrode=-20.0, x_bc=(P.PSIX_DIRICHLET, P.PSIX_NEUMANN), tol=1e-8,
+                      warm_start=False, check_every=16)
+    s.solve_potential(pot)  # first launches
+    res = {}
+
+    def run():
+        res["it"], res["r"] = s.solve_potential(pot)
+    sec = time_region(run, s.stream)
+    it = res["it"]
+    out["laplace"] = {"iterations": it, "residual": res["r"], "solve_ms": round(sec * 1e3, 2),
+                      "ms_per_iter": round(sec * 1e3 / max(it, 1), 4),
+                      "gbs": round(per_iter * nf * it / sec / 1e9, 1)}
+    # -4 thermal voltages (about -100 mV) keeps the explicit ion update within
+    # its positivity bound on this lattice; -20 would not
+    cp = P.Potential(psi_electrode=-4.0, x_bc=(P.PSIX_DIRICHLET, P.PSIX_NEUMANN), kappa2=0.5, tol=1e-6,
+                     warm_start=True)
+    try:
+        s.flow_steps(2)
+        s.np_step_coupled(2, cp, every=1, fused=True)
+        sec = time_region(lambda: s.np_step_coupled(coupled_steps, cp, every=1, fused=True), s.stream)
+        out["coupled_pnp"] = {"steps": coupled_steps, "ms_per_step": round(sec * 1e3 / coupled_steps, 3),
+                              "mlups": round(nf * coupled_steps / sec / 1e6, 1), "psi_electrode": -4.0,
+                              "kappa2": 0.5, "every": 1}
+    except P.CdiError as exc:
+        out["coupled_pnp"] = {"error": str(exc)}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_rates(steps: int, streaming: int, n: int = 64):
     """Batched stepping of n uneven instances (cubes of edge 48-160, own seed,
     porosity, potential and inlet velocity): the fused step of all instances
@@ -174,6 +222,7 @@ def main():
     ap.add_argument("--streaming", choices=("pull", "aa"), default="pull",
                     help="population streaming of the FP32 / FP16 forms")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--no-potential", action="store_true", help="skip the potential-solve leg")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the serving trace (0 skips the serving leg)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -243,6 +292,8 @@ def main():
         "moments": form("moments", rmo),
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_potential:
+        out["potential"] = potential_rates()
     if not args.no_batch:
         out["batched"] = batched_rates(K, strm)
     if args.serve_requests > 0:

@@ -92,14 +92,18 @@ typedef struct {
  *   D[2], z[2]   diffusivity and valence of Na+ (index 0) and Cl- (index 1)
  *   c0           inlet and initial concentration ("initially saturated")
  *   c_out        outlet ghost concentration (CDI_NPX_DIRICHLET only)
- *   Ka           adsorption constant of Eq. (6); <= 0 selects
+ *   Ka           adsorption constant of Eq. (6); 0 selects
  *                Ka = (4.28e-3 / 1.03e-2) * u_in / porosity, the paper's
- *                Da/Pe ratio of its base case times the mean pore velocity
+ *                Da/Pe ratio of its base case times the mean pore velocity;
+ *                a negative value selects Ka = 0 (a blocking electrode, as
+ *                the charged wall of the electromigration check, Sec. 3)
  *   dpsi_vt      potential drop inlet minus outlet in thermal voltages; the
- *                potential is the ramp dpsi_vt * (1 - (x + 1/2)/nx)
+ *                potential is the ramp dpsi_vt * (1 - (x + 1/2)/nx) until a
+ *                field is given or solved (cdi_solve_potential)
  *   psi_field    device, N_f floats in fluid-node order, or NULL: a
- *                prescribed potential (thermal voltages) replacing the ramp;
- *                the buffer must outlive the solver
+ *                prescribed potential (thermal voltages) replacing the ramp,
+ *                copied at initialisation. With a field, the x-end faces
+ *                carry no migration (the ghost cell shares the cell's value)
  *   np_x_bc      treatment of the two x-end faces for Nernst-Planck
  *   np_substeps  Nernst-Planck sub-steps per step (dt = 1/np_substeps);
  *                fused steps need 1
@@ -308,8 +312,69 @@ int cdi_batch_get_launch(const cdi_batch *b, int32_t *workgroups, int32_t *block
 int cdi_batch_autotune(cdi_batch *b, int32_t steps, const int32_t *modes, int32_t *workgroups,
                        double *ms_per_step);
 
+/* ------------------------------------------------------------ electric potential
+ * Poisson's equation for the potential, Eq. (4), with the charge density of
+ * Eq. (5), and a constant potential on the electrode surface as the Dirichlet
+ * condition at the liquid-solid interface (Sec. 2). In thermal voltages
+ * psi~ = e psi / k_B T and lattice units, with lambda_D the Debye length of a
+ * symmetric electrolyte at c0 (lambda_D^2 = eps_r eps_0 k_B T / (2 e F c0),
+ * the length in Eq. (10)), the equation reads
+ *   lap psi~ = -(kappa2 / (2 c0)) sum_i z_i C_i,   kappa2 = (dx / lambda_D)^2.
+ * Finite volumes on the fluid voxels: a face between two fluid cells carries
+ * psi_N - psi_P, an electrode face 2 (psi_electrode - psi_P) (the value holds
+ * on the face, half a cell from the centre), an inert face nothing, and each
+ * x-end face is Dirichlet (value psi_x), field-free, or periodic (both ends).
+ * The symmetric positive definite system is solved by Jacobi-preconditioned
+ * conjugate gradients in FP64 on the GPU; the result (stored as FP32) becomes
+ * the potential of every later ion step. */
+enum { CDI_PSIX_DIRICHLET = 0, CDI_PSIX_NEUMANN = 1, CDI_PSIX_PERIODIC = 2 };
+
+typedef struct {
+    double psi_electrode;  /* psi~ on every electrode (label 1) face */
+    int32_t x_bc[2];       /* CDI_PSIX_* of the faces x = 0 and x = nx */
+    double psi_x[2];       /* their Dirichlet values */
+    double kappa2;         /* (dx / lambda_D)^2 >= 0; 0 = Laplace (charge neglected) */
+    double tol;            /* stop at |b - A psi|_2 <= tol |b|_2 (FP64 residual) */
+    int32_t max_iter;      /* iteration cap */
+    int32_t check_every;   /* iterations between convergence read-backs (0 = 32) */
+    int32_t warm_start;    /* 1: start from the field in use (if any), 0: from zero */
+} cdi_potential;
+
+typedef struct {
+    int32_t iterations;    /* CG iterations taken */
+    double residual;       /* final |b - A psi|_2 / |b|_2 */
+} cdi_potential_result;
+
+/* Device workspace of the solve (4 FP64 vectors and a byte per node, plus
+ * per-workgroup sums); needed only during the call. */
+int cdi_potential_bytes(const cdi_solver *s, uint64_t *bytes);
+
+/* Solve for the potential of the current concentrations. ws: device, >=
+ * cdi_potential_bytes, 256-byte aligned. Synchronises once per check_every
+ * iterations. The iterate is the same for any check_every (the stop is
+ * decided on the device). Returns OK; NOT_CONVERGED after max_iter (the last
+ * iterate is installed); INVALID without any Dirichlet face (the potential is
+ * then fixed only up to a constant) or for bad settings; DIVERGED on a
+ * non-finite residual or a breakdown (nothing installed). out (host,
+ * nullable) receives iterations and residual. */
+int cdi_solve_potential(cdi_solver *s, const cdi_potential *pot, void *ws, uint64_t ws_bytes,
+                        cdi_potential_result *out);
+
+/* Coupled Poisson-Nernst-Planck: nsteps ion steps (fused_flow as in
+ * cdi_np_step), with the potential solved afresh from the concentrations
+ * before every `every`-th step (explicit, lagged coupling; the positivity
+ * check of cdi_np_step runs after every solve). The coupling adds the
+ * dielectric relaxation rate D kappa2 to each species' update, which the
+ * positivity check does not bound: keep dt D kappa2 well below 1. */
+int cdi_np_step_coupled(cdi_solver *s, int64_t nsteps, int32_t fused_flow, const cdi_potential *pot,
+                        int32_t every, void *ws, uint64_t ws_bytes);
+
+/* The potential in use (thermal voltages), N_f floats in fluid-node order:
+ * the solved or given field, else the ramp. Synchronous. */
+int cdi_copy_potential(cdi_solver *s, float *psi);
+
 /* Checkpoint: the complete device state (populations, moments, fields,
- * accumulators, counters, AA parity) to and from host memory. */
+ * potential, accumulators, counters, AA parity) to and from host memory. */
 int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes);
 int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes);
 int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes);

@@ -20,6 +20,7 @@ NPX_INLET_OUTLET, NPX_PERIODIC, NPX_CLOSED, NPX_DIRICHLET = 0, 1, 2, 3
 FP32, FP16_DEV, MOMENTS = 0, 1, 2
 STREAM_AA, STREAM_PULL = 0, 1
 MODE_IDLE, MODE_FLOW, MODE_IONS, MODE_FUSED = 0, 1, 2, 3
+PSIX_DIRICHLET, PSIX_NEUMANN, PSIX_PERIODIC = 0, 1, 2
 
 STATUS_NAMES = {
     0: "OK", 1: "STAGNATED", -1: "INVALID", -2: "GEOMETRY", -3: "UNSTABLE", -4: "NOT_CONVERGED",
@@ -71,6 +72,16 @@ class CTuning(C.Structure):
                 ("nbr_list", C.c_int32)]
 
 
+class CPotential(C.Structure):
+    _fields_ = [("psi_electrode", C.c_double), ("x_bc", C.c_int32 * 2), ("psi_x", C.c_double * 2),
+                ("kappa2", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32), ("warm_start", C.c_int32)]
+
+
+class CPotentialResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("residual", C.c_double)]
+
+
 P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
 
 # name -> (restype, argtypes); the list of symbols include/cdi.h declares
@@ -105,6 +116,10 @@ SIGNATURES = {
     "cdi_batch_set_launch": (C.c_int, [P, I32, I32]),
     "cdi_batch_get_launch": (C.c_int, [P, P, P]),
     "cdi_batch_autotune": (C.c_int, [P, I32, P, P, P]),
+    "cdi_potential_bytes": (C.c_int, [P, P]),
+    "cdi_solve_potential": (C.c_int, [P, P, P, U64, P]),
+    "cdi_np_step_coupled": (C.c_int, [P, I64, I32, P, I32, P, U64]),
+    "cdi_copy_potential": (C.c_int, [P, P]),
     "cdi_snapshot_bytes": (C.c_int, [P, P]),
     "cdi_snapshot": (C.c_int, [P, P, U64]),
     "cdi_restore": (C.c_int, [P, P, U64]),

@@ -5,6 +5,7 @@
 #include "cdi.h"
 #include "cdi_internal.h"
 #include "geomgen.h"
+#include "pot_internal.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -284,6 +285,7 @@ namespace {
 struct SnapHeader {
     uint64_t magic, bytes;
     int32_t parity, mcur, jcur, ccur, jstate, fcur;
+    int32_t psi_on, pad;  // the potential in use is the field in the state (else the ramp)
     int64_t flow_steps, np_steps, nf;
 };
 constexpr uint64_t kSnapMagic = 0x43444931534e4150ull;
@@ -625,7 +627,9 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     s->vox = V;
     s->node = N;
     s->porosity = (double)n_fluid / (double)nvox;
-    s->ka = params->Ka > 0 ? params->Ka : (4.28e-3 / 1.03e-2) * params->u_in / s->porosity;
+    s->ka = params->Ka > 0   ? params->Ka
+            : params->Ka < 0 ? 0.0  // no adsorption: a blocking electrode
+                             : (4.28e-3 / 1.03e-2) * params->u_in / s->porosity;
     for (int k = 0; k < 2; ++k) s->keff[k] = s->ka * params->D[k] / (params->D[k] + 0.5 * s->ka);
 
     Grid &g = s->g;
@@ -893,6 +897,156 @@ int cdi_set_concentration(cdi_solver *s, const float *c)
     return planes_h2d(s, s->node.C[s->ccur], c, 2);
 }
 
+// ------------------------------------------------------------ electric potential
+
+namespace {
+
+struct PotLayout {
+    double *x, *r, *p, *q, *part, *state;
+    uint8_t *dg;
+    uint64_t bytes;
+};
+
+PotLayout pot_layout(void *ws, int P)
+{
+    const int G = pot_workgroups(P / kTile);
+    Carver c(ws);
+    PotLayout L;
+    L.x = c.take<double>(8ull * P);
+    L.r = c.take<double>(8ull * P);
+    L.p = c.take<double>(8ull * P);
+    L.q = c.take<double>(8ull * P);
+    L.dg = c.take<uint8_t>((uint64_t)P);
+    L.part = c.take<double>(8ull * pot_part_doubles(G));
+    L.state = c.take<double>(8ull * kStSlots);
+    L.bytes = c.off;
+    return L;
+}
+
+int check_potential(const cdi_solver *s, const cdi_potential *pc)
+{
+    if (!pc) return fail(CDI_E_INVALID, "potential settings are NULL");
+    for (int e = 0; e < 2; ++e)
+        if (pc->x_bc[e] < CDI_PSIX_DIRICHLET || pc->x_bc[e] > CDI_PSIX_PERIODIC)
+            return fail(CDI_E_INVALID, "bad x_bc[%d]", e);
+    if ((pc->x_bc[0] == CDI_PSIX_PERIODIC) != (pc->x_bc[1] == CDI_PSIX_PERIODIC))
+        return fail(CDI_E_INVALID, "a periodic potential needs both x ends periodic");
+    if (!(pc->tol >= 0) || pc->max_iter < 0 || pc->check_every < 0)
+        return fail(CDI_E_INVALID, "bad tol, max_iter or check_every");
+    if (!std::isfinite(pc->psi_electrode) || !std::isfinite(pc->psi_x[0]) || !std::isfinite(pc->psi_x[1]) ||
+        !std::isfinite(pc->kappa2) || pc->kappa2 < 0)
+        return fail(CDI_E_INVALID, "non-finite potential values or negative kappa2");
+    if (8ull * s->P > 4294967295ull)
+        return fail(CDI_E_INVALID, "too many fluid nodes for the potential solve (limit 2^29)");
+    return CDI_OK;
+}
+
+int solve_potential(cdi_solver *s, const cdi_potential *pc, void *ws, uint64_t ws_bytes,
+                    cdi_potential_result *out)
+{
+    int rc = check_potential(s, pc);
+    if (rc) return rc;
+    if (!ws || ((uintptr_t)ws % kAlign)) return fail(CDI_E_BUFFER, "workspace NULL or not 256-byte aligned");
+    const PotLayout W = pot_layout(ws, s->P);
+    if (ws_bytes < W.bytes) return fail(CDI_E_BUFFER, "potential workspace too small: %llu < %llu",
+                                        (unsigned long long)ws_bytes, (unsigned long long)W.bytes);
+    PotArgs a{};
+    a.g = s->g;
+    a.xbc[0] = pc->x_bc[0];
+    a.xbc[1] = pc->x_bc[1];
+    a.psi_e = pc->psi_electrode;
+    a.psi_x[0] = pc->psi_x[0];
+    a.psi_x[1] = pc->psi_x[1];
+    a.src = pc->kappa2 / (2.0 * s->params.c0);
+    a.z[0] = (float)s->params.z[0];
+    a.z[1] = (float)s->params.z[1];
+    a.C = s->node.C[s->ccur];
+    a.psi0 = pc->warm_start ? s->p.psi : nullptr;
+    a.x = W.x;
+    a.r = W.r;
+    a.p = W.p;
+    a.q = W.q;
+    a.dg = W.dg;
+    a.part = W.part;
+    a.state = W.state;
+    const int G = pot_workgroups(s->ntiles);
+    HIPCHK(launch_pot_setup(s->dim, a, G, pc->tol, s->stream));
+    double st[kStSlots];
+    if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
+    if (st[kStNdir] == 0)
+        return fail(CDI_E_INVALID, "no Dirichlet face (electrode or x end): the potential is not determined");
+    int iters = 0;
+    if (st[kStBb] == 0) {  // b = 0: the solution is zero
+        HIPCHK(launch_fill_f32(s->node.psi, 0.f, s->P, s->stream));
+        st[kStDone] = kDoneConverged;
+        st[kStRr] = 0;
+    } else {
+        const int chunk = pc->check_every > 0 ? pc->check_every : 32;
+        while (st[kStDone] == 0 && iters < pc->max_iter) {
+            const int n = std::min(chunk, pc->max_iter - iters);
+            for (int k = iters; k < iters + n; ++k) HIPCHK(launch_pot_iter(s->dim, a, G, k, s->stream));
+            if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
+            iters = st[kStDone] != 0 ? (int)st[kStIters] : iters + n;
+        }
+        if (st[kStDone] == kDoneDiverged || st[kStDone] == kDoneBreakdown)
+            return fail(CDI_E_DIVERGED, "potential solve %s after %d iterations",
+                        st[kStDone] == kDoneDiverged ? "diverged" : "broke down", iters);
+        HIPCHK(launch_pot_store(a, s->node.psi, s->stream));
+    }
+    s->p.psi = s->node.psi;
+    if (out) {
+        out->iterations = iters;
+        out->residual = st[kStBb] > 0 ? std::sqrt(st[kStRr] / st[kStBb]) : 0.0;
+    }
+    if (st[kStDone] == 0)
+        return fail(CDI_E_NOT_CONVERGED, "potential solve: %d iterations, relative residual %g", iters,
+                    std::sqrt(st[kStRr] / st[kStBb]));
+    return CDI_OK;
+}
+
+}  // namespace
+
+int cdi_potential_bytes(const cdi_solver *s, uint64_t *bytes)
+{
+    if (!s || !bytes) return fail(CDI_E_INVALID, "NULL argument");
+    *bytes = pot_layout(nullptr, s->P).bytes;
+    return CDI_OK;
+}
+
+int cdi_solve_potential(cdi_solver *s, const cdi_potential *pot, void *ws, uint64_t ws_bytes,
+                        cdi_potential_result *out)
+{
+    if (!s) return fail(CDI_E_INVALID, "NULL solver");
+    return solve_potential(s, pot, ws, ws_bytes, out);
+}
+
+int cdi_np_step_coupled(cdi_solver *s, int64_t nsteps, int32_t fused_flow, const cdi_potential *pot,
+                        int32_t every, void *ws, uint64_t ws_bytes)
+{
+    if (!s || nsteps < 0 || every < 1) return fail(CDI_E_INVALID, "bad arguments");
+    for (int64_t k = 0; k < nsteps; k += every) {
+        int rc = solve_potential(s, pot, ws, ws_bytes, nullptr);
+        if (rc) return rc;
+        if ((rc = cdi_np_step(s, std::min<int64_t>(every, nsteps - k), fused_flow)) != CDI_OK) return rc;
+    }
+    return CDI_OK;
+}
+
+int cdi_copy_potential(cdi_solver *s, float *psi)
+{
+    if (!s || !psi) return fail(CDI_E_INVALID, "NULL argument");
+    if (s->p.psi) return planes_d2h(s, psi, s->node.psi, 1);
+    // the ramp of the x coordinate
+    std::vector<int32_t> fluid((size_t)s->nf);
+    int rc = d2h(s, fluid.data(), s->vox.fluid, 4ull * s->nf);
+    if (rc) return rc;
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int x = (int)(fluid[(size_t)n] % s->g.nx);
+        psi[n] = (float)(s->params.dpsi_vt * (1.0 - (x + 0.5) / s->g.nx));
+    }
+    return CDI_OK;
+}
+
 int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes)
 {
     if (!s || !bytes) return fail(CDI_E_INVALID, "NULL argument");
@@ -905,7 +1059,7 @@ int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes)
     if (!s || !host) return fail(CDI_E_INVALID, "NULL argument");
     if (bytes < sizeof(SnapHeader) + s->node.state_bytes) return fail(CDI_E_BUFFER, "snapshot buffer too small");
     SnapHeader h{kSnapMagic, s->node.state_bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, s->fcur,
-                 s->flow_steps, s->np_steps, s->nf};
+                 s->p.psi != nullptr, 0, s->flow_steps, s->np_steps, s->nf};
     std::memcpy(host, &h, sizeof h);
     return d2h(s, (uint8_t *)host + sizeof h, s->node.base, s->node.state_bytes);
 }
@@ -929,6 +1083,7 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
     s->jstate = h.jstate;
     s->flow_steps = h.flow_steps;
     s->np_steps = h.np_steps;
+    s->p.psi = h.psi_on ? s->node.psi : nullptr;
     return CDI_OK;
 }
 

@@ -1,0 +1,301 @@
+// pot.hip -- the electric potential of Poisson's equation, Eq. (4), with the
+// charge density of Eq. (5) and the electrode's Dirichlet value (Sec. 2),
+// solved on the compacted fluid lattice by Jacobi-preconditioned conjugate
+// gradients.
+//
+// Discretisation (finite volumes, one unknown per fluid cell centre, psi in
+// thermal voltages): a face between two fluid cells carries psi_N - psi_P; a
+// face on an electrode voxel carries 2 (psi_e - psi_P) (the Dirichlet value
+// sits on the face, half a cell away); an inert face carries nothing; an x
+// end face is Dirichlet (value psi_x), field-free, or periodic. A cell
+// balances its face fluxes against the charge term src * sum_i z_i C_i, src =
+// kappa2 / (2 c0). As A psi = b: A_PP = number of fluid faces + 2 per
+// Dirichlet face, A_PN = -1 per fluid face, b_P = src sum z C + 2 sum psi_face.
+//
+// The CG vectors are FP64 in internal node order (stride P). Every kernel
+// runs G persistent workgroups; workgroup c (its XCD-contiguous position)
+// owns the contiguous tile range [c T / G, (c + 1) T / G), so an XCD sweeps
+// one contiguous eighth of the lattice and finds the tiles above and below
+// in its own L2. A dot product is one FP64 partial per workgroup; the kernel
+// that needs the total sums the G partials itself, in a fixed order, so
+// every workgroup derives the same alpha and beta and the result does not
+// depend on timing. Iteration k runs three kernels:
+//   spmv  q = A p, partial p.q
+//   axpy  alpha = rz_k / p.q; x += alpha p; r -= alpha q; partials r.z, r.r
+//   dir   stop when |r| <= tol |b|, else beta = rz_{k+1} / rz_k, p = z + beta p
+// with z = r / diag. The r.z partials alternate between two slots by the
+// parity of k, so no kernel overwrites a sum another workgroup of the same
+// kernel is still reading. After the stop every later launch returns at once.
+#include "cdi_internal.h"
+#include "device_common.h"
+#include "pot_internal.h"
+
+namespace cdi {
+
+namespace {
+
+// Partial-sum regions, G doubles each.
+enum { kRz0 = 0, kRz1 = 1, kRr = 2, kPq = 3, kBb = 4, kNd = 5, kRegions = 6 };
+
+__device__ inline void tile_range(int ntiles, int &t0, int &t1)
+{
+    const long long G = gridDim.x;
+    const long long c = xcd_tile(blockIdx.x, gridDim.x);
+    t0 = (int)(c * ntiles / G);
+    t1 = (int)((c + 1) * ntiles / G);
+}
+
+// Sum of v over the workgroup in a fixed order, returned to every thread.
+__device__ inline double wg_sum(double v, double *sm)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();  // sm may still be read from a previous call
+    if (lane == 0) sm[wave] = v;
+    __syncthreads();
+    double s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sm[w];
+    return s;
+}
+
+// Whether the solve has stopped, read once per workgroup so that all its
+// waves take the same branch (a stop may be recorded by workgroup 0 of the
+// running kernel; every workgroup then skips the same update either way).
+__device__ inline bool stopped(const double *state, int *flag)
+{
+    if (threadIdx.x == 0) *flag = state[kStDone] != 0.0;
+    __syncthreads();
+    return *flag != 0;
+}
+
+// Total of a partial-sum region (G values), the same in every workgroup.
+__device__ inline double region_sum(const double *part, int G, double *sm)
+{
+    double v = 0;
+    for (int k = threadIdx.x; k < G; k += blockDim.x) v += part[k];
+    return wg_sum(v, sm);
+}
+
+// Map values of the 2D face neighbours of node n, and its diagonal.
+template <class L>
+__device__ inline void node_faces(const PotArgs &a, int n, int (&m)[2 * L::D], int &diag)
+{
+    int x, y, z;
+    unpack_xyz(a.g, ldu(a.g.fluid, (uint32_t)n), x, y, z);
+    NbCtx c;
+    nb_ctx<L>(a.g, x, y, z, a.xbc[0] == kPsixPeriodic, c);
+    diag = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * L::D; ++k) {
+        // directions 1 .. 2D are the faces +x, -x, +y, -y (, +z, -z)
+        m[k] = nb_get<L>(a.g, c, k + 1);
+        if (m[k] >= 0)
+            diag += 1;
+        else if (m[k] == kElectrode)
+            diag += 2;
+        else if (m[k] == kOutside && a.xbc[k & 1 ? 0 : 1] == kPsixDirichlet)
+            diag += 2;
+    }
+}
+
+template <class L>
+__global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
+{
+    __shared__ double sm[kTile / 64];
+    int t0, t1;
+    tile_range(a.g.P / kTile, t0, t1);
+    const int P = a.g.P;
+    double rz = 0, rr = 0, bb = 0, nd = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int n = t * kTile + threadIdx.x;
+        double xv = 0, rv = 0, zv = 0;
+        int diag = 0;
+        if (n < a.g.n_f) {
+            int m[2 * L::D];
+            node_faces<L>(a, n, m, diag);
+            double b = a.src * ((double)a.z[0] * ldu(a.C, (uint32_t)n) +
+                                (double)a.z[1] * ldu(a.C, (uint32_t)(P + n)));
+            xv = a.psi0 ? (double)ldu(a.psi0, (uint32_t)n) : 0.0;
+            double ax = diag * xv;
+#pragma unroll
+            for (int k = 0; k < 2 * L::D; ++k) {
+                if (m[k] >= 0) {
+                    if (a.psi0) ax -= (double)ldu(a.psi0, (uint32_t)m[k]);
+                } else if (m[k] == kElectrode) {
+                    b += 2.0 * a.psi_e;
+                    nd += 1;
+                } else if (m[k] == kOutside && a.xbc[k & 1 ? 0 : 1] == kPsixDirichlet) {
+                    b += 2.0 * a.psi_x[k & 1 ? 0 : 1];
+                    nd += 1;
+                }
+            }
+            rv = b - ax;
+            zv = diag > 0 ? rv / diag : 0.0;
+            rz += rv * zv;
+            rr += rv * rv;
+            bb += b * b;
+        }
+        stu(a.x, (uint32_t)n, xv);
+        stu(a.r, (uint32_t)n, rv);
+        stu(a.p, (uint32_t)n, zv);
+        a.dg[n] = (uint8_t)diag;
+    }
+    const double s_rz = wg_sum(rz, sm), s_rr = wg_sum(rr, sm), s_bb = wg_sum(bb, sm);
+    const double s_nd = wg_sum(nd, sm);
+    if (threadIdx.x == 0) {
+        const int G = gridDim.x;
+        a.part[kRz0 * G + blockIdx.x] = s_rz;
+        a.part[kRr * G + blockIdx.x] = s_rr;
+        a.part[kBb * G + blockIdx.x] = s_bb;
+        a.part[kNd * G + blockIdx.x] = s_nd;
+    }
+}
+
+template <class L>
+__global__ __launch_bounds__(kTile) void pot_spmv_kernel(PotArgs a)
+{
+    __shared__ double sm[kTile / 64];
+    __shared__ int stop;
+    if (stopped(a.state, &stop)) return;
+    int t0, t1;
+    tile_range(a.g.P / kTile, t0, t1);
+    double pq = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int n = t * kTile + threadIdx.x;
+        if (n >= a.g.n_f) continue;
+        int m[2 * L::D], diag;
+        node_faces<L>(a, n, m, diag);
+        const double pn = ldu(a.p, (uint32_t)n);
+        double q = diag * pn;
+#pragma unroll
+        for (int k = 0; k < 2 * L::D; ++k)
+            if (m[k] >= 0) q -= ldu(a.p, (uint32_t)m[k]);
+        stu(a.q, (uint32_t)n, q);
+        pq += pn * q;
+    }
+    const double s = wg_sum(pq, sm);
+    if (threadIdx.x == 0) a.part[kPq * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
+{
+    __shared__ double sm[kTile / 64];
+    __shared__ int stop;
+    if (stopped(a.state, &stop)) return;
+    const int G = gridDim.x;
+    const double rz = region_sum(a.part + (k & 1 ? kRz1 : kRz0) * G, G, sm);
+    const double pq = region_sum(a.part + kPq * G, G, sm);
+    if (!(pq > 0.0) || !isfinite(rz / pq)) {  // breakdown: A p has no positive energy
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.state[kStDone] = kDoneBreakdown;
+        return;
+    }
+    const double alpha = rz / pq;
+    int t0, t1;
+    tile_range(a.g.P / kTile, t0, t1);
+    double rz1 = 0, rr = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int n = t * kTile + threadIdx.x;
+        if (n >= a.g.n_f) continue;
+        const double pn = ldu(a.p, (uint32_t)n), qn = ldu(a.q, (uint32_t)n);
+        stu(a.x, (uint32_t)n, ldu(a.x, (uint32_t)n) + alpha * pn);
+        const double rn = ldu(a.r, (uint32_t)n) - alpha * qn;
+        stu(a.r, (uint32_t)n, rn);
+        const int d = a.dg[n];
+        const double zn = d > 0 ? rn / d : 0.0;
+        rz1 += rn * zn;
+        rr += rn * rn;
+    }
+    const double s_rz = wg_sum(rz1, sm), s_rr = wg_sum(rr, sm);
+    if (threadIdx.x == 0) {
+        a.part[(k & 1 ? kRz0 : kRz1) * G + blockIdx.x] = s_rz;
+        a.part[kRr * G + blockIdx.x] = s_rr;
+    }
+}
+
+__global__ __launch_bounds__(kTile) void pot_dir_kernel(PotArgs a, int k)
+{
+    __shared__ double sm[kTile / 64];
+    __shared__ int stop;
+    if (stopped(a.state, &stop)) return;
+    const int G = gridDim.x;
+    const double rz_old = region_sum(a.part + (k & 1 ? kRz1 : kRz0) * G, G, sm);
+    const double rz_new = region_sum(a.part + (k & 1 ? kRz0 : kRz1) * G, G, sm);
+    const double rr = region_sum(a.part + kRr * G, G, sm);
+    const bool conv = rr <= a.state[kStTol2Bb];
+    const bool bad = !isfinite(rr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.state[kStIters] = k + 1;
+        a.state[kStRr] = rr;
+        if (conv || bad) a.state[kStDone] = bad ? kDoneDiverged : kDoneConverged;
+    }
+    if (conv || bad) return;
+    const double beta = rz_new / rz_old;
+    int t0, t1;
+    tile_range(a.g.P / kTile, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int n = t * kTile + threadIdx.x;
+        if (n >= a.g.n_f) continue;
+        const int d = a.dg[n];
+        const double zn = d > 0 ? ldu(a.r, (uint32_t)n) / d : 0.0;
+        stu(a.p, (uint32_t)n, zn + beta * ldu(a.p, (uint32_t)n));
+    }
+}
+
+// Totals of the start (one workgroup): |b|^2, |r0|^2, Dirichlet faces.
+__global__ __launch_bounds__(kTile) void pot_state_kernel(PotArgs a, int G, double tol)
+{
+    __shared__ double sm[kTile / 64];
+    const double bb = region_sum(a.part + kBb * G, G, sm);
+    const double rr = region_sum(a.part + kRr * G, G, sm);
+    const double nd = region_sum(a.part + kNd * G, G, sm);
+    if (threadIdx.x == 0) {
+        a.state[kStBb] = bb;
+        a.state[kStTol2Bb] = tol * tol * bb;
+        a.state[kStRr] = rr;
+        a.state[kStNdir] = nd;
+        a.state[kStIters] = 0;
+        a.state[kStDone] = rr <= tol * tol * bb ? kDoneConverged : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kTile) void pot_store_kernel(const double *x, float *psi, int n_f)
+{
+    const int n = blockIdx.x * kTile + threadIdx.x;
+    if (n < n_f) psi[n] = (float)x[n];
+}
+
+}  // namespace
+
+int pot_workgroups(int ntiles) { return ntiles < kPotMaxWorkgroups ? ntiles : kPotMaxWorkgroups; }
+
+uint64_t pot_part_doubles(int G) { return (uint64_t)kRegions * G; }
+
+hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStream_t s)
+{
+    if (dim == 2)
+        pot_setup_kernel<D2Q9><<<G, kTile, 0, s>>>(a);
+    else
+        pot_setup_kernel<D3Q19><<<G, kTile, 0, s>>>(a);
+    pot_state_kernel<<<1, kTile, 0, s>>>(a, G, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, hipStream_t s)
+{
+    if (dim == 2)
+        pot_spmv_kernel<D2Q9><<<G, kTile, 0, s>>>(a);
+    else
+        pot_spmv_kernel<D3Q19><<<G, kTile, 0, s>>>(a);
+    pot_axpy_kernel<<<G, kTile, 0, s>>>(a, k);
+    pot_dir_kernel<<<G, kTile, 0, s>>>(a, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_pot_store(const PotArgs &a, float *psi, hipStream_t s)
+{
+    const int tiles = a.g.P / kTile;
+    if (tiles > 0) pot_store_kernel<<<tiles, kTile, 0, s>>>(a.x, psi, a.g.n_f);
+    return hipGetLastError();
+}
+
+}  // namespace cdi

@@ -1,0 +1,46 @@
+// pot_internal.h -- argument block and launchers of the potential solve
+// (pot.hip): Poisson's equation, Eq. (4), with the charge of Eq. (5), by
+// Jacobi-preconditioned conjugate gradients on the compacted lattice.
+#pragma once
+
+#include "cdi_internal.h"
+
+namespace cdi {
+
+// x-end faces of the potential problem (same numbering as the public enum)
+constexpr int kPsixDirichlet = 0, kPsixNeumann = 1, kPsixPeriodic = 2;
+
+// persistent workgroups of every solve kernel (fewer when there are fewer tiles)
+constexpr int kPotMaxWorkgroups = 2048;
+
+// Solver state in device memory (doubles): stop code, iterations done,
+// |r|^2 of the last check, |b|^2, tol^2 |b|^2, Dirichlet faces counted.
+enum { kStDone = 0, kStIters = 1, kStRr = 2, kStBb = 3, kStTol2Bb = 4, kStNdir = 5, kStSlots = 8 };
+constexpr double kDoneConverged = 1, kDoneDiverged = 2, kDoneBreakdown = 3;
+
+struct PotArgs {
+    Grid g;
+    int xbc[2];          // kPsix* of the x = 0 and x = nx faces
+    double psi_e;        // electrode face value
+    double psi_x[2];     // Dirichlet x-face values
+    double src;          // kappa2 / (2 c0): charge term per unit sum z C
+    float z[2];          // valences
+    const float *C;      // concentrations, 2 planes of P
+    const float *psi0;   // start (the field in use) or nullptr (zero)
+    double *x, *r, *p, *q;  // CG vectors, P each
+    uint8_t *dg;         // diagonal of A per node (0 .. 12)
+    double *part;        // per-workgroup partial sums (pot_part_doubles)
+    double *state;       // kStSlots doubles
+};
+
+int pot_workgroups(int ntiles);
+uint64_t pot_part_doubles(int G);
+// r = b - A x0, z, p = z, the diagonal, and the state (stop code set when the
+// start already meets tol).
+hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStream_t s);
+// CG iteration k (spmv, axpy, dir); returns at once after a stop.
+hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, hipStream_t s);
+// psi[n] = (float) x[n] for the fluid nodes.
+hipError_t launch_pot_store(const PotArgs &a, float *psi, hipStream_t s);
+
+}  // namespace cdi

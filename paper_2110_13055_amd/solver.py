@@ -99,6 +99,29 @@ def plan(geom: Geometry, params: Optional[Params] = None) -> L.CPlanInfo:
     return info
 
 
+@dataclass
+class Potential:
+    """Settings of the potential solve (Poisson, Eq. 4-5; see cdi_potential in
+    include/cdi.h). Values in thermal voltages, lattice units."""
+    psi_electrode: float = 0.0
+    x_bc: tuple = (L.PSIX_NEUMANN, L.PSIX_NEUMANN)
+    psi_x: tuple = (0.0, 0.0)
+    kappa2: float = 0.0
+    tol: float = 1e-10
+    max_iter: int = 100000
+    check_every: int = 0
+    warm_start: bool = True
+
+    def to_c(self) -> L.CPotential:
+        c = L.CPotential()
+        c.psi_electrode = self.psi_electrode
+        c.x_bc[0], c.x_bc[1] = self.x_bc
+        c.psi_x[0], c.psi_x[1] = self.psi_x
+        c.kappa2, c.tol, c.max_iter = self.kappa2, self.tol, self.max_iter
+        c.check_every, c.warm_start = self.check_every, 1 if self.warm_start else 0
+        return c
+
+
 def _torch():
     import torch
     return torch
@@ -220,6 +243,35 @@ class Solver:
     def set_concentration(self, c: np.ndarray):
         a = np.ascontiguousarray(c, dtype=np.float32).reshape(2, self.n_fluid)
         L.check(self.lib.cdi_set_concentration(self.h, C.c_void_p(a.ctypes.data)), "cdi_set_concentration")
+
+    # -------------------------------------------------------------- potential
+    def _pot_ws(self):
+        nb = C.c_uint64()
+        L.check(self.lib.cdi_potential_bytes(self.h, C.byref(nb)), "cdi_potential_bytes")
+        ws = getattr(self, "_pot_buf", None)
+        if ws is None or ws.numel() < nb.value:
+            self._pot_buf = ws = _torch().empty(int(nb.value), dtype=_torch().uint8, device=self.device)
+        return ws
+
+    def solve_potential(self, pot: "Potential", allow_not_converged: bool = False):
+        """Solve Eq. (4)-(5) for the current concentrations; the result is the
+        potential of later ion steps. Returns (iterations, relative residual)."""
+        ws = self._pot_ws()
+        c, out = pot.to_c(), L.CPotentialResult()
+        rc = self.lib.cdi_solve_potential(self.h, C.byref(c), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                          C.byref(out))
+        L.check(rc, "cdi_solve_potential", (L.OK, L.E_NOT_CONVERGED) if allow_not_converged else (L.OK,))
+        return out.iterations, out.residual
+
+    def np_step_coupled(self, n: int, pot: "Potential", every: int = 1, fused: bool = False):
+        """n ion steps with the potential re-solved every `every` steps."""
+        ws = self._pot_ws()
+        c = pot.to_c()
+        L.check(self.lib.cdi_np_step_coupled(self.h, n, 1 if fused else 0, C.byref(c), every,
+                                             C.c_void_p(ws.data_ptr()), ws.numel()), "cdi_np_step_coupled")
+
+    def potential(self) -> np.ndarray:
+        return self._get("cdi_copy_potential", (self.n_fluid,), np.float32)
 
     # -------------------------------------------------------------- tuning
     def tuning(self):

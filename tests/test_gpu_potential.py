@@ -1,0 +1,190 @@
+"""GPU potential solve (Poisson, Eq. 4, with the charge of Eq. 5 and the
+electrode's Dirichlet value, Sec. 2) through the C ABI, against the FP64
+oracle and the closed forms of the discrete problem.
+
+Bar: the GPU stops at a relative residual of 1e-12 and the oracle at 1e-13,
+both in FP64; with the condition numbers of these lattices (below 1e4) the
+two iterates differ by far less than the FP32 rounding of the stored field,
+so the bound is a few FP32 ulps of the largest value: max |psi_gpu -
+psi_oracle| <= 1e-6 * max(1, max |psi|). Concentrations after ion steps on a
+solved potential meet the Nernst-Planck bar of the parity tests (1e-4 c0).
+"""
+import numpy as np
+import pytest
+
+from helpers import oracle_labels, oracle_solver
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2110_13055_amd")
+from paper_2110_13055_amd import _lib as L  # noqa: E402
+from paper_2110_13055_amd import Geometry, Params, Potential, Solver, preset  # noqa: E402
+
+TOL_GPU, TOL_ORACLE = 1e-12, 1e-13
+
+
+def bar(ref):
+    return 1e-6 * max(1.0, float(np.abs(ref).max()))
+
+
+def spheres(seed=7, n=40, phi=0.55, **pk):
+    g = Geometry(dim=3, nx=n, ny=n - 8, nz=n - 13, kind=L.SPHERES, porosity=phi, r_min=2.5, r_max=5.0,
+                 buffer_x=2, seed=seed)
+    return g, Params(u_in=5e-4, dpsi_vt=4.0, D=(0.05, 0.076), **pk)
+
+
+def both(g, p, pot, conc=None):
+    """Solve on the GPU and in the oracle with the same settings."""
+    s = Solver(g, p)
+    o = oracle_solver(g, p)
+    if conc is not None:
+        s.set_concentration(conc)
+        o.set_conc(conc.astype(np.float32).astype(np.float64))
+    it, res = s.solve_potential(pot)
+    assert res <= pot.tol
+    rc, _, _ = o.solve_potential(pot.psi_electrode, pot.x_bc, pot.psi_x, pot.kappa2, TOL_ORACLE)
+    assert rc == 0
+    return s, o, it
+
+
+@pytest.mark.parametrize("x_bc", [(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), (L.PSIX_DIRICHLET, L.PSIX_DIRICHLET),
+                                  (L.PSIX_NEUMANN, L.PSIX_NEUMANN), (L.PSIX_PERIODIC, L.PSIX_PERIODIC)])
+def test_laplace_3d_matches_oracle(x_bc):
+    g, p = spheres()
+    pot = Potential(psi_electrode=-1.5, x_bc=x_bc, psi_x=(0.0, 2.0), tol=TOL_GPU)
+    s, o, it = both(g, p, pot)
+    assert s.n_fluid % 256 != 0 and s.n_fluid > 8 * 256  # several tiles and a ragged tail
+    ref = o.potential()
+    assert np.abs(s.potential() - ref).max() <= bar(ref)
+
+
+@pytest.mark.parametrize("kappa2", [0.05, 2.0])
+def test_poisson_2d_with_charge_matches_oracle(kappa2):
+    g, p, _ = preset("channel2d_128x64")
+    rng = np.random.default_rng(11)
+    s0 = Solver(g, p)
+    conc = rng.uniform(0.2, 1.8, size=(2, s0.n_fluid)).astype(np.float32)
+    s0.close()
+    pot = Potential(psi_electrode=-3.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), kappa2=kappa2, tol=TOL_GPU)
+    s, o, _ = both(g, p, pot, conc)
+    ref = o.potential()
+    assert np.abs(s.potential() - ref).max() <= bar(ref)
+
+
+def test_closed_forms_on_the_gpu():
+    # linear profile between Dirichlet x faces, no electrode, inert y walls (2D)
+    nx, ny = 300, 10
+    lab = np.zeros((ny, nx), np.uint8)
+    lab[0, :] = lab[-1, :] = 2
+    g = Geometry(dim=2, nx=nx, ny=ny, kind=L.USER_LABELS, user_labels=lab.reshape(-1), walls_y=0, buffer_x=0)
+    p = Params(u_in=0.0, np_x_bc=L.NPX_CLOSED)
+    s = Solver(g, p)
+    s.solve_potential(Potential(x_bc=(L.PSIX_DIRICHLET, L.PSIX_DIRICHLET), psi_x=(5.0, -1.0), tol=1e-13))
+    _, fl = s.fluid_index()
+    exact = 5.0 - 6.0 * (fl % nx + 0.5) / nx
+    assert np.abs(s.potential() - exact).max() <= 1e-6 * 5
+    # uniform charge between electrode planes (3D): the parabola plus s/8
+    nx, ny, nz = 16, 22, 12
+    lab = np.zeros((nz, ny, nx), np.uint8)
+    lab[:, 0, :] = lab[:, -1, :] = 1
+    g = Geometry(dim=3, nx=nx, ny=ny, nz=nz, kind=L.USER_LABELS, user_labels=lab.reshape(-1), walls_y=0, buffer_x=0)
+    s = Solver(g, Params(u_in=0.0, np_x_bc=L.NPX_CLOSED))
+    s.set_concentration(np.vstack([np.full(s.n_fluid, 1.75), np.full(s.n_fluid, 1.0)]))
+    kappa2, psi_e = 0.4, 0.5
+    s.solve_potential(Potential(psi_electrode=psi_e, kappa2=kappa2, tol=1e-13))
+    _, fl = s.fluid_index()
+    y = (fl // nx) % ny
+    src = kappa2 / 2.0 * 0.75
+    exact = psi_e + 0.5 * src * (y - 0.5) * (ny - 1.5 - y) + src / 8.0
+    assert np.abs(s.potential() - exact).max() <= 1e-6 * np.abs(exact).max()
+
+
+def test_iterate_independent_of_check_interval_and_repeatable():
+    g, p = spheres(seed=9)
+    out = []
+    for ce in (1, 7, 32, 0):
+        s = Solver(g, p)
+        it, res = s.solve_potential(Potential(psi_electrode=2.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN),
+                                              tol=1e-9, check_every=ce, warm_start=False))
+        out.append((it, res, s.potential()))
+    for it, res, psi in out[1:]:
+        assert it == out[0][0] and res == out[0][1] and np.array_equal(psi, out[0][2])
+
+
+def test_warm_start_and_ion_steps_on_the_solved_field():
+    g, p, _ = preset("channel2d_128x64")
+    pot = Potential(psi_electrode=-4.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), tol=TOL_GPU)
+    s, o, it_cold = both(g, p, pot)
+    # a second solve starts from the stored FP32 field (relative residual near
+    # FP32 rounding, not zero), so it needs fewer iterations, not none
+    it_warm, _ = s.solve_potential(pot)
+    assert it_warm < it_cold // 2
+    assert np.abs(s.potential() - o.potential()).max() <= bar(o.potential())
+    # ion steps on the solved potential, oracle fed the same FP32 field
+    s.flow_steps(800)
+    o2 = oracle_solver(g, p, psi=s.potential().astype(np.float64))
+    o2.flow_steps(800)
+    s.np_step(400)
+    assert o2.np_steps(400) == 0
+    assert np.abs(s.concentration() - o2.conc()).max() <= 1e-4
+    ao = o2.adsorbed_total()
+    assert np.all(np.abs(s.adsorbed_total() - ao) <= 1e-4 * np.abs(ao))
+
+
+def test_coupled_pnp_matches_oracle():
+    g, p = spheres(seed=5, n=32)
+    p.u_in = 0.0
+    p.Ka = -1.0  # blocking electrode: the double layer forms without adsorption
+    kw = dict(psi_electrode=-2.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), kappa2=0.5)
+    s = Solver(g, p)
+    o = oracle_solver(g, p)
+    s.np_step_coupled(300, Potential(tol=TOL_GPU, **kw), every=3)
+    assert o.np_steps_coupled(300, every=3, tol=TOL_ORACLE, **kw) == 0
+    c, co = s.concentration(), o.conc()
+    assert np.abs(c - co).max() <= 1e-4
+    assert c[0].max() > 1.05  # cations gathered at the negative electrode
+    assert np.abs(s.potential() - o.potential()).max() <= 1e-4
+    b = s.mass_balance()
+    assert np.all(b[:, 1] == 0.0)
+
+
+def test_errors():
+    g, p = spheres()
+    s = Solver(g, p)
+    with pytest.raises(L.CdiError) as e:  # bad settings
+        s.solve_potential(Potential(x_bc=(L.PSIX_PERIODIC, L.PSIX_DIRICHLET)))
+    assert e.value.code == L.E_INVALID
+    with pytest.raises(L.CdiError) as e:
+        s.solve_potential(Potential(kappa2=-1.0))
+    assert e.value.code == L.E_INVALID
+    # singular: all fluid, periodic x, no electrode
+    lab = np.zeros((6, 8, 10), np.uint8)
+    g0 = Geometry(dim=3, nx=10, ny=8, nz=6, kind=L.USER_LABELS, user_labels=lab.reshape(-1), walls_y=0, buffer_x=0)
+    s0 = Solver(g0, Params(u_in=0.0, np_x_bc=L.NPX_PERIODIC))
+    with pytest.raises(L.CdiError) as e:
+        s0.solve_potential(Potential(x_bc=(L.PSIX_PERIODIC, L.PSIX_PERIODIC)))
+    assert e.value.code == L.E_INVALID
+    # not converged within the cap: the last iterate is installed
+    it, res = s.solve_potential(Potential(psi_electrode=1.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN),
+                                          tol=1e-14, max_iter=3, warm_start=False), allow_not_converged=True)
+    assert it == 3 and res > 1e-14
+    # workspace too small
+    import ctypes as C
+    import torch
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    c = Potential().to_c()
+    rc = s.lib.cdi_solve_potential(s.h, C.byref(c), C.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert rc == L.E_BUFFER
+
+
+def test_snapshot_carries_the_solved_field():
+    g, p = spheres(seed=4)
+    s = Solver(g, p)
+    s.solve_potential(Potential(psi_electrode=1.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN)))
+    blob = s.snapshot()
+    t = Solver(g, p)
+    t.restore(blob)
+    assert np.array_equal(t.potential(), s.potential())
+    s.np_step(50)
+    t.np_step(50)
+    assert np.array_equal(t.concentration(), s.concentration())
