@@ -93,17 +93,17 @@ def potential_rates(coupled_steps: int = 10):
     1e-8. Coupled: fused LBM + ion steps with the potential re-solved from the
     current charge (electrode at -4, kappa2 = 0.5, warm start, 1e-6) before
     every step.
-    Algorithmic bytes of one CG iteration per fluid node: spmv reads p, the
-    packed coordinates and the voxel map (4 B per voxel) and writes q; axpy
-    reads x, r, p, q and the diagonal byte and writes x, r; dir reads r, the
-    diagonal and p and writes p."""
+    Algorithmic bytes of one CG iteration per fluid node: the stencil kernel
+    reads r, the old direction, the diagonal byte and the six face-neighbour
+    indices and writes the new direction and q = A p (57 B); the update
+    kernel reads x, r, p, q and the diagonal byte and writes x, r (49 B)."""
     import torch
     import paper_2110_13055_amd as P
     g, p, _ = P.preset(WORKLOAD)
     s = P.Solver(g, p)
-    nf, nvox = s.n_fluid, g.n_vox
-    per_iter = 8 + 8 + 4 + 4.0 * nvox / nf + 49 + 25
-    out = {"algorithmic_bytes_per_node_iter": round(per_iter, 1)}
+    nf = s.n_fluid
+    per_iter = (8 + 8 + 1 + 24 + 8 + 8) + (32 + 1 + 16)
+    out = {"n_fluid": nf, "algorithmic_bytes_per_node_iter": round(per_iter, 1)}
     pot = P.Potential(psi_electrode=-20.0, x_bc=(P.PSIX_DIRICHLET, P.PSIX_NEUMANN), tol=1e-8,
                       warm_start=False, check_every=16)
     s.solve_potential(pot)  # first launches
@@ -223,6 +223,8 @@ def main():
                     help="population streaming of the FP32 / FP16 forms")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--no-potential", action="store_true", help="skip the potential-solve leg")
+    ap.add_argument("--potential-only", action="store_true",
+                    help="run only the potential-solve leg and print its record (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the serving trace (0 skips the serving leg)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -245,6 +247,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.potential_only:
+        print(json.dumps({"workload": WORKLOAD, "potential": potential_rates()}), flush=True)
+        return
     strm = P.STREAM_PULL if args.streaming == "pull" else P.STREAM_AA
     r32 = gpu_rates(P.FP32, args.steps, args.warmup, strm)
     r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup, strm)

@@ -345,8 +345,13 @@ typedef struct {
     double residual;       /* final |b - A psi|_2 / |b|_2 */
 } cdi_potential_result;
 
-/* Device workspace of the solve (4 FP64 vectors and a byte per node, plus
- * per-workgroup sums); needed only during the call. */
+/* Device workspace of the solve (5 FP64 vectors and a byte per node, plus
+ * per-workgroup sums); needed only during the call. The solve reads face
+ * neighbours from the solver's neighbour list when the potential's x ends
+ * are periodic exactly when the lattice's are, else through the voxel map;
+ * the result is the same. Iterates are bitwise repeatable on one device (the
+ * number of persistent workgroups, which fixes the summation order, follows
+ * the device's compute-unit count). */
 int cdi_potential_bytes(const cdi_solver *s, uint64_t *bytes);
 
 /* Solve for the potential of the current concentrations. ws: device, >=

@@ -19,13 +19,15 @@
 // in its own L2. A dot product is one FP64 partial per workgroup; the kernel
 // that needs the total sums the G partials itself, in a fixed order, so
 // every workgroup derives the same alpha and beta and the result does not
-// depend on timing. Iteration k runs three kernels:
-//   spmv  q = A p, partial p.q
-//   axpy  alpha = rz_k / p.q; x += alpha p; r -= alpha q; partials r.z, r.r
-//   dir   stop when |r| <= tol |b|, else beta = rz_{k+1} / rz_k, p = z + beta p
-// with z = r / diag. The r.z partials alternate between two slots by the
-// parity of k, so no kernel overwrites a sum another workgroup of the same
-// kernel is still reading. After the stop every later launch returns at once.
+// depend on timing. Iteration k runs two kernels:
+//   dirspmv  stop when |r_k| <= tol |b|; else beta = rz_k / rz_{k-1},
+//            p_k = z_k + beta p_{k-1} (z = r / diag), q = A p_k, partial p.q
+//   axpy     alpha = rz_k / p.q; x += alpha p_k; r -= alpha q; partials r.z, r.r
+// The search direction alternates between two buffers (a node reads its
+// neighbours' old p while they write their new one), and so do the r.z
+// partials, by the parity of k, so no kernel overwrites a value another
+// workgroup of the same kernel may still read. After the stop every later
+// launch returns at once.
 #include "cdi_internal.h"
 #include "device_common.h"
 #include "pot_internal.h"
@@ -151,32 +153,121 @@ __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
     }
 }
 
-template <class L>
-__global__ __launch_bounds__(kTile) void pot_spmv_kernel(PotArgs a)
+// Face neighbours (map values) of node n: from the neighbour list, or
+// looked up through the voxel map after the node's coordinates.
+template <class L, int NBR>
+__device__ inline void face_maps(const PotArgs &a, int n, int (&m)[2 * L::D])
 {
+    if (NBR) {
+#pragma unroll
+        for (int k = 0; k < 2 * L::D; ++k) m[k] = ldu(a.nbr, (uint32_t)(k * a.g.P + n));
+        return;
+    }
+    int x, y, z;
+    unpack_xyz(a.g, ldu(a.g.fluid, (uint32_t)n), x, y, z);
+    NbCtx c;
+    nb_ctx<L>(a.g, x, y, z, a.xbc[0] == kPsixPeriodic, c);
+#pragma unroll
+    for (int k = 0; k < 2 * L::D; ++k) m[k] = nb_get<L>(a.g, c, k + 1);
+}
+
+// The new search direction at one node: z + beta p with z = r / diag. Node n
+// evaluates it for itself and for its neighbours with this one expression,
+// so every copy of a node's value is the same number.
+__device__ inline double new_dir(double r, int d, double p, double beta)
+{
+    const double z = d > 0 ? r / d : 0.0;
+    return z + beta * p;
+}
+
+// Stop test on |r_k|^2 (the r.r partials of the last axpy); the same
+// decision in every workgroup. Workgroup 0 records it.
+__device__ inline bool stop_test(const PotArgs &a, int k, double *sm)
+{
+    const int G = gridDim.x;
+    const double rr = region_sum(a.part + kRr * G, G, sm);
+    const bool bad = !isfinite(rr);
+    const bool stop = bad || rr <= a.state[kStTol2Bb];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.state[kStIters] = k;
+        a.state[kStRr] = rr;
+        if (stop) a.state[kStDone] = bad ? kDoneDiverged : kDoneConverged;
+    }
+    return stop;
+}
+
+// Iteration k, first half: stop test on r_k; beta = rz_k / rz_{k-1} (0 at
+// k = 0, where the start's p already is z); p_k = z_k + beta p_{k-1} into
+// the other direction buffer; q = A p_k; partial p_k . q. A node needs p_k
+// of its fluid neighbours, which it forms from their r, diagonal and old p.
+// NN nodes per thread (tiles t and t + 1 of the range), all loads issued
+// before any arithmetic.
+template <class L, int NBR, int NN>
+__global__ __launch_bounds__(kTile) void pot_dirspmv_kernel(PotArgs a, int k)
+{
+    constexpr int F = 2 * L::D;
     __shared__ double sm[kTile / 64];
     __shared__ int stop;
     if (stopped(a.state, &stop)) return;
+    const int G = gridDim.x;
+    double beta = 0.0;
+    if (k > 0) {
+        if (stop_test(a, k, sm)) return;
+        beta = region_sum(a.part + (k & 1 ? kRz1 : kRz0) * G, G, sm) /
+               region_sum(a.part + (k & 1 ? kRz0 : kRz1) * G, G, sm);
+    }
+    const double *pold = k & 1 ? a.p2 : a.p;
+    double *pnew = k & 1 ? a.p : a.p2;
     int t0, t1;
     tile_range(a.g.P / kTile, t0, t1);
     double pq = 0;
-    for (int t = t0; t < t1; ++t) {
-        const int n = t * kTile + threadIdx.x;
-        if (n >= a.g.n_f) continue;
-        int m[2 * L::D], diag;
-        node_faces<L>(a, n, m, diag);
-        const double pn = ldu(a.p, (uint32_t)n);
-        double q = diag * pn;
+    for (int t = t0; t < t1; t += NN) {
+        int n[NN], m[NN][F];
+        bool act[NN];
 #pragma unroll
-        for (int k = 0; k < 2 * L::D; ++k)
-            if (m[k] >= 0) q -= ldu(a.p, (uint32_t)m[k]);
-        stu(a.q, (uint32_t)n, q);
-        pq += pn * q;
+        for (int j = 0; j < NN; ++j) {
+            n[j] = (t + j) * kTile + threadIdx.x;
+            act[j] = t + j < t1 && n[j] < a.g.n_f;
+            if (act[j])
+                face_maps<L, NBR>(a, n[j], m[j]);
+            else
+#pragma unroll
+                for (int f = 0; f < F; ++f) m[j][f] = kInert;
+        }
+        double r0[NN], p0[NN], rm[NN][F], pm[NN][F];
+        int d0[NN], dm[NN][F];
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            r0[j] = act[j] ? ldu(a.r, (uint32_t)n[j]) : 0.0;
+            p0[j] = act[j] ? ldu(pold, (uint32_t)n[j]) : 0.0;
+            d0[j] = act[j] ? a.dg[n[j]] : 0;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const bool fl = m[j][f] >= 0;
+                rm[j][f] = fl ? ldu(a.r, (uint32_t)m[j][f]) : 0.0;
+                pm[j][f] = fl ? ldu(pold, (uint32_t)m[j][f]) : 0.0;
+                dm[j][f] = fl ? a.dg[m[j][f]] : 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            if (!act[j]) continue;
+            const double pn = new_dir(r0[j], d0[j], p0[j], beta);
+            double q = d0[j] * pn;
+#pragma unroll
+            for (int f = 0; f < F; ++f)
+                if (m[j][f] >= 0) q -= new_dir(rm[j][f], dm[j][f], pm[j][f], beta);
+            stu(pnew, (uint32_t)n[j], pn);
+            stu(a.q, (uint32_t)n[j], q);
+            pq += pn * q;
+        }
     }
     const double s = wg_sum(pq, sm);
-    if (threadIdx.x == 0) a.part[kPq * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) a.part[kPq * G + blockIdx.x] = s;
 }
 
+// Iteration k, second half: alpha = rz_k / (p_k . q); x += alpha p_k;
+// r -= alpha q; partials rz_{k+1} (into the other r.z slot) and |r_{k+1}|^2.
 __global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
 {
     __shared__ double sm[kTile / 64];
@@ -190,13 +281,14 @@ __global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
         return;
     }
     const double alpha = rz / pq;
+    const double *pk = k & 1 ? a.p : a.p2;
     int t0, t1;
     tile_range(a.g.P / kTile, t0, t1);
     double rz1 = 0, rr = 0;
     for (int t = t0; t < t1; ++t) {
         const int n = t * kTile + threadIdx.x;
         if (n >= a.g.n_f) continue;
-        const double pn = ldu(a.p, (uint32_t)n), qn = ldu(a.q, (uint32_t)n);
+        const double pn = ldu(pk, (uint32_t)n), qn = ldu(a.q, (uint32_t)n);
         stu(a.x, (uint32_t)n, ldu(a.x, (uint32_t)n) + alpha * pn);
         const double rn = ldu(a.r, (uint32_t)n) - alpha * qn;
         stu(a.r, (uint32_t)n, rn);
@@ -212,32 +304,19 @@ __global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
     }
 }
 
-__global__ __launch_bounds__(kTile) void pot_dir_kernel(PotArgs a, int k)
+// The stop test of iteration k on its own (one workgroup), run after a batch
+// of iterations ending with iteration k - 1: records the same decision the
+// next iteration would take.
+__global__ __launch_bounds__(kTile) void pot_check_kernel(PotArgs a, int k, int G)
 {
     __shared__ double sm[kTile / 64];
-    __shared__ int stop;
-    if (stopped(a.state, &stop)) return;
-    const int G = gridDim.x;
-    const double rz_old = region_sum(a.part + (k & 1 ? kRz1 : kRz0) * G, G, sm);
-    const double rz_new = region_sum(a.part + (k & 1 ? kRz0 : kRz1) * G, G, sm);
+    if (a.state[kStDone] != 0.0) return;  // one workgroup: written only by earlier kernels
     const double rr = region_sum(a.part + kRr * G, G, sm);
-    const bool conv = rr <= a.state[kStTol2Bb];
-    const bool bad = !isfinite(rr);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.state[kStIters] = k + 1;
+    if (threadIdx.x == 0) {
+        const bool bad = !isfinite(rr);
+        a.state[kStIters] = k;
         a.state[kStRr] = rr;
-        if (conv || bad) a.state[kStDone] = bad ? kDoneDiverged : kDoneConverged;
-    }
-    if (conv || bad) return;
-    const double beta = rz_new / rz_old;
-    int t0, t1;
-    tile_range(a.g.P / kTile, t0, t1);
-    for (int t = t0; t < t1; ++t) {
-        const int n = t * kTile + threadIdx.x;
-        if (n >= a.g.n_f) continue;
-        const int d = a.dg[n];
-        const double zn = d > 0 ? ldu(a.r, (uint32_t)n) / d : 0.0;
-        stu(a.p, (uint32_t)n, zn + beta * ldu(a.p, (uint32_t)n));
+        if (bad || rr <= a.state[kStTol2Bb]) a.state[kStDone] = bad ? kDoneDiverged : kDoneConverged;
     }
 }
 
@@ -266,9 +345,31 @@ __global__ __launch_bounds__(kTile) void pot_store_kernel(const double *x, float
 
 }  // namespace
 
-int pot_workgroups(int ntiles) { return ntiles < kPotMaxWorkgroups ? ntiles : kPotMaxWorkgroups; }
+// nodes per thread of the stencil kernel
+constexpr int kPotNodes = 2;
 
-uint64_t pot_part_doubles(int G) { return (uint64_t)kRegions * G; }
+uint64_t pot_part_doubles() { return (uint64_t)kRegions * kPotMaxWorkgroups; }
+
+// As many persistent workgroups as the stencil kernel (the largest register
+// footprint of the solve) keeps resident on the device at once: a workgroup
+// that had to wait for a free slot would double the kernel's time.
+hipError_t pot_workgroups(int dim, int ntiles, bool nbr, int *G)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const void *k = dim == 2 ? (nbr ? (const void *)pot_dirspmv_kernel<D2Q9, 1, kPotNodes>
+                                    : (const void *)pot_dirspmv_kernel<D2Q9, 0, kPotNodes>)
+                             : (nbr ? (const void *)pot_dirspmv_kernel<D3Q19, 1, kPotNodes>
+                                    : (const void *)pot_dirspmv_kernel<D3Q19, 0, kPotNodes>);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTile, 0);
+    if (e != hipSuccess) return e;
+    long long g = (long long)cus * (per_cu > 0 ? per_cu : 1);
+    g = g < kPotMaxWorkgroups ? g : kPotMaxWorkgroups;
+    *G = (int)(ntiles < g ? ntiles : g);
+    return hipSuccess;
+}
 
 hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStream_t s)
 {
@@ -280,14 +381,28 @@ hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStr
     return hipGetLastError();
 }
 
+template <class L>
+void pot_iter_l(const PotArgs &a, int G, int k, hipStream_t s)
+{
+    if (a.nbr)
+        pot_dirspmv_kernel<L, 1, kPotNodes><<<G, kTile, 0, s>>>(a, k);
+    else
+        pot_dirspmv_kernel<L, 0, kPotNodes><<<G, kTile, 0, s>>>(a, k);
+    pot_axpy_kernel<<<G, kTile, 0, s>>>(a, k);
+}
+
 hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, hipStream_t s)
 {
     if (dim == 2)
-        pot_spmv_kernel<D2Q9><<<G, kTile, 0, s>>>(a);
+        pot_iter_l<D2Q9>(a, G, k, s);
     else
-        pot_spmv_kernel<D3Q19><<<G, kTile, 0, s>>>(a);
-    pot_axpy_kernel<<<G, kTile, 0, s>>>(a, k);
-    pot_dir_kernel<<<G, kTile, 0, s>>>(a, k);
+        pot_iter_l<D3Q19>(a, G, k, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pot_check(const PotArgs &a, int G, int k, hipStream_t s)
+{
+    pot_check_kernel<<<1, kTile, 0, s>>>(a, k, G);
     return hipGetLastError();
 }
 

@@ -10,8 +10,8 @@ namespace cdi {
 // x-end faces of the potential problem (same numbering as the public enum)
 constexpr int kPsixDirichlet = 0, kPsixNeumann = 1, kPsixPeriodic = 2;
 
-// persistent workgroups of every solve kernel (fewer when there are fewer tiles)
-constexpr int kPotMaxWorkgroups = 2048;
+// upper bound of the persistent workgroups of the solve kernels
+constexpr int kPotMaxWorkgroups = 4096;
 
 // Solver state in device memory (doubles): stop code, iterations done,
 // |r|^2 of the last check, |b|^2, tol^2 |b|^2, Dirichlet faces counted.
@@ -27,19 +27,27 @@ struct PotArgs {
     float z[2];          // valences
     const float *C;      // concentrations, 2 planes of P
     const float *psi0;   // start (the field in use) or nullptr (zero)
-    double *x, *r, *p, *q;  // CG vectors, P each
+    double *x, *r, *q;   // CG vectors, P each
+    double *p, *p2;      // search direction, alternating between two buffers
+    const int *nbr;      // face neighbours (planes 0 .. 2D-1 of the node list) or nullptr
     uint8_t *dg;         // diagonal of A per node (0 .. 12)
     double *part;        // per-workgroup partial sums (pot_part_doubles)
     double *state;       // kStSlots doubles
 };
 
-int pot_workgroups(int ntiles);
-uint64_t pot_part_doubles(int G);
+// Persistent workgroups of a solve on the current device (at most
+// kPotMaxWorkgroups, at most one per tile).
+hipError_t pot_workgroups(int dim, int ntiles, bool nbr, int *G);
+// Doubles of the partial-sum area (sized for kPotMaxWorkgroups).
+uint64_t pot_part_doubles();
 // r = b - A x0, z, p = z, the diagonal, and the state (stop code set when the
 // start already meets tol).
 hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStream_t s);
-// CG iteration k (spmv, axpy, dir); returns at once after a stop.
+// CG iteration k (stop test, direction and A p; then the x and r updates);
+// returns at once after a stop.
 hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, hipStream_t s);
+// The stop test of iteration k alone (after iterations up to k - 1).
+hipError_t launch_pot_check(const PotArgs &a, int G, int k, hipStream_t s);
 // psi[n] = (float) x[n] for the fluid nodes.
 hipError_t launch_pot_store(const PotArgs &a, float *psi, hipStream_t s);
 

@@ -153,13 +153,100 @@ def main():
     ap.add_argument("--md", required=True)
     ap.add_argument("--json", required=True)
     ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--potential", action="store_true",
+                    help="summarise the potential-solve kernels (bench.py --potential-only)")
     a = ap.parse_args()
-    rec, md = summarise(a.trace, a.fetch, a.write, a.bench_log, a.copy_mib, a.command)
+    fn = summarise_potential if a.potential else summarise
+    rec, md = fn(a.trace, a.fetch, a.write, a.bench_log, a.copy_mib, a.command)
     with open(a.json, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     with open(a.md, "w") as fh:
         fh.write(md)
+
+
+
+# ---------------------------------------------------------------- potential solve
+
+POT_KERNELS = {"pot_dirspmv_kernel": "direction + A p (stencil)", "pot_axpy_kernel": "x, r update"}
+
+
+def _pot_kernel(name: str):
+    for k in POT_KERNELS:
+        if k in name:
+            return k
+    return None
+
+
+def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
+    """Per-iteration kernels of the potential solve: mean duration, HBM bytes
+    per fluid node and GB/s over the dispatches that did work (launches after
+    the device-side stop return at once and are left out: below 5% of the
+    kernel's longest dispatch)."""
+    durs = defaultdict(list)
+    for r in _csv(_find(trace, "kernel_trace.csv")):
+        k = _pot_kernel(r["Kernel_Name"])
+        if k:
+            durs[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    n_fluid = None
+    with open(bench_log) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"potential"' in line:
+                n_fluid = json.loads(line)["potential"]["n_fluid"]
+    if n_fluid is None:
+        raise ValueError("bench log holds no potential record with n_fluid")
+
+    def counters(d, counter):
+        per, copy = defaultdict(list), None
+        for r in _csv(_find(d, "counter_collection.csv")):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in r["Kernel_Name"]:
+                copy = v if copy is None or v > copy else copy
+                continue
+            k = _pot_kernel(r["Kernel_Name"])
+            if k:
+                per[k].append(v)
+        out = {}
+        for k, v in per.items():
+            top = max(v)
+            work = [x for x in v if x >= 0.05 * top]
+            out[k] = sum(work) / len(work)
+        return out, copy
+
+    fr, fcopy = counters(fetch, "FETCH_SIZE")
+    wr, wcopy = counters(write, "WRITE_SIZE")
+    copy_bytes = copy_mib * 1024.0 * 1024.0
+    fscale, wscale = copy_bytes / fcopy, copy_bytes / wcopy
+    rows = []
+    for k in POT_KERNELS:
+        if k not in durs:
+            continue
+        top = max(durs[k])
+        work = [x for x in durs[k] if x >= 0.05 * top]
+        dur = sum(work) / len(work)
+        fb, wb = fr.get(k, float("nan")) * fscale, wr.get(k, float("nan")) * wscale
+        rows.append(dict(kernel=k, role=POT_KERNELS[k], dispatches=len(work), avg_ms=dur * 1e3,
+                         read_per_node=fb / n_fluid, write_per_node=wb / n_fluid, gbs=(fb + wb) / dur / 1e9))
+    per_iter_ms = sum(r["avg_ms"] for r in rows)
+    per_iter_bytes = sum((r["read_per_node"] + r["write_per_node"]) for r in rows)
+    record = dict(n_fluid=n_fluid, counter_scale={"FETCH_SIZE": fscale, "WRITE_SIZE": wscale},
+                  kernels=rows, iteration_ms=per_iter_ms, iteration_bytes_per_node=per_iter_bytes,
+                  commands=list(commands))
+    md = [f"# Potential solve (Jacobi-PCG) on the 512^3 electrode ({n_fluid} fluid nodes)", "",
+          "Counter scale from the copy probe: FETCH_SIZE x "
+          f"{fscale:.1f} B, WRITE_SIZE x {wscale:.1f} B per unit.", "",
+          "| kernel | role | working dispatches | avg ms | HBM read B/node | HBM write B/node | GB/s |",
+          "|---|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        md.append(f"| {r['kernel']} | {r['role']} | {r['dispatches']} | {r['avg_ms']:.3f} | "
+                  f"{r['read_per_node']:.1f} | {r['write_per_node']:.1f} | {r['gbs']:.0f} |")
+    md += ["", f"One CG iteration: {per_iter_ms:.3f} ms, {per_iter_bytes:.1f} HBM bytes per fluid node.", "",
+           "Commands (repository root; the three runs of the same bench command):", ""]
+    md += [f"    {c}" for c in commands]
+    return record, "\n".join(md) + "\n"
 
 
 if __name__ == "__main__":
