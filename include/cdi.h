@@ -48,7 +48,7 @@ extern "C" {
 #define CDI_E_BUFFER (-7)        /* workspace too small or misaligned */
 
 /* ---------------------------------------------------------------- enums */
-enum { CDI_DISKS = 0, CDI_SPHERES = 1, CDI_USER_LABELS = 2 };
+enum { CDI_DISKS = 0, CDI_SPHERES = 1, CDI_USER_LABELS = 2, CDI_FIBRES = 3 };
 enum { CDI_INLET_OUTLET = 0, CDI_BODY_FORCE = 1 };
 enum { CDI_EQ_QUADRATIC = 0, CDI_EQ_LINEAR = 1 };
 enum { CDI_NPX_INLET_OUTLET = 0, CDI_NPX_PERIODIC = 1, CDI_NPX_CLOSED = 2, CDI_NPX_DIRICHLET = 3 };
@@ -63,9 +63,15 @@ enum { CDI_STREAM_AA = 0, CDI_STREAM_PULL = 1 };
  *   seed         SplitMix64 seed of the primitive generator
  *   kind         CDI_DISKS (2D, non-overlapping, random sequential addition),
  *                CDI_SPHERES (3D, overlapping, Boolean model, periodic y/z),
- *                CDI_USER_LABELS (labels copied from user_labels)
+ *                CDI_USER_LABELS (labels copied from user_labels),
+ *                CDI_FIBRES (3D straight overlapping fibres, Sec. 5: each a
+ *                random core line through a random point, extended to the
+ *                domain faces, every voxel within the radius solid; added
+ *                until the Boolean-model porosity reaches the target; no
+ *                wrap; edges <= 1024, r_max <= 64)
  *   porosity     target pore fraction over all voxels
- *   r_min,r_max  primitive radius range (lattice units)
+ *   r_min,r_max  primitive radius range (lattice units; fibres: half the
+ *                fibre diameter)
  *   min_gap      disks only: minimum surface gap (lattice units)
  *   walls_y      2D only: rows 0 and ny-1 are inert walls (else y periodic)
  *   buffer_x     always-fluid planes at each x end (>= 2 with inlet/outlet)

@@ -10,6 +10,8 @@ from .oracle import (  # noqa: F401
     build,
     compact,
     disks,
+    fibres,
+    voxelize_fibres,
     library,
     spheres,
     sphere_count,

@@ -97,6 +97,37 @@ int oracle_voxelize(int dim, int nx, int ny, int nz, int walls_y, int buffer_x,
     return ORACLE_OK;
 }
 
+/* Straight fibres (Sec. 5): a voxel of the interior slab is electrode iff
+ * its centre c lies within r of some fibre's infinite core line o + t d, i.e.
+ * |(c - o) x d|^2 <= r^2 |d|^2, in exact integer arithmetic (1/256 units).
+ * Every voxel is tested against every fibre. */
+int oracle_voxelize_fibres(int nx, int ny, int nz, int buffer_x, const int64_t *fibres, int64_t nfib,
+                           uint8_t *labels)
+{
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    for (int64_t v = 0; v < nvox; ++v) labels[v] = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nz; ++k) {
+        for (int j = 0; j < ny; ++j) {
+            for (int i = buffer_x; i < nx - buffer_x; ++i) {
+                const int64_t c[3] = {128 * (2 * (int64_t)i + 1), 128 * (2 * (int64_t)j + 1),
+                                      128 * (2 * (int64_t)k + 1)};
+                for (int64_t f = 0; f < nfib; ++f) {
+                    const int64_t *F = fibres + 8 * f;
+                    const int64_t vx = c[0] - F[1], vy = c[1] - F[2], vz = c[2] - F[3];
+                    const int64_t dx = F[4], dy = F[5], dz = F[6];
+                    const int64_t ax = vy * dz - vz * dy, ay = vz * dx - vx * dz, az = vx * dy - vy * dx;
+                    if (ax * ax + ay * ay + az * az <= F[0] * F[0] * (dx * dx + dy * dy + dz * dz)) {
+                        labels[((int64_t)k * ny + j) * nx + i] = 1;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    return ORACLE_OK;
+}
+
 int64_t oracle_compact(const uint8_t *labels, int64_t nvox, int32_t *map, int32_t *fluid)
 {
     int64_t n = 0;

@@ -75,6 +75,13 @@ typedef struct {
 int oracle_voxelize(int dim, int nx, int ny, int nz, int walls_y, int buffer_x,
                     const int64_t *prims, int64_t nprims, uint8_t *labels);
 
+/* Voxelise straight fibres (8 int64 each: r, ox, oy, oz, dx, dy, dz, unused;
+ * lengths in 1/256 lattice units, d an integer direction): a voxel with
+ * buffer_x <= x < nx - buffer_x is electrode (1) iff its centre lies within r
+ * of some fibre's infinite core line; no wrap. */
+int oracle_voxelize_fibres(int nx, int ny, int nz, int buffer_x, const int64_t *fibres, int64_t nfib,
+                           uint8_t *labels);
+
 /* Rank fluid voxels in lexicographic (x fastest) order. map[v] = rank, or -1
  * for electrode, -2 for inert voxels. fluid[rank] = v. Returns N_f. */
 int64_t oracle_compact(const uint8_t *labels, int64_t nvox, int32_t *map, int32_t *fluid);

@@ -92,6 +92,8 @@ def library():
             "geomgen_spheres": (I, [I, I, I, I, C.c_uint64, D, D, D, P, P]),
             "geomgen_sphere_count": (I64, [I, I, I, I, D, D, D]),
             "geomgen_free": (None, [P]),
+            "geomgen_fibres": (I, [I, I, I, I, C.c_uint64, D, D, D, P, P]),
+            "oracle_voxelize_fibres": (I, [I, I, I, I, P, I64, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -142,6 +144,28 @@ def spheres(nx, ny, nz, buffer_x, seed, porosity, r_min, r_max):
 
 def sphere_count(nx, ny, nz, buffer_x, porosity, r_min, r_max) -> int:
     return int(library().geomgen_sphere_count(nx, ny, nz, buffer_x, porosity, r_min, r_max))
+
+
+def fibres(nx, ny, nz, buffer_x, seed, porosity, r_min, r_max):
+    """Seeded straight fibres -> int64[n, 8] (r, ox, oy, oz, dx, dy, dz, 0)."""
+    lib = library()
+    pp, n = C.c_void_p(), C.c_int64()
+    rc = lib.geomgen_fibres(nx, ny, nz, buffer_x, seed, porosity, r_min, r_max, C.byref(pp), C.byref(n))
+    if rc != 0:
+        raise RuntimeError(f"geomgen_fibres failed rc={rc}")
+    buf = (C.c_int64 * (8 * n.value)).from_address(pp.value)
+    arr = np.frombuffer(buf, dtype=np.int64).reshape(n.value, 8).copy()
+    lib.geomgen_free(pp)
+    return arr
+
+
+def voxelize_fibres(nx, ny, nz, buffer_x, fib) -> np.ndarray:
+    fib = np.ascontiguousarray(fib, dtype=np.int64).reshape(-1, 8)
+    labels = np.zeros(nx * ny * nz, dtype=np.uint8)
+    rc = library().oracle_voxelize_fibres(nx, ny, nz, buffer_x, _ptr(fib), fib.shape[0], _ptr(labels))
+    if rc != 0:
+        raise RuntimeError("oracle_voxelize_fibres failed")
+    return labels
 
 
 def voxelize(dim, nx, ny, nz, walls_y, buffer_x, prims) -> np.ndarray:

@@ -8,10 +8,10 @@ adsorption law as a face flux (Liu, Waugh, Komini Babu, Spendelow, Kang,
 """
 from . import _lib  # noqa: F401
 from ._lib import (  # noqa: F401
-    BODY_FORCE, DISKS, EQ_LINEAR, EQ_QUADRATIC, FP16_DEV, FP32, INLET_OUTLET, MOMENTS, NPX_CLOSED,
+    BODY_FORCE, DISKS, FIBRES, EQ_LINEAR, EQ_QUADRATIC, FP16_DEV, FP32, INLET_OUTLET, MOMENTS, NPX_CLOSED,
     NPX_DIRICHLET, NPX_INLET_OUTLET, NPX_PERIODIC, SPHERES, USER_LABELS, CdiError,
     MODE_FLOW, MODE_FUSED, MODE_IDLE, MODE_IONS, STREAM_AA, STREAM_PULL, PSIX_DIRICHLET, PSIX_NEUMANN,
     PSIX_PERIODIC,
 )
 from .solver import Batch, Geometry, Params, Potential, Solver, plan  # noqa: F401
-from .presets import PRESETS, batch_instances, preset, serving_requests  # noqa: F401
+from .presets import PRESETS, batch_instances, fibre_case, fibre_sweep, preset, serving_requests  # noqa: F401

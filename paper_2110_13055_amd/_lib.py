@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libcdi.so")
 
 OK, STAGNATED = 0, 1
 E_INVALID, E_GEOMETRY, E_UNSTABLE, E_NOT_CONVERGED, E_DIVERGED, E_DEVICE, E_BUFFER = -1, -2, -3, -4, -5, -6, -7
-DISKS, SPHERES, USER_LABELS = 0, 1, 2
+DISKS, SPHERES, USER_LABELS, FIBRES = 0, 1, 2, 3
 INLET_OUTLET, BODY_FORCE = 0, 1
 EQ_QUADRATIC, EQ_LINEAR = 0, 1
 NPX_INLET_OUTLET, NPX_PERIODIC, NPX_CLOSED, NPX_DIRICHLET = 0, 1, 2, 3

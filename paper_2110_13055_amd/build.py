@@ -47,7 +47,9 @@ def build(verbose: bool = True) -> str:
     bdir = os.path.join(ROOT, "_build")
     os.makedirs(bdir, exist_ok=True)
     gen_o = os.path.join(bdir, "geomgen.o")
-    _run(["gcc", "-O2", "-std=c11", "-fPIC", "-c", os.path.join(HERE, "inputs", "geomgen.c"),
+    # the generator's porosity stop rule is floating point: the same source,
+    # compiler and flags as the CPU reference's copy, no contraction
+    _run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-c", os.path.join(HERE, "inputs", "geomgen.c"),
           "-o", gen_o])
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
     incs = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),

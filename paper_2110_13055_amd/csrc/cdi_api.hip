@@ -4,6 +4,7 @@
 // kernels of geometry.hip and step.hip.
 #include "cdi.h"
 #include "cdi_internal.h"
+#include "geometry_internal.h"
 #include "geomgen.h"
 #include "pot_internal.h"
 
@@ -86,7 +87,11 @@ int check_geometry(const cdi_geometry *g)
     }
     if (g->kind == CDI_DISKS && g->dim != 2) return fail(CDI_E_INVALID, "disks need dim 2");
     if (g->kind == CDI_SPHERES && g->dim != 3) return fail(CDI_E_INVALID, "spheres need dim 3");
-    if (g->kind != CDI_DISKS && g->kind != CDI_SPHERES) return fail(CDI_E_INVALID, "unknown kind");
+    if (g->kind == CDI_FIBRES && g->dim != 3) return fail(CDI_E_INVALID, "fibres need dim 3");
+    if (g->kind != CDI_DISKS && g->kind != CDI_SPHERES && g->kind != CDI_FIBRES)
+        return fail(CDI_E_INVALID, "unknown kind");
+    if (g->kind == CDI_FIBRES && (g->nx > 1024 || g->ny > 1024 || nz > 1024 || g->r_max > 64))
+        return fail(CDI_E_INVALID, "fibres: lattice edges <= 1024 and r_max <= 64 (exact int64 inside test)");
     if (!(g->porosity > 0 && g->porosity <= 1)) return fail(CDI_E_INVALID, "porosity out of (0, 1]");
     if (!(g->r_min > 0 && g->r_max >= g->r_min)) return fail(CDI_E_INVALID, "bad radius range");
     if (g->buffer_x < 0 || 2 * g->buffer_x >= g->nx) return fail(CDI_E_INVALID, "bad buffer_x");
@@ -134,6 +139,20 @@ int make_prims(const cdi_geometry *g, std::vector<geomgen_prim> &out, int64_t *n
     }
     if (rc == GEOMGEN_E_JAMMED) return fail(CDI_E_GEOMETRY, "random sequential addition jammed before the porosity");
     if (rc != GEOMGEN_OK) return fail(CDI_E_INVALID, "primitive generator rejected the geometry (rc %d)", rc);
+    out.assign(pp, pp + n);
+    geomgen_free(pp);
+    return CDI_OK;
+}
+
+// Seeded straight fibres of a CDI_FIBRES geometry (host).
+int make_fibres(const cdi_geometry *g, std::vector<geomgen_fibre> &out)
+{
+    out.clear();
+    geomgen_fibre *pp = nullptr;
+    int64_t n = 0;
+    const int rc = geomgen_fibres(g->nx, g->ny, g->nz, g->buffer_x, g->seed, g->porosity, g->r_min, g->r_max,
+                                  &pp, &n);
+    if (rc != GEOMGEN_OK) return fail(CDI_E_INVALID, "fibre generator rejected the geometry (rc %d)", rc);
     out.assign(pp, pp + n);
     geomgen_free(pp);
     return CDI_OK;
@@ -197,7 +216,7 @@ VoxLayout vox_layout(void *ws, const cdi_geometry *g, int64_t nprims)
     L.blk2 = c.take<int>(4ull * (uint64_t)compact_blocks(E));
     L.nfluid = c.take<int64_t>(8);
     L.nfluid2 = c.take<int64_t>(8);
-    L.prims = c.take<int64_t>(32ull * (uint64_t)(nprims > 0 ? nprims : 1));
+    L.prims = c.take<int64_t>(64ull * (uint64_t)(nprims > 0 ? nprims : 1));  // 8 int64 per fibre, 4 otherwise
     L.bytes = c.off;
     return L;
 }
@@ -503,6 +522,11 @@ int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *
                                       geom->r_min, geom->r_max);
         if (nprims < 0) return fail(CDI_E_INVALID, "sphere generator rejected the geometry");
         nf_est = (int64_t)llround(geom->porosity * (double)nvox);
+    } else if (geom->kind == CDI_FIBRES) {
+        std::vector<geomgen_fibre> fb;
+        if ((rc = make_fibres(geom, fb)) != CDI_OK) return rc;
+        nprims = (int64_t)fb.size();
+        nf_est = (int64_t)llround(geom->porosity * (double)nvox);
     } else {
         nf_est = 0;
         for (int64_t v = 0; v < nvox; ++v) nf_est += geom->user_labels[v] == 0;
@@ -529,8 +553,13 @@ int cdi_build_geometry(const cdi_geometry *geom, void *vox_ws, uint64_t vox_ws_b
     if (!vox_ws || ((uintptr_t)vox_ws % kAlign)) return fail(CDI_E_BUFFER, "vox_ws NULL or not 256-byte aligned");
     const int64_t nvox = geom_nvox(geom);
     std::vector<geomgen_prim> pr;
-    if ((rc = make_prims(geom, pr, nullptr)) != CDI_OK) return rc;
-    const int64_t nprims = (int64_t)pr.size();
+    std::vector<geomgen_fibre> fb;
+    if (geom->kind == CDI_FIBRES) {
+        if ((rc = make_fibres(geom, fb)) != CDI_OK) return rc;
+    } else if ((rc = make_prims(geom, pr, nullptr)) != CDI_OK) {
+        return rc;
+    }
+    const int64_t nprims = geom->kind == CDI_FIBRES ? (int64_t)fb.size() : (int64_t)pr.size();
     VoxLayout L = vox_layout(vox_ws, geom, nprims);
     if (vox_ws_bytes < L.bytes) return fail(CDI_E_BUFFER, "vox_ws too small: %llu < %llu",
                                             (unsigned long long)vox_ws_bytes, (unsigned long long)L.bytes);
@@ -538,6 +567,12 @@ int cdi_build_geometry(const cdi_geometry *geom, void *vox_ws, uint64_t vox_ws_b
     const int nz = geom->dim == 2 ? 1 : geom->nz;
     if (geom->kind == CDI_USER_LABELS) {
         HIPCHK(hipMemcpyAsync(L.labels, geom->user_labels, (size_t)nvox, hipMemcpyHostToDevice, st));
+    } else if (geom->kind == CDI_FIBRES) {
+        if (nprims > 0)
+            HIPCHK(hipMemcpyAsync(L.prims, fb.data(), sizeof(geomgen_fibre) * (size_t)nprims,
+                                  hipMemcpyHostToDevice, st));
+        HIPCHK(launch_init_labels(L.labels, geom->nx, geom->ny, nz, 0, st));
+        HIPCHK(launch_voxelize_fibres(L.labels, L.prims, nprims, geom->nx, geom->ny, nz, geom->buffer_x, st));
     } else {
         if (nprims > 0)
             HIPCHK(hipMemcpyAsync(L.prims, pr.data(), sizeof(geomgen_prim) * (size_t)nprims,
@@ -593,6 +628,10 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     } else if (geom->kind == CDI_SPHERES) {
         nprims = geomgen_sphere_count(geom->nx, geom->ny, geom->nz, geom->buffer_x, geom->porosity,
                                       geom->r_min, geom->r_max);
+    } else if (geom->kind == CDI_FIBRES) {
+        std::vector<geomgen_fibre> fb;
+        if ((rc = make_fibres(geom, fb)) != CDI_OK) return rc;
+        nprims = (int64_t)fb.size();
     }
     VoxLayout V = vox_layout(vox_ws, geom, nprims);
     if (vox_ws_bytes < V.bytes) return fail(CDI_E_BUFFER, "vox_ws too small");

@@ -2,11 +2,13 @@
 // numbering (the paper's image-voxel grid, Sec. 2), plus small fill kernels.
 //
 // Labels: 0 pore, 1 adsorbing electrode, 2 inert wall. A voxel (i,j,k) is
-// solid iff some primitive contains its centre, tested exactly in int64 on
-// 1/256-lattice-unit coordinates (centre of voxel i is 128*(2i+1)).
+// solid iff some primitive (disk, sphere, or straight fibre of Sec. 5)
+// contains its centre, tested exactly in int64 on 1/256-lattice-unit
+// coordinates (centre of voxel i is 128*(2i+1)).
 // Fluid voxels are numbered in lexicographic order, x fastest; the result is
 // independent of scheduling (a three-pass block scan).
 #include "cdi_internal.h"
+#include "geometry_internal.h"
 
 namespace cdi {
 
@@ -74,6 +76,51 @@ __global__ void voxelize_kernel(uint8_t *labels, const int64_t *prims, int dim, 
             uint8_t *l = labels + ((int64_t)kk * ny + jj) * nx + i;
             if (*l != 2) *l = 1;
         }
+    }
+}
+
+// Straight fibres, one block per fibre. A voxel centre within r of the core
+// line o + t d lies, in its plane across the dominant axis a of d, within
+// r |d| / |d_a| of the point where the line crosses that plane (the in-plane
+// distance is at most the 3D distance divided by |d_a| / |d|). Each thread
+// takes (plane, window cell) pairs of a window one voxel wider than that
+// radius; the exact integer test |(c - o) x d|^2 <= r^2 |d|^2 decides. No
+// wrap; x is clipped to the interior slab.
+__global__ void voxelize_fibres_kernel(uint8_t *labels, const int64_t *fib, int nx, int ny, int nz, int bx)
+{
+    const int64_t *F = fib + 8 * (int64_t)blockIdx.x;
+    const int64_t r = F[0];
+    const int64_t o[3] = {F[1], F[2], F[3]}, d[3] = {F[4], F[5], F[6]};
+    int a = 0;
+    for (int k = 1; k < 3; ++k)
+        if ((d[k] < 0 ? -d[k] : d[k]) > (d[a] < 0 ? -d[a] : d[a])) a = k;
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const int lo[3] = {bx, 0, 0}, hi[3] = {nx - bx, ny, nz};
+    const int64_t dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const int64_t r2dd = r * r * dd;
+    const double da = (double)(d[a] < 0 ? -d[a] : d[a]);
+    const int W = (int)ceil((double)r / 256.0 * sqrt((double)dd) / da) + 1;
+    const int side = 2 * W + 1;
+    const int64_t cells = (int64_t)side * side;
+    const int64_t total = (int64_t)(hi[a] - lo[a]) * cells;
+    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) {
+        const int ia = lo[a] + (int)(t / cells);
+        const int rem = (int)(t % cells);
+        const double tt = (double)(128 * (2 * (int64_t)ia + 1) - o[a]) / (double)d[a];
+        const double pb = ((double)o[b] + tt * (double)d[b]) / 256.0 - 0.5;
+        const double pc = ((double)o[c] + tt * (double)d[c]) / 256.0 - 0.5;
+        const int ib = (int)floor(pb + 0.5) - W + rem % side;
+        const int ic = (int)floor(pc + 0.5) - W + rem / side;
+        if (ib < lo[b] || ib >= hi[b] || ic < lo[c] || ic >= hi[c]) continue;
+        int64_t idx[3];
+        idx[a] = ia;
+        idx[b] = ib;
+        idx[c] = ic;
+        const int64_t vx = 128 * (2 * idx[0] + 1) - o[0];
+        const int64_t vy = 128 * (2 * idx[1] + 1) - o[1];
+        const int64_t vz = 128 * (2 * idx[2] + 1) - o[2];
+        const int64_t ax = vy * d[2] - vz * d[1], ay = vz * d[0] - vx * d[2], az = vx * d[1] - vy * d[0];
+        if (ax * ax + ay * ay + az * az <= r2dd) labels[(idx[2] * ny + idx[1]) * nx + idx[0]] = 1;
     }
 }
 
@@ -293,6 +340,13 @@ hipError_t launch_voxelize(uint8_t *labels, const int64_t *prims, int64_t nprims
 {
     if (nprims <= 0) return hipSuccess;
     voxelize_kernel<<<(unsigned)nprims, 256, 0, s>>>(labels, prims, dim, nx, ny, nz, walls_y, buffer_x);
+    return hipGetLastError();
+}
+
+hipError_t launch_voxelize_fibres(uint8_t *labels, const int64_t *fibres, int64_t nfib, int nx, int ny, int nz,
+                                  int buffer_x, hipStream_t s)
+{
+    if (nfib > 0) voxelize_fibres_kernel<<<(unsigned)nfib, 256, 0, s>>>(labels, fibres, nx, ny, nz, buffer_x);
     return hipGetLastError();
 }
 

@@ -197,3 +197,91 @@ int geomgen_spheres(int nx, int ny, int nz, int buffer_x, uint64_t seed,
     *n_out = n;
     return GEOMGEN_OK;
 }
+
+/* Length (lattice units) of the line o + t d inside the box lo <= p <= hi
+ * (1/256 units), by the slab method. */
+static double chord_length(const int64_t o[3], const int64_t d[3], const int64_t lo[3],
+                           const int64_t hi[3])
+{
+    double tlo = -INFINITY, thi = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0) continue; /* the origin lies inside the slab of this axis */
+        double t1 = (double)(lo[a] - o[a]) / (double)d[a];
+        double t2 = (double)(hi[a] - o[a]) / (double)d[a];
+        if (t1 > t2) {
+            const double t = t1;
+            t1 = t2;
+            t2 = t;
+        }
+        if (t1 > tlo) tlo = t1;
+        if (t2 < thi) thi = t2;
+    }
+    if (!(thi > tlo)) return 0.0;
+    const double dn = sqrt((double)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+    return (thi - tlo) * dn / 256.0;
+}
+
+int geomgen_fibres(int nx, int ny, int nz, int buffer_x, uint64_t seed,
+                   double porosity, double r_min, double r_max,
+                   geomgen_fibre **out, int64_t *n_out)
+{
+    if (!out || !n_out) return GEOMGEN_E_INVALID;
+    if (nx < 2 * buffer_x + 1 || ny < 1 || nz < 1 || buffer_x < 0 || nx > 1024 || ny > 1024 ||
+        nz > 1024 || r_min <= 0 || r_max < r_min || r_max > 64 || porosity <= 0 || porosity >= 1)
+        return GEOMGEN_E_INVALID;
+    const double nvox = (double)nx * ny * nz;
+    const double nbuf = 2.0 * buffer_x * (double)ny * nz;
+    const double nint = nvox - nbuf;
+    const double phi_int = (porosity * nvox - nbuf) / nint;
+    if (!(phi_int > 0.0 && phi_int < 1.0)) return GEOMGEN_E_INVALID;
+    const double target = -log(phi_int) * nint; /* sum of v_k that reaches phi_int */
+    const double pi = 3.14159265358979323846;
+    const int64_t rlo = llround(r_min * 256.0), rhi = llround(r_max * 256.0);
+    const int64_t lo[3] = {256 * (int64_t)buffer_x, 0, 0};
+    const int64_t hi[3] = {256 * (int64_t)(nx - buffer_x), 256 * (int64_t)ny, 256 * (int64_t)nz};
+    int64_t cap = 1024, n = 0;
+    geomgen_fibre *f = (geomgen_fibre *)malloc(sizeof(geomgen_fibre) * (size_t)cap);
+    if (!f) return GEOMGEN_E_NOMEM;
+    uint64_t st = seed;
+    double covered = 0.0;
+    while (covered < target) {
+        if (n == cap) {
+            if (cap >= (int64_t)1 << 24) {
+                free(f);
+                return GEOMGEN_E_INVALID;
+            }
+            geomgen_fibre *g = (geomgen_fibre *)realloc(f, sizeof(geomgen_fibre) * (size_t)(2 * cap));
+            if (!g) {
+                free(f);
+                return GEOMGEN_E_NOMEM;
+            }
+            f = g;
+            cap *= 2;
+        }
+        geomgen_fibre *p = &f[n];
+        p->r = geomgen_uniform_int(&st, rlo, rhi);
+        p->ox = geomgen_uniform_int(&st, lo[0], hi[0] - 1);
+        p->oy = geomgen_uniform_int(&st, lo[1], hi[1] - 1);
+        p->oz = geomgen_uniform_int(&st, lo[2], hi[2] - 1);
+        for (;;) {
+            const int64_t a = geomgen_uniform_int(&st, -1024, 1024);
+            const int64_t b = geomgen_uniform_int(&st, -1024, 1024);
+            const int64_t c = geomgen_uniform_int(&st, -1024, 1024);
+            const int64_t q = a * a + b * b + c * c;
+            if (q > 0 && q <= 1024 * 1024) {
+                p->dx = a;
+                p->dy = b;
+                p->dz = c;
+                break;
+            }
+        }
+        p->pad = 0;
+        const int64_t o[3] = {p->ox, p->oy, p->oz}, d[3] = {p->dx, p->dy, p->dz};
+        const double r = (double)p->r / 256.0;
+        covered += pi * r * r * chord_length(o, d, lo, hi);
+        ++n;
+    }
+    *out = f;
+    *n_out = n;
+    return GEOMGEN_OK;
+}

@@ -4,8 +4,8 @@
  * The paper builds its porous electrodes from voxel images (Sec. 2, MAC grid:
  * one grid block per image voxel; Sec. 4 SEM image; Sec. 5 random fibres).
  * The images themselves are not available, so workloads are synthetic: a
- * seeded list of solid primitives (disks in 2D, spheres in 3D) with the
- * porosity and grain sizes of the paper's electrodes.
+ * seeded list of solid primitives (disks in 2D, spheres or straight fibres
+ * in 3D) with the porosity and grain sizes of the paper's electrodes.
  *
  * This module only draws primitives. It holds none of the transport or flow
  * arithmetic. Both the GPU library and the CPU reference implementation
@@ -77,6 +77,35 @@ int geomgen_spheres(int nx, int ny, int nz, int buffer_x, uint64_t seed,
 /* Number of spheres geomgen_spheres would draw (no allocation). */
 int64_t geomgen_sphere_count(int nx, int ny, int nz, int buffer_x,
                              double porosity, double r_min, double r_max);
+
+/*
+ * One straight fibre (Sec. 5): radius r and a point o of its core line in
+ * 1/256 lattice units, and the core line's direction d as an integer vector
+ * (any length; |d_i| <= 1024). The fibre is every voxel whose centre lies
+ * within r of the infinite core line, inside the interior slab.
+ */
+typedef struct {
+    int64_t r, ox, oy, oz, dx, dy, dz, pad;
+} geomgen_fibre;
+
+/*
+ * 3D overlapping straight fibres (Sec. 5: a random core orientation through a
+ * random point, extended to the domain faces, voxels within the radius solid,
+ * free overlap). Draws per fibre: radius (uniform on [r_min, r_max] in 1/256
+ * units), origin (ox, oy, oz uniform in the interior slab box
+ * [buffer_x, nx - buffer_x) x [0, ny) x [0, nz)), then direction attempts of
+ * three draws (a, b, c) uniform on [-1024, 1024] until 0 < a^2 + b^2 + c^2 <=
+ * 1024^2 (a point uniform in the ball: an isotropic direction, integers
+ * only). Fibres are added until the Boolean-model pore fraction of the slab,
+ * exp(-sum_k v_k / V_int), is <= phi_int (the interior porosity that gives the
+ * requested overall porosity with the fluid buffers), where v_k = pi r_k^2
+ * L_k and L_k is the length of fibre k's core line inside the slab box.
+ * Fibres do not wrap. Limits: nx, ny, nz <= 1024, r_max <= 64 (the exact
+ * inside test then fits int64). *out is malloc'd (geomgen_free).
+ */
+int geomgen_fibres(int nx, int ny, int nz, int buffer_x, uint64_t seed,
+                   double porosity, double r_min, double r_max,
+                   geomgen_fibre **out, int64_t *n_out);
 
 void geomgen_free(void *p);
 

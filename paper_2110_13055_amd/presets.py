@@ -46,6 +46,39 @@ PRESETS = {
 }
 
 
+# Sec. 5 fibrous electrodes in lattice units: voxel 100 nm, D = 1e-9 m^2/s for
+# both ions (Sec. 4) mapped to D = 0.05, so one step is 5e-7 s; the mean pore
+# velocity 1e-6 m/s becomes 5e-6 and K_a = 1e-6 m/s becomes 5e-6 (same
+# scale); the fibre surface at -1.2 V is -46.7 thermal voltages (298.15 K).
+FIBRE_DX_M = 100e-9
+FIBRE_D_LU = 0.05
+FIBRE_DT_S = FIBRE_D_LU * FIBRE_DX_M ** 2 / 1e-9
+FIBRE_U_PORE = 1e-6 * FIBRE_DT_S / FIBRE_DX_M
+FIBRE_KA = 1e-6 * FIBRE_DT_S / FIBRE_DX_M
+FIBRE_PSI_SURFACE = -1.2 / (1.380649e-23 * 298.15 / 1.602176634e-19)
+
+
+def fibre_case(diameter_vox: int, porosity: float, n: int = 150, seed: int = BASE_SEED,
+               precision: int = L.FP32, streaming: int = L.STREAM_PULL):
+    """One electrode of the Sec. 5 sweep: n^3 voxels of straight overlapping
+    fibres of the given diameter (4, 6, 8 voxels = 400, 600, 800 nm), the given
+    porosity, inlet/outlet flow along x with the mean pore velocity of Sec. 5
+    (the inlet plug is the superficial velocity phi * U), K_a of Sec. 4.
+    -> (Geometry, Params)."""
+    r = diameter_vox / 2.0
+    g = Geometry(dim=3, nx=n, ny=n, nz=n, kind=L.FIBRES, porosity=porosity, r_min=r, r_max=r,
+                 buffer_x=2, seed=seed)
+    p = Params(u_in=porosity * FIBRE_U_PORE, dpsi_vt=0.0, D=(FIBRE_D_LU, FIBRE_D_LU), Ka=FIBRE_KA,
+               precision=precision, streaming=streaming)
+    return g, p
+
+
+def fibre_sweep(n: int = 150, **kw):
+    """The 12 electrodes of Sec. 5: diameters 4/6/8 voxels x porosity 0.5-0.8.
+    -> list of ((diameter, porosity), Geometry, Params)."""
+    return [((d, phi),) + fibre_case(d, phi, n=n, **kw) for d in (4, 6, 8) for phi in (0.5, 0.6, 0.7, 0.8)]
+
+
 def preset(name: str, precision: int = L.FP32, **overrides):
     """-> (Geometry, Params, extra) for a named workload."""
     spec = PRESETS[name]

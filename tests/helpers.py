@@ -14,6 +14,10 @@ def oracle_labels(geom):
     from paper_2110_13055_amd import _lib as L
     if geom.kind == L.USER_LABELS:
         return np.ascontiguousarray(geom.user_labels, dtype=np.uint8).reshape(-1)
+    if geom.kind == L.FIBRES:
+        fib = oracle.fibres(geom.nx, geom.ny, geom.nz, geom.buffer_x, geom.seed, geom.porosity, geom.r_min,
+                            geom.r_max)
+        return oracle.voxelize_fibres(geom.nx, geom.ny, geom.nz, geom.buffer_x, fib)
     if geom.kind == L.DISKS:
         prims, _ = oracle.disks(geom.nx, geom.ny, geom.buffer_x, geom.walls_y, geom.seed, geom.porosity,
                                 geom.r_min, geom.r_max, geom.min_gap)

@@ -166,3 +166,77 @@ def test_splitmix64_reference_vector(oracle_lib):
     x1 = oracle_lib.geomgen_splitmix64(ctypes.byref(st))
     assert x0 == 0xE220A8397B1DCDAF
     assert x1 == 0x6E789E6AA1B965F4
+
+
+# ---------------------------------------------------------------- fibres (Sec. 5)
+
+def _brute_fibres(nx, ny, nz, bx, fib):
+    """Direct definition in floating point on small lattices: a voxel centre
+    within r of the fibre's infinite core line (distance by projection)."""
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = np.stack([x + 0.5, y + 0.5, z + 0.5], axis=-1) * 256.0
+    lab = np.zeros((nz, ny, nx), dtype=np.uint8)
+    for r, ox, oy, oz, dx, dy, dz, _ in fib:
+        d = np.array([dx, dy, dz], dtype=np.float64)
+        v = c - np.array([ox, oy, oz], dtype=np.float64)
+        t = v @ d / (d @ d)
+        dist2 = ((v - t[..., None] * d) ** 2).sum(-1)
+        lab[dist2 <= float(r) ** 2 * (1 + 1e-12)] = 1
+    lab[:, :, :bx] = 0
+    lab[:, :, nx - bx:] = 0
+    return lab.reshape(-1)
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4])
+def test_axis_fibre_covers_the_lattice_disk(R):
+    # a fibre along x through voxel centres covers, in every interior plane,
+    # exactly the lattice points of radius R
+    n, bx = 20, 2
+    c = 256 * 10 + 128
+    fib = np.array([[256 * R, 256 * 3, c, c, 1024, 0, 0, 0]], dtype=np.int64)
+    lab = oracle.voxelize_fibres(n, n, n, bx, fib)
+    assert int((lab == 1).sum()) == (n - 2 * bx) * _gauss_count_2d(R)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fibre_voxels_brute_force(seed):
+    nx, ny, nz, bx = 26, 21, 17, 2
+    fib = oracle.fibres(nx, ny, nz, bx, seed, 0.7, 1.5, 3.0)
+    assert 3 <= fib.shape[0] <= 200
+    lab = oracle.voxelize_fibres(nx, ny, nz, bx, fib)
+    assert np.array_equal(lab, _brute_fibres(nx, ny, nz, bx, fib))
+
+
+def test_fibre_draws_ranges_and_isotropy():
+    nx, ny, nz, bx = 150, 150, 150, 2
+    fib = oracle.fibres(nx, ny, nz, bx, 2110, 0.5, 1.0, 4.0)
+    r, o, d = fib[:, 0], fib[:, 1:4], fib[:, 4:7].astype(np.float64)
+    assert r.min() >= 256 and r.max() <= 1024
+    assert o[:, 0].min() >= 256 * bx and o[:, 0].max() < 256 * (nx - bx)
+    assert o[:, 1:].min() >= 0 and o[:, 1].max() < 256 * ny and o[:, 2].max() < 256 * nz
+    q = (d ** 2).sum(1)
+    assert q.min() > 0 and q.max() <= 1024 ** 2
+    u = d / np.sqrt(q)[:, None]
+    n = u.shape[0]
+    # isotropic directions: mean ~ 0, second moment ~ I/3 (a few standard errors)
+    assert np.abs(u.mean(0)).max() < 4 / np.sqrt(3 * n)
+    assert np.abs(u.T @ u / n - np.eye(3) / 3).max() < 4 * np.sqrt(4 / 45 / n)
+
+
+@pytest.mark.parametrize("phi,r", [(0.5, 2.0), (0.6, 3.0), (0.7, 4.0), (0.8, 2.0)])
+def test_fibre_porosity_close_to_target(phi, r):
+    n, bx = 96, 2
+    fib = oracle.fibres(n, n, n, bx, 2110, phi, r, r)
+    lab = oracle.voxelize_fibres(n, n, n, bx, fib)
+    assert abs((lab == 0).mean() - phi) < 0.03
+
+
+def test_fibre_generator_is_deterministic_and_rejects_bad_input():
+    a = oracle.fibres(40, 30, 30, 2, 9, 0.6, 2.0, 2.0)
+    b = oracle.fibres(40, 30, 30, 2, 9, 0.6, 2.0, 2.0)
+    c = oracle.fibres(40, 30, 30, 2, 10, 0.6, 2.0, 2.0)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    for bad in ((2000, 30, 30, 2, 9, 0.6, 2.0, 2.0), (40, 30, 30, 2, 9, 1.0, 2.0, 2.0),
+                (40, 30, 30, 2, 9, 0.6, 2.0, 80.0)):
+        with pytest.raises(RuntimeError):
+            oracle.fibres(*bad)
