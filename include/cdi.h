@@ -384,6 +384,37 @@ int cdi_np_step_coupled(cdi_solver *s, int64_t nsteps, int32_t fused_flow, const
  * the solved or given field, else the ramp. Synchronous. */
 int cdi_copy_potential(cdi_solver *s, float *psi);
 
+/* ------------------------------------------------------------ diagnostics (Sec. 4)
+ * The dimensionless numbers and averages the paper reports. */
+typedef struct {
+    int64_t n_surface;       /* fluid-electrode voxel faces (x wraps only with the body-force drive) */
+    int64_t n_inlet;         /* fluid voxels of the x = 0 plane */
+    double specific_surface; /* s = n_surface / N_vox (electrode area per volume, lattice units) */
+    double l_c;              /* characteristic length pi / s */
+    double U;                /* U = sum_i u_i / (N phi): streamwise velocity of the current
+                                populations summed over the fluid, over N_f */
+    double Pe[2], Da[2];     /* U l_c / D_i and K_a l_c / D_i per species */
+} cdi_diag;
+
+/* Surface, velocity and the dimensionless numbers (FP64 sums in a fixed
+ * order). Synchronises. */
+int cdi_diagnostics(cdi_solver *s, cdi_diag *out);
+
+/* Vertically averaged concentrations along the flow axis (Figs. 6 and 9):
+ * out (host, 3 nx doubles): out[x], out[nx + x] = mean C of Na, Cl over the
+ * fluid voxels of plane x, out[2 nx + x] = their number. Synchronises. */
+int cdi_profile_x(cdi_solver *s, double *out);
+
+/* Salt removal over a window of nsteps ion steps between two cdi_mass_balance
+ * read-backs bal0, bal1 (host): P_rm = (C_in - C_out) / C_in per species
+ * (out[0], out[1]) with C_in = c0 and C_out the flux-weighted outlet
+ * concentration, (Out1 - Out0) / (u_in n_inlet nsteps); out[2] = their mean
+ * (salt); out[3] = U A P_rm nsteps / (V_t phi), the amount removed per pore
+ * volume in the window (Sec. 4.1), A = ny nz, V_t phi = N_f, U and n_inlet
+ * from cdi_diagnostics. Host arithmetic only. */
+int cdi_salt_removal(const cdi_solver *s, const double bal0[8], const double bal1[8], int64_t nsteps,
+                     int64_t n_inlet, double U, double out[4]);
+
 /* Checkpoint: the complete device state (populations, moments, fields,
  * potential, accumulators, counters, AA parity) to and from host memory. */
 int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes);

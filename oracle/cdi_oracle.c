@@ -962,3 +962,77 @@ int oracle_np_steps_coupled(oracle_solver *s, int64_t n, int fused, const oracle
     }
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics of Sec. 4: Pe, Da, l_c = pi / s, U, vertical averages.        */
+/* ------------------------------------------------------------------------ */
+
+void oracle_diagnostics(const oracle_solver *s, oracle_diag *out)
+{
+    const oracle_cfg *c = &s->cfg;
+    const int periodic_x = c->drive == ORACLE_DRIVE_BODY_FORCE;
+    int64_t faces = 0, inlet = 0;
+    double usum = 0;
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        for (int axis = 0; axis < c->dim; ++axis)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                int off[3] = {0, 0, 0};
+                off[axis] = sgn;
+                const int64_t vn = neighbour(s, v, off[0], off[1], off[2], periodic_x);
+                if (vn >= 0 && s->labels[vn] == 1) ++faces;
+            }
+        if (v % c->nx == 0) ++inlet;
+        double rho, u[3];
+        moments(s, s->f, v, 1, &rho, u);
+        usum += u[0];
+    }
+    out->n_surface = faces;
+    out->n_inlet = inlet;
+    /* s: electrode surface per unit total volume (faces of unit area over N
+     * voxels); l_c = pi / s */
+    out->specific_surface = (double)faces / (double)s->nvox;
+    out->l_c = faces > 0 ? 3.14159265358979323846 / out->specific_surface : INFINITY;
+    /* U = sum_i u_i / (N phi): the streamwise velocity summed over all grid
+     * blocks (zero in the solid) over the number of pore blocks */
+    out->U = s->nf > 0 ? usum / (double)s->nf : 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+        out->Pe[sp] = out->U * out->l_c / c->D[sp];
+        out->Da[sp] = s->ka * out->l_c / c->D[sp];
+    }
+}
+
+void oracle_profile_x(const oracle_solver *s, double *out)
+{
+    const int nx = s->cfg.nx;
+    for (int k = 0; k < 3 * nx; ++k) out[k] = 0;
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        const int x = (int)(v % nx);
+        out[x] += s->C[v];
+        out[nx + x] += s->C[s->nvox + v];
+        out[2 * nx + x] += 1.0;
+    }
+    for (int x = 0; x < nx; ++x)
+        if (out[2 * nx + x] > 0) {
+            out[x] /= out[2 * nx + x];
+            out[nx + x] /= out[2 * nx + x];
+        }
+}
+
+/* Salt removal of Sec. 4.1 over a window of nsteps ion steps between two
+ * balances: P_rm = (C_in - C_out) / C_in per species, C_in = c0 and C_out the
+ * outflowing amount over the volume that entered, u_in n_inlet nsteps;
+ * out[2] the mean of the two species; out[3] = U A P_rm dt / (V_t phi) with
+ * A = ny nz and V_t phi = N_f. */
+void oracle_salt_removal(const oracle_solver *s, const double *bal0, const double *bal1, int64_t nsteps,
+                         int64_t n_inlet, double U, double out[4])
+{
+    const double volume = s->cfg.u_in * (double)n_inlet * (double)nsteps;
+    for (int sp = 0; sp < 2; ++sp) {
+        const double c_out = (bal1[4 * sp + 3] - bal0[4 * sp + 3]) / volume;
+        out[sp] = (s->cfg.c0 - c_out) / s->cfg.c0;
+    }
+    out[2] = 0.5 * (out[0] + out[1]);
+    out[3] = U * (double)s->cfg.ny * (double)s->cfg.nz * out[2] * (double)nsteps / (double)s->nf;
+}

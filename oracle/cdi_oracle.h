@@ -159,6 +159,26 @@ int oracle_np_steps_coupled(oracle_solver *s, int64_t n, int fused, const oracle
  * field or the solved one. */
 void oracle_get_potential(const oracle_solver *s, double *psi);
 
+/* ---- diagnostics of Sec. 4 ---- */
+typedef struct {
+    int64_t n_surface;       /* fluid-electrode voxel faces */
+    int64_t n_inlet;         /* fluid voxels of the x = 0 plane */
+    double specific_surface; /* s = n_surface / N (per lattice unit) */
+    double l_c;              /* pi / s */
+    double U;                /* sum of u_x over the fluid / N_f (u of the current populations) */
+    double Pe[2], Da[2];     /* U l_c / D_i, K_a l_c / D_i */
+} oracle_diag;
+
+void oracle_diagnostics(const oracle_solver *s, oracle_diag *out);
+/* Vertically averaged concentrations: out[x], out[nx + x] = mean C of Na, Cl
+ * over the fluid voxels of plane x; out[2 nx + x] = their number. */
+void oracle_profile_x(const oracle_solver *s, double *out);
+
+/* Salt removal and removed amount over a window between two oracle_balance
+ * read-backs nsteps ion steps apart (see cdi_oracle.c). */
+void oracle_salt_removal(const oracle_solver *s, const double *bal0, const double *bal1, int64_t nsteps,
+                         int64_t n_inlet, double U, double out[4]);
+
 /* Threads the OpenMP loops use (1 if built without OpenMP). */
 int oracle_threads(void);
 

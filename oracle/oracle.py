@@ -46,6 +46,11 @@ class _Potential(C.Structure):
                 ("kappa2", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int)]
 
 
+class _Diag(C.Structure):
+    _fields_ = [("n_surface", C.c_int64), ("n_inlet", C.c_int64), ("specific_surface", C.c_double),
+                ("l_c", C.c_double), ("U", C.c_double), ("Pe", C.c_double * 2), ("Da", C.c_double * 2)]
+
+
 class _Prim(C.Structure):
     _fields_ = [("r", C.c_int64), ("cx", C.c_int64), ("cy", C.c_int64), ("cz", C.c_int64)]
 
@@ -88,6 +93,9 @@ def library():
             "oracle_solve_potential": (I, [P, P, P, P]),
             "oracle_get_potential": (None, [P, P]),
             "oracle_np_steps_coupled": (I, [P, I64, I, P, I]),
+            "oracle_diagnostics": (None, [P, P]),
+            "oracle_profile_x": (None, [P, P]),
+            "oracle_salt_removal": (None, [P, P, P, I64, I64, D, P]),
             "geomgen_disks": (I, [I, I, I, I, C.c_uint64, D, D, D, D, P, P, P]),
             "geomgen_spheres": (I, [I, I, I, I, C.c_uint64, D, D, D, P, P]),
             "geomgen_sphere_count": (I64, [I, I, I, I, D, D, D]),
@@ -343,6 +351,24 @@ class OracleSolver:
         pc.psi_x[0], pc.psi_x[1] = psi_x
         pc.kappa2, pc.tol, pc.max_iter = kappa2, tol, max_iter
         return int(self.lib.oracle_np_steps_coupled(self.h, n, int(fused), C.byref(pc), every))
+
+    def diagnostics(self) -> dict:
+        d = _Diag()
+        self.lib.oracle_diagnostics(self.h, C.byref(d))
+        return {"n_surface": d.n_surface, "n_inlet": d.n_inlet, "specific_surface": d.specific_surface,
+                "l_c": d.l_c, "U": d.U, "Pe": tuple(d.Pe), "Da": tuple(d.Da)}
+
+    def profile_x(self) -> np.ndarray:
+        out = np.empty((3, self.cfg.nx))
+        self.lib.oracle_profile_x(self.h, _ptr(out))
+        return out
+
+    def salt_removal(self, bal0, bal1, nsteps: int, n_inlet: int, U: float) -> np.ndarray:
+        b0 = np.ascontiguousarray(bal0, dtype=np.float64).reshape(-1)
+        b1 = np.ascontiguousarray(bal1, dtype=np.float64).reshape(-1)
+        out = np.empty(4)
+        self.lib.oracle_salt_removal(self.h, _ptr(b0), _ptr(b1), nsteps, n_inlet, U, _ptr(out))
+        return out
 
     def potential(self) -> np.ndarray:
         p = np.empty(self.nf)

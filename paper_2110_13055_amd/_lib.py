@@ -82,6 +82,11 @@ class CPotentialResult(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("residual", C.c_double)]
 
 
+class CDiag(C.Structure):
+    _fields_ = [("n_surface", C.c_int64), ("n_inlet", C.c_int64), ("specific_surface", C.c_double),
+                ("l_c", C.c_double), ("U", C.c_double), ("Pe", C.c_double * 2), ("Da", C.c_double * 2)]
+
+
 P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
 
 # name -> (restype, argtypes); the list of symbols include/cdi.h declares
@@ -120,6 +125,9 @@ SIGNATURES = {
     "cdi_solve_potential": (C.c_int, [P, P, P, U64, P]),
     "cdi_np_step_coupled": (C.c_int, [P, I64, I32, P, I32, P, U64]),
     "cdi_copy_potential": (C.c_int, [P, P]),
+    "cdi_diagnostics": (C.c_int, [P, P]),
+    "cdi_profile_x": (C.c_int, [P, P]),
+    "cdi_salt_removal": (C.c_int, [P, P, P, I64, I64, D, P]),
     "cdi_snapshot_bytes": (C.c_int, [P, P]),
     "cdi_snapshot": (C.c_int, [P, P, U64]),
     "cdi_restore": (C.c_int, [P, P, U64]),

@@ -4,6 +4,7 @@
 // kernels of geometry.hip and step.hip.
 #include "cdi.h"
 #include "cdi_internal.h"
+#include "diag_internal.h"
 #include "geometry_internal.h"
 #include "geomgen.h"
 #include "pot_internal.h"
@@ -236,6 +237,7 @@ struct NodeLayout {
     double *acc, *resid, *part, *red;
     int *sched;
     int *nbr;    // neighbour list (Q-1 planes of P), built once
+    double *diag;  // diagnostics scratch (per-tile and per-plane-chunk sums)
     void *base;  // start of the state a checkpoint carries (state_bytes from here)
     uint64_t state_bytes, bytes;
 };
@@ -243,7 +245,18 @@ struct NodeLayout {
 // Bytes per stored population of a storage kind.
 static int pop_bytes(int st) { return st == kF32 ? 4 : st == kF16 ? 2 : 0; }
 
-static NodeLayout node_layout(void *ws, int dim, int st, int pull, int64_t P, int64_t plane)
+// Doubles of the diagnostics scratch: per-tile sums (3 per tile) or the
+// vertical-profile partials (3 per x plane and z chunk) plus its result (3 nx).
+static uint64_t diag_doubles(const cdi_geometry *g, int64_t P)
+{
+    const int64_t nz = g->dim == 2 ? 1 : g->nz;
+    const int64_t prof = 3ll * g->nx * ((nz + 7) / 8) + 3ll * g->nx;
+    const int64_t tiles = 3 * (P / kTile) + 3;
+    return (uint64_t)(prof > tiles ? prof : tiles);
+}
+
+static NodeLayout node_layout(void *ws, int dim, int st, int pull, int64_t P, int64_t plane,
+                              uint64_t ndiag)
 {
     const int Q = dim == 2 ? 9 : 19;
     const int64_t ntiles = P / kTile;
@@ -273,6 +286,7 @@ static NodeLayout node_layout(void *ws, int dim, int st, int pull, int64_t P, in
     L.state_bytes = c.off;  // everything a checkpoint must carry ends here
     L.sched = c.take<int>(4ull * ntiles);
     L.nbr = c.take<int>(4ull * (Q - 1) * P);
+    L.diag = c.take<double>(8ull * ndiag);
     L.bytes = c.off;
     return L;
 }
@@ -604,7 +618,7 @@ int cdi_node_bytes(const cdi_geometry *geom, const cdi_params *params, int64_t n
     if (!bytes || n_fluid <= 0) return fail(CDI_E_INVALID, "bad n_fluid or bytes pointer");
     const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
     *bytes = node_layout(nullptr, geom->dim, params->precision, params->streaming == CDI_STREAM_PULL, P,
-                         (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz)).bytes;
+                         (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz), diag_doubles(geom, P)).bytes;
     return CDI_OK;
 }
 
@@ -641,7 +655,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     if (P * (st_kind == kF32 ? 4 : 16) > 4294967295LL)
         return fail(CDI_E_INVALID, "too many fluid nodes for one instance (limit 2^30, 2^28 with moment buffers)");
     NodeLayout N = node_layout(node_ws, geom->dim, st_kind, params->streaming == CDI_STREAM_PULL, P,
-                               (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz));
+                               (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz), diag_doubles(geom, P));
     if (node_ws_bytes < N.bytes) return fail(CDI_E_BUFFER, "node_ws too small: %llu < %llu",
                                              (unsigned long long)node_ws_bytes, (unsigned long long)N.bytes);
     if (params->np_x_bc != CDI_NPX_PERIODIC && params->np_x_bc != CDI_NPX_CLOSED && geom->nx < 2)
@@ -1091,6 +1105,57 @@ int cdi_copy_potential(cdi_solver *s, float *psi)
         const int x = (int)(fluid[(size_t)n] % s->g.nx);
         psi[n] = (float)(s->params.dpsi_vt * (1.0 - (x + 0.5) / s->g.nx));
     }
+    return CDI_OK;
+}
+
+// ------------------------------------------------------------ diagnostics (Sec. 4)
+
+int cdi_diagnostics(cdi_solver *s, cdi_diag *out)
+{
+    if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
+    // u of the current populations into tmp (d planes), then the tile sums
+    HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
+                          s->mb ? s->node.M[s->mcur] : nullptr, nullptr, s->node.tmp, nullptr, s->stream));
+    HIPCHK(launch_diag(s->dim, s->g, s->node.tmp, s->node.nbr, s->node.diag, s->node.red, s->stream));
+    double h[3];
+    int rc = d2h(s, h, s->node.red, sizeof h);
+    if (rc) return rc;
+    out->n_surface = (int64_t)h[1];
+    out->n_inlet = (int64_t)h[2];
+    out->specific_surface = h[1] / (double)s->nvox;
+    out->l_c = h[1] > 0 ? M_PI / out->specific_surface : INFINITY;
+    out->U = h[0] / (double)s->nf;
+    for (int k = 0; k < 2; ++k) {
+        out->Pe[k] = out->U * out->l_c / s->params.D[k];
+        out->Da[k] = s->ka * out->l_c / s->params.D[k];
+    }
+    return CDI_OK;
+}
+
+int cdi_profile_x(cdi_solver *s, double *out)
+{
+    if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
+    const int nx = s->g.nx;
+    double *res = s->node.diag + 3ll * nx * profile_chunks(s->g);
+    HIPCHK(launch_profile_x(s->g, s->node.C[s->ccur], s->node.diag, res, s->stream));
+    return d2h(s, out, res, 24ull * nx);
+}
+
+int cdi_salt_removal(const cdi_solver *s, const double bal0[8], const double bal1[8], int64_t nsteps,
+                     int64_t n_inlet, double U, double out[4])
+{
+    if (!s || !bal0 || !bal1 || !out || nsteps <= 0 || n_inlet <= 0)
+        return fail(CDI_E_INVALID, "bad arguments");
+    const double c_in = s->params.c0;
+    const double inflow = s->params.u_in * (double)n_inlet * (double)nsteps;  // volume that entered
+    if (!(inflow > 0)) return fail(CDI_E_INVALID, "no inflow (u_in <= 0)");
+    for (int k = 0; k < 2; ++k) {
+        const double c_out = (bal1[4 * k + 3] - bal0[4 * k + 3]) / inflow;  // flux-weighted outlet concentration
+        out[k] = (c_in - c_out) / c_in;
+    }
+    out[2] = 0.5 * (out[0] + out[1]);
+    const double area = (double)s->g.ny * (double)s->g.nz;
+    out[3] = U * area * out[2] * (double)nsteps / (double)s->nf;
     return CDI_OK;
 }
 

@@ -273,6 +273,29 @@ class Solver:
     def potential(self) -> np.ndarray:
         return self._get("cdi_copy_potential", (self.n_fluid,), np.float32)
 
+    # -------------------------------------------------------------- diagnostics (Sec. 4)
+    def diagnostics(self) -> dict:
+        d = L.CDiag()
+        L.check(self.lib.cdi_diagnostics(self.h, C.byref(d)), "cdi_diagnostics")
+        return {"n_surface": d.n_surface, "n_inlet": d.n_inlet, "specific_surface": d.specific_surface,
+                "l_c": d.l_c, "U": d.U, "Pe": tuple(d.Pe), "Da": tuple(d.Da)}
+
+    def profile_x(self) -> np.ndarray:
+        """(3, nx): mean Na, mean Cl and fluid count of every x plane."""
+        out = np.empty((3, self.geom.nx))
+        L.check(self.lib.cdi_profile_x(self.h, C.c_void_p(out.ctypes.data)), "cdi_profile_x")
+        return out
+
+    def salt_removal(self, bal0, bal1, nsteps: int, n_inlet: int, U: float) -> np.ndarray:
+        """[P_rm Na, P_rm Cl, P_rm salt, removed amount] over a window between
+        two mass_balance() read-backs nsteps ion steps apart."""
+        b0 = np.ascontiguousarray(bal0, dtype=np.float64).reshape(-1)
+        b1 = np.ascontiguousarray(bal1, dtype=np.float64).reshape(-1)
+        out = np.empty(4)
+        L.check(self.lib.cdi_salt_removal(self.h, C.c_void_p(b0.ctypes.data), C.c_void_p(b1.ctypes.data),
+                                          nsteps, n_inlet, U, C.c_void_p(out.ctypes.data)), "cdi_salt_removal")
+        return out
+
     # -------------------------------------------------------------- tuning
     def tuning(self):
         t = L.CTuning()
