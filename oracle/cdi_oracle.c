@@ -1036,3 +1036,211 @@ void oracle_salt_removal(const oracle_solver *s, const double *bal0, const doubl
     out[2] = 0.5 * (out[0] + out[1]);
     out[3] = U * (double)s->cfg.ny * (double)s->cfg.nz * out[2] * (double)nsteps / (double)s->nf;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Implicit Nernst-Planck (the paper's time scheme, Sec. 2) and the steady   */
+/* state.                                                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * For frozen u and psi the outflow of a cell is affine in the concentrations
+ * of its species: out(C) = A C - b, with b = -out(0) the ghost (inlet,
+ * outlet) terms. A backward-Euler step solves (I/dt + A) C' = C/dt + b; the
+ * steady state solves A C = b. Both by BiCGSTAB (van der Vorst 1992) with
+ * the diagonal of the matrix as right preconditioner, per species.
+ */
+typedef struct {
+    const oracle_solver *s;
+    int sp;
+    double idt;   /* 1/dt, 0 for the steady problem */
+    double *W;    /* 2 x nvox scratch: the field of species sp goes in its slot */
+} np_op;
+
+/* y = (idt I + A) x over the fluid cells (nvox arrays) */
+static void np_op_apply(np_op *op, const double *x, double *y)
+{
+    const oracle_solver *s = op->s;
+    const int64_t nv = s->nvox;
+    double *slot = op->W + (int64_t)op->sp * nv;
+    for (int64_t n = 0; n < s->nf; ++n) slot[s->fluid[n]] = x[s->fluid[n]];
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        double fa, fi, fo;
+        const double full = cell_outflow(s, v, op->sp, op->W, &fa, &fi, &fo, NULL);
+        y[v] = full + op->idt * x[v];
+    }
+    /* remove the constant part: out(0) */
+    for (int64_t n = 0; n < s->nf; ++n) slot[s->fluid[n]] = 0.0;
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        double fa, fi, fo;
+        y[v] -= cell_outflow(s, v, op->sp, op->W, &fa, &fi, &fo, NULL);
+    }
+}
+
+/* diagonal of (idt I + A) and b = -out(0) */
+static void np_op_diag_rhs(np_op *op, double *dg, double *b)
+{
+    const oracle_solver *s = op->s;
+    double *slot = op->W + (int64_t)op->sp * s->nvox;
+    for (int64_t n = 0; n < s->nf; ++n) slot[s->fluid[n]] = 0.0;
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t v = s->fluid[n];
+        double fa, fi, fo, d;
+        b[v] = -cell_outflow(s, v, op->sp, op->W, &fa, &fi, &fo, &d);
+        dg[v] = d + op->idt;
+    }
+}
+
+static double np_dot(const oracle_solver *s, const double *a, const double *b) { return pot_dot(s, a, b); }
+
+/* Solve (idt I + A) x = rhs from the start x; returns iterations or -1. */
+static int np_bicgstab(np_op *op, const double *rhs, double *x, double tol, int max_iter, double *relres)
+{
+    const oracle_solver *s = op->s;
+    const int64_t nv = s->nvox;
+    double *r = calloc((size_t)nv, sizeof(double)), *rh = calloc((size_t)nv, sizeof(double));
+    double *p = calloc((size_t)nv, sizeof(double)), *v = calloc((size_t)nv, sizeof(double));
+    double *y = calloc((size_t)nv, sizeof(double)), *z = calloc((size_t)nv, sizeof(double));
+    double *t = calloc((size_t)nv, sizeof(double)), *sv = calloc((size_t)nv, sizeof(double));
+    double *dg = calloc((size_t)nv, sizeof(double)), *bb = calloc((size_t)nv, sizeof(double));
+    int it = -1;
+    if (!r || !rh || !p || !v || !y || !z || !t || !sv || !dg || !bb) goto done;
+    np_op_diag_rhs(op, dg, bb);
+    np_op_apply(op, x, t);
+    for (int64_t n = 0; n < s->nf; ++n) {
+        const int64_t c = s->fluid[n];
+        r[c] = rhs[c] - t[c];
+        rh[c] = r[c];
+    }
+    const double bnorm = sqrt(np_dot(s, rhs, rhs));
+    double rho = 1, alpha = 1, omega = 1;
+    double rn = sqrt(np_dot(s, r, r));
+    it = 0;
+    while (bnorm > 0 && rn > tol * bnorm && it < max_iter) {
+        const double rho1 = np_dot(s, rh, r);
+        const double beta = (rho1 / rho) * (alpha / omega);
+        rho = rho1;
+        for (int64_t n = 0; n < s->nf; ++n) {
+            const int64_t c = s->fluid[n];
+            p[c] = r[c] + beta * (p[c] - omega * v[c]);
+            y[c] = p[c] / dg[c];
+        }
+        np_op_apply(op, y, v);
+        alpha = rho / np_dot(s, rh, v);
+        for (int64_t n = 0; n < s->nf; ++n) {
+            const int64_t c = s->fluid[n];
+            sv[c] = r[c] - alpha * v[c];
+            z[c] = sv[c] / dg[c];
+        }
+        np_op_apply(op, z, t);
+        const double tt = np_dot(s, t, t);
+        omega = tt > 0 ? np_dot(s, t, sv) / tt : 0.0;
+        for (int64_t n = 0; n < s->nf; ++n) {
+            const int64_t c = s->fluid[n];
+            x[c] += alpha * y[c] + omega * z[c];
+            r[c] = sv[c] - omega * t[c];
+        }
+        rn = sqrt(np_dot(s, r, r));
+        ++it;
+        if (!isfinite(rn) || omega == 0.0) {
+            it = -1;
+            break;
+        }
+    }
+    if (relres) *relres = bnorm > 0 ? rn / bnorm : 0.0;
+    if (it >= max_iter && rn > tol * bnorm) it = -2;
+done:
+    free(r), free(rh), free(p), free(v), free(y), free(z), free(t), free(sv), free(dg), free(bb);
+    return it;
+}
+
+/* Right-hand side b of species sp (the ghost terms) into b. */
+static void np_rhs(np_op *op, double *b)
+{
+    const oracle_solver *s = op->s;
+    double *dg = calloc((size_t)s->nvox, sizeof(double));
+    np_op_diag_rhs(op, dg, b);
+    free(dg);
+}
+
+int oracle_np_steady(oracle_solver *s, double tol, int max_iter, int *iters)
+{
+    if (!s->u_valid) oracle_freeze_velocity(s);
+    const int64_t nv = s->nvox;
+    double *W = calloc((size_t)(2 * nv), sizeof(double)), *b = calloc((size_t)nv, sizeof(double));
+    double *x = calloc((size_t)nv, sizeof(double));
+    int rc = ORACLE_OK, tot = 0;
+    for (int sp = 0; sp < 2 && rc == ORACLE_OK; ++sp) {
+        np_op op = {s, sp, 0.0, W};
+        np_rhs(&op, b);
+        for (int64_t n = 0; n < s->nf; ++n) x[s->fluid[n]] = s->C[(int64_t)sp * nv + s->fluid[n]];
+        const int it = np_bicgstab(&op, b, x, tol, max_iter, NULL);
+        if (it < 0) rc = it == -2 ? ORACLE_E_NOT_CONVERGED : ORACLE_E_DIVERGED;
+        else tot += it;
+        if (rc == ORACLE_OK)
+            for (int64_t n = 0; n < s->nf; ++n) s->C[(int64_t)sp * nv + s->fluid[n]] = x[s->fluid[n]];
+    }
+    if (iters) *iters = tot;
+    free(W), free(b), free(x);
+    return rc;
+}
+
+/* Per species: rates of adsorption, inflow and outflow of the current state
+ * (out[3 sp + k], per unit time). */
+void oracle_np_rates(const oracle_solver *s, double out[6])
+{
+    for (int sp = 0; sp < 2; ++sp) {
+        double a = 0, in = 0, o = 0;
+        for (int64_t n = 0; n < s->nf; ++n) {
+            double fa, fi, fo;
+            cell_outflow(s, s->fluid[n], sp, s->C, &fa, &fi, &fo, NULL);
+            a += fa;
+            in += fi;
+            o += fo;
+        }
+        out[3 * sp] = a;
+        out[3 * sp + 1] = in;
+        out[3 * sp + 2] = o;
+    }
+}
+
+int oracle_np_implicit(oracle_solver *s, double dt, int64_t nsteps, double tol, int max_iter, int *iters)
+{
+    if (!(dt > 0) || nsteps < 0) return ORACLE_E_INVALID;
+    if (!s->u_valid) oracle_freeze_velocity(s);
+    const int64_t nv = s->nvox;
+    double *W = calloc((size_t)(2 * nv), sizeof(double)), *b = calloc((size_t)nv, sizeof(double));
+    double *x = calloc((size_t)nv, sizeof(double)), *rhs = calloc((size_t)nv, sizeof(double));
+    int rc = ORACLE_OK, tot = 0;
+    for (int64_t k = 0; k < nsteps && rc == ORACLE_OK; ++k) {
+        for (int sp = 0; sp < 2 && rc == ORACLE_OK; ++sp) {
+            np_op op = {s, sp, 1.0 / dt, W};
+            np_rhs(&op, b);
+            for (int64_t n = 0; n < s->nf; ++n) {
+                const int64_t c = s->fluid[n];
+                x[c] = s->C[(int64_t)sp * nv + c];
+                rhs[c] = x[c] / dt + b[c];
+            }
+            const int it = np_bicgstab(&op, rhs, x, tol, max_iter, NULL);
+            if (it < 0) rc = it == -2 ? ORACLE_E_NOT_CONVERGED : ORACLE_E_DIVERGED;
+            else tot += it;
+            if (rc == ORACLE_OK)
+                for (int64_t n = 0; n < s->nf; ++n) s->Cn[(int64_t)sp * nv + s->fluid[n]] = x[s->fluid[n]];
+        }
+        if (rc != ORACLE_OK) break;
+        double *t = s->C;
+        s->C = s->Cn;
+        s->Cn = t;
+        /* the fluxes of the new state over dt enter the accumulators */
+        double rates[6];
+        oracle_np_rates(s, rates);
+        for (int sp = 0; sp < 2; ++sp)
+            for (int q = 0; q < 3; ++q) s->acc[sp][q] += dt * rates[3 * sp + q];
+        s->np_steps++;
+    }
+    if (iters) *iters = tot;
+    free(W), free(b), free(x), free(rhs);
+    return rc;
+}

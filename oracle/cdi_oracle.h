@@ -179,6 +179,19 @@ void oracle_profile_x(const oracle_solver *s, double *out);
 void oracle_salt_removal(const oracle_solver *s, const double *bal0, const double *bal1, int64_t nsteps,
                          int64_t n_inlet, double U, double out[4]);
 
+/* ---- implicit ion transport (the paper's time scheme, Sec. 2) ---- */
+/* Steady state of the ion equations on the frozen flow and current
+ * potential (A C = b, BiCGSTAB to relative residual tol), from the current
+ * concentrations. The accumulators are left as they are. */
+int oracle_np_steady(oracle_solver *s, double tol, int max_iter, int *iters);
+/* nsteps backward-Euler steps of length dt: (I/dt + A) C' = C/dt + b; the
+ * new state's adsorption, inflow and outflow rates times dt enter the
+ * accumulators (the scheme conserves M + A + Out - In exactly). */
+int oracle_np_implicit(oracle_solver *s, double dt, int64_t nsteps, double tol, int max_iter, int *iters);
+/* Adsorption, inflow and outflow rates of the current state per species:
+ * out[3 sp + 0..2]. */
+void oracle_np_rates(const oracle_solver *s, double out[6]);
+
 /* Threads the OpenMP loops use (1 if built without OpenMP). */
 int oracle_threads(void);
 

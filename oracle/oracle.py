@@ -96,6 +96,9 @@ def library():
             "oracle_diagnostics": (None, [P, P]),
             "oracle_profile_x": (None, [P, P]),
             "oracle_salt_removal": (None, [P, P, P, I64, I64, D, P]),
+            "oracle_np_steady": (I, [P, D, I, P]),
+            "oracle_np_implicit": (I, [P, D, I64, D, I, P]),
+            "oracle_np_rates": (None, [P, P]),
             "geomgen_disks": (I, [I, I, I, I, C.c_uint64, D, D, D, D, P, P, P]),
             "geomgen_spheres": (I, [I, I, I, I, C.c_uint64, D, D, D, P, P]),
             "geomgen_sphere_count": (I64, [I, I, I, I, D, D, D]),
@@ -369,6 +372,21 @@ class OracleSolver:
         out = np.empty(4)
         self.lib.oracle_salt_removal(self.h, _ptr(b0), _ptr(b1), nsteps, n_inlet, U, _ptr(out))
         return out
+
+    def np_steady(self, tol=1e-12, max_iter=100000):
+        it = C.c_int()
+        rc = self.lib.oracle_np_steady(self.h, tol, max_iter, C.byref(it))
+        return rc, it.value
+
+    def np_implicit(self, dt: float, n: int, tol=1e-12, max_iter=100000):
+        it = C.c_int()
+        rc = self.lib.oracle_np_implicit(self.h, dt, n, tol, max_iter, C.byref(it))
+        return rc, it.value
+
+    def np_rates(self) -> np.ndarray:
+        out = np.empty(6)
+        self.lib.oracle_np_rates(self.h, _ptr(out))
+        return out.reshape(2, 3)
 
     def potential(self) -> np.ndarray:
         p = np.empty(self.nf)
