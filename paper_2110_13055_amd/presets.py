@@ -47,11 +47,14 @@ PRESETS = {
 
 
 # Sec. 5 fibrous electrodes in lattice units: voxel 100 nm, D = 1e-9 m^2/s for
-# both ions (Sec. 4) mapped to D = 0.05, so one step is 5e-7 s; the mean pore
-# velocity 1e-6 m/s becomes 5e-6 and K_a = 1e-6 m/s becomes 5e-6 (same
-# scale); the fibre surface at -1.2 V is -46.7 thermal voltages (298.15 K).
+# both ions (Sec. 4) mapped to D = 0.15 (the largest round value inside the
+# explicit update's positivity bound, 6 D < 1, so the slow diffusive and
+# adsorptive approach to steady state takes the fewest steps), so one step
+# is 1.5e-6 s; the mean pore velocity 1e-6 m/s becomes 1.5e-5 and K_a =
+# 1e-6 m/s becomes 1.5e-5 (same scale); the fibre surface at -1.2 V is -46.7
+# thermal voltages (298.15 K).
 FIBRE_DX_M = 100e-9
-FIBRE_D_LU = 0.05
+FIBRE_D_LU = 0.15
 FIBRE_DT_S = FIBRE_D_LU * FIBRE_DX_M ** 2 / 1e-9
 FIBRE_U_PORE = 1e-6 * FIBRE_DT_S / FIBRE_DX_M
 FIBRE_KA = 1e-6 * FIBRE_DT_S / FIBRE_DX_M
