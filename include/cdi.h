@@ -384,6 +384,42 @@ int cdi_np_step_coupled(cdi_solver *s, int64_t nsteps, int32_t fused_flow, const
  * the solved or given field, else the ramp. Synchronous. */
 int cdi_copy_potential(cdi_solver *s, float *psi);
 
+/* ------------------------------------------------------------ implicit ion transport
+ * The paper discretises Eq. (3) with an implicit finite-volume method (Sec. 2).
+ * For the frozen advecting flux and the current potential each species'
+ * outflow is affine in its concentrations, out(C) = A C - b (the explicit
+ * step's face fluxes, adsorption and ghost terms; coefficients evaluated in
+ * FP32 as the explicit step does, applied in FP64). A backward-Euler step of
+ * length dt solves (I/dt + A) C' = C/dt + b; the steady state solves A C = b;
+ * both by BiCGSTAB with the diagonal as preconditioner, both species
+ * together, to the relative residual tol (|rhs - M C'| <= tol |rhs|). The
+ * stop is decided on the device; the iterate is bitwise repeatable on one
+ * device. The scheme is unconditionally positive and stable (no positivity
+ * check is needed or made). */
+
+/* Device workspace of the ion solves (7 FP64 vector pairs and an FP32 pair
+ * per node, plus per-workgroup sums); needed only during a call. */
+int cdi_np_solve_bytes(const cdi_solver *s, uint64_t *bytes);
+
+/* The steady concentrations on the frozen flow, from the current ones
+ * (installed as the current state; the accumulators and step count are not
+ * changed). ws: device, >= cdi_np_solve_bytes, 256-byte aligned.
+ * Synchronises every 32 iterations. OK, NOT_CONVERGED after max_iter (the
+ * last iterate is installed) or DIVERGED (nothing installed). iterations
+ * (host, nullable): the larger of the two species' counts. */
+int cdi_np_steady(cdi_solver *s, double tol, int32_t max_iter, void *ws, uint64_t ws_bytes, int32_t *iterations);
+
+/* nsteps backward-Euler steps of length dt > 0; after each, the new state's
+ * adsorption, inflow and outflow rates times dt enter the accumulators (the
+ * balance M + A + Out - In is kept to the solver tolerance). iterations: the
+ * total over the steps. Statuses as cdi_np_steady (a failed step ends the call). */
+int cdi_np_implicit(cdi_solver *s, double dt, int64_t nsteps, double tol, int32_t max_iter, void *ws,
+                    uint64_t ws_bytes, int32_t *iterations);
+
+/* Rates of the current concentrations per species, FP64: out[3 sp + 0]
+ * adsorption, + 1 inflow, + 2 outflow (amount per unit time). Synchronises. */
+int cdi_np_rates(cdi_solver *s, double out[6]);
+
 /* ------------------------------------------------------------ diagnostics (Sec. 4)
  * The dimensionless numbers and averages the paper reports. */
 typedef struct {

@@ -125,6 +125,10 @@ SIGNATURES = {
     "cdi_solve_potential": (C.c_int, [P, P, P, U64, P]),
     "cdi_np_step_coupled": (C.c_int, [P, I64, I32, P, I32, P, U64]),
     "cdi_copy_potential": (C.c_int, [P, P]),
+    "cdi_np_solve_bytes": (C.c_int, [P, P]),
+    "cdi_np_steady": (C.c_int, [P, D, I32, P, U64, P]),
+    "cdi_np_implicit": (C.c_int, [P, D, I64, D, I32, P, U64, P]),
+    "cdi_np_rates": (C.c_int, [P, P]),
     "cdi_diagnostics": (C.c_int, [P, P]),
     "cdi_profile_x": (C.c_int, [P, P]),
     "cdi_salt_removal": (C.c_int, [P, P, P, I64, I64, D, P]),

@@ -6,6 +6,7 @@
 #include "cdi_internal.h"
 #include "diag_internal.h"
 #include "geometry_internal.h"
+#include "np_solve_internal.h"
 #include "geomgen.h"
 #include "pot_internal.h"
 
@@ -251,7 +252,7 @@ static uint64_t diag_doubles(const cdi_geometry *g, int64_t P)
 {
     const int64_t nz = g->dim == 2 ? 1 : g->nz;
     const int64_t prof = 3ll * g->nx * ((nz + 7) / 8) + 3ll * g->nx;
-    const int64_t tiles = 3 * (P / kTile) + 3;
+    const int64_t tiles = 6 * (P / kTile) + 6;  // diagnostics: 3 per tile; ion rates: 6 per tile
     return (uint64_t)(prof > tiles ? prof : tiles);
 }
 
@@ -1105,6 +1106,139 @@ int cdi_copy_potential(cdi_solver *s, float *psi)
         const int x = (int)(fluid[(size_t)n] % s->g.nx);
         psi[n] = (float)(s->params.dpsi_vt * (1.0 - (x + 0.5) / s->g.nx));
     }
+    return CDI_OK;
+}
+
+// ------------------------------------------------------------ implicit ion transport
+
+namespace {
+
+struct NpsLayout {
+    double *x, *r, *rh, *pv, *v, *sv, *t, *part, *state;
+    float *dg;
+    uint64_t bytes;
+};
+
+NpsLayout nps_layout(void *ws, int P)
+{
+    Carver c(ws);
+    NpsLayout L;
+    L.x = c.take<double>(16ull * P);
+    L.r = c.take<double>(16ull * P);
+    L.rh = c.take<double>(16ull * P);
+    L.pv = c.take<double>(16ull * P);
+    L.v = c.take<double>(16ull * P);
+    L.sv = c.take<double>(16ull * P);
+    L.t = c.take<double>(16ull * P);
+    L.dg = c.take<float>(8ull * P);
+    L.part = c.take<double>(8ull * nps_part_doubles());
+    L.state = c.take<double>(8ull * kNsSlots);
+    L.bytes = c.off;
+    return L;
+}
+
+// One solve of (idt I + A) C' = idt C + b from C' = C; installs the result
+// into the current concentrations unless it diverged.
+int np_solve(cdi_solver *s, double idt, double tol, int32_t max_iter, void *ws, uint64_t ws_bytes, int *iters)
+{
+    if (!(tol >= 0) || max_iter < 0) return fail(CDI_E_INVALID, "bad tol or max_iter");
+    if (!ws || ((uintptr_t)ws % kAlign)) return fail(CDI_E_BUFFER, "workspace NULL or not 256-byte aligned");
+    if (16ull * s->P > 4294967295ull) return fail(CDI_E_INVALID, "too many fluid nodes for the ion solve (limit 2^28)");
+    const NpsLayout W = nps_layout(ws, s->P);
+    if (ws_bytes < W.bytes) return fail(CDI_E_BUFFER, "ion-solve workspace too small: %llu < %llu",
+                                        (unsigned long long)ws_bytes, (unsigned long long)W.bytes);
+    int rc = ensure_j(s);
+    if (rc) return rc;
+    NpsArgs a{};
+    a.g = s->g;
+    a.p = s->p;
+    a.C = s->node.C[s->ccur];
+    a.j = s->node.j[s->jcur];
+    a.idt = idt;
+    a.x = W.x;
+    a.r = W.r;
+    a.rh = W.rh;
+    a.pv = W.pv;
+    a.v = W.v;
+    a.sv = W.sv;
+    a.t = W.t;
+    a.dg = W.dg;
+    a.part = W.part;
+    a.state = W.state;
+    int G = 0;
+    HIPCHK(nps_workgroups(s->dim, s->ntiles, &G));
+    HIPCHK(launch_nps_setup(s->dim, a, G, tol, s->stream));
+    double st[kNsSlots];
+    if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
+    int k = 0;
+    while (st[kNsDone] == 0 && k < max_iter) {
+        const int n = std::min(32, max_iter - k);
+        for (int q = k; q < k + n; ++q) HIPCHK(launch_nps_iter(s->dim, a, G, q, s->stream));
+        k += n;
+        HIPCHK(launch_nps_check(a, G, k, s->stream));
+        if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
+    }
+    *iters = (int)std::max(st[kNsIters], st[kNsIters + 1]);
+    if (st[kNsDone] == 2.0) return fail(CDI_E_DIVERGED, "ion solve diverged or broke down after %d iterations", k);
+    HIPCHK(launch_nps_store(a, s->node.C[s->ccur], s->stream));
+    if (st[kNsDone] == 0)
+        return fail(CDI_E_NOT_CONVERGED, "ion solve: %d iterations, relative residuals %g, %g", k,
+                    std::sqrt(st[kNsRr] / std::max(st[kNsBb], 1e-300)),
+                    std::sqrt(st[kNsRr + 1] / std::max(st[kNsBb + 1], 1e-300)));
+    return CDI_OK;
+}
+
+}  // namespace
+
+int cdi_np_solve_bytes(const cdi_solver *s, uint64_t *bytes)
+{
+    if (!s || !bytes) return fail(CDI_E_INVALID, "NULL argument");
+    *bytes = nps_layout(nullptr, s->P).bytes;
+    return CDI_OK;
+}
+
+int cdi_np_steady(cdi_solver *s, double tol, int32_t max_iter, void *ws, uint64_t ws_bytes, int32_t *iterations)
+{
+    if (!s) return fail(CDI_E_INVALID, "NULL solver");
+    int it = 0;
+    const int rc = np_solve(s, 0.0, tol, max_iter, ws, ws_bytes, &it);
+    if (iterations) *iterations = it;
+    return rc;
+}
+
+int cdi_np_implicit(cdi_solver *s, double dt, int64_t nsteps, double tol, int32_t max_iter, void *ws,
+                    uint64_t ws_bytes, int32_t *iterations)
+{
+    if (!s || !(dt > 0) || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
+    int64_t total = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        int it = 0;
+        const int rc = np_solve(s, 1.0 / dt, tol, max_iter, ws, ws_bytes, &it);
+        total += it;
+        if (rc) {
+            if (iterations) *iterations = (int32_t)std::min<int64_t>(total, INT32_MAX);
+            return rc;
+        }
+        // the new state's fluxes over dt enter the accumulators
+        HIPCHK(launch_nps_rates(s->dim, s->g, s->p, s->node.C[s->ccur], s->node.j[s->jcur], dt, s->node.acc,
+                                nullptr, nullptr, s->stream));
+        s->np_steps++;
+    }
+    if (iterations) *iterations = (int32_t)std::min<int64_t>(total, INT32_MAX);
+    return CDI_OK;
+}
+
+int cdi_np_rates(cdi_solver *s, double out[6])
+{
+    if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
+    int rc = ensure_j(s);
+    if (rc) return rc;
+    HIPCHK(launch_nps_rates(s->dim, s->g, s->p, s->node.C[s->ccur], s->node.j[s->jcur], 1.0, nullptr,
+                            s->node.diag, s->node.red, s->stream));
+    double h[6];  // accumulator order: A_na, A_cl, In_na, In_cl, Out_na, Out_cl
+    if ((rc = d2h(s, h, s->node.red, sizeof h)) != CDI_OK) return rc;
+    for (int sp = 0; sp < 2; ++sp)
+        for (int k = 0; k < 3; ++k) out[3 * sp + k] = h[2 * k + sp];
     return CDI_OK;
 }
 

@@ -31,6 +31,7 @@
 #include "cdi_internal.h"
 #include "device_common.h"
 #include "pot_internal.h"
+#include "reduce_common.h"
 
 namespace cdi {
 
@@ -39,44 +40,10 @@ namespace {
 // Partial-sum regions, G doubles each.
 enum { kRz0 = 0, kRz1 = 1, kRr = 2, kPq = 3, kBb = 4, kNd = 5, kRegions = 6 };
 
-__device__ inline void tile_range(int ntiles, int &t0, int &t1)
-{
-    const long long G = gridDim.x;
-    const long long c = xcd_tile(blockIdx.x, gridDim.x);
-    t0 = (int)(c * ntiles / G);
-    t1 = (int)((c + 1) * ntiles / G);
-}
-
-// Sum of v over the workgroup in a fixed order, returned to every thread.
-__device__ inline double wg_sum(double v, double *sm)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();  // sm may still be read from a previous call
-    if (lane == 0) sm[wave] = v;
-    __syncthreads();
-    double s = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sm[w];
-    return s;
-}
-
 // Whether the solve has stopped, read once per workgroup so that all its
 // waves take the same branch (a stop may be recorded by workgroup 0 of the
 // running kernel; every workgroup then skips the same update either way).
-__device__ inline bool stopped(const double *state, int *flag)
-{
-    if (threadIdx.x == 0) *flag = state[kStDone] != 0.0;
-    __syncthreads();
-    return *flag != 0;
-}
-
-// Total of a partial-sum region (G values), the same in every workgroup.
-__device__ inline double region_sum(const double *part, int G, double *sm)
-{
-    double v = 0;
-    for (int k = threadIdx.x; k < G; k += blockDim.x) v += part[k];
-    return wg_sum(v, sm);
-}
+__device__ inline bool stopped(const double *state, int *flag) { return stopped_at(state, kStDone, flag); }
 
 // Map values of the 2D face neighbours of node n, and its diagonal.
 template <class L>

@@ -273,6 +273,37 @@ class Solver:
     def potential(self) -> np.ndarray:
         return self._get("cdi_copy_potential", (self.n_fluid,), np.float32)
 
+    # -------------------------------------------------------------- implicit ion transport
+    def _nps_ws(self):
+        nb = C.c_uint64()
+        L.check(self.lib.cdi_np_solve_bytes(self.h, C.byref(nb)), "cdi_np_solve_bytes")
+        ws = getattr(self, "_nps_buf", None)
+        if ws is None or ws.numel() < nb.value:
+            self._nps_buf = ws = _torch().empty(int(nb.value), dtype=_torch().uint8, device=self.device)
+        return ws
+
+    def np_steady(self, tol: float = 1e-10, max_iter: int = 100000, allow_not_converged: bool = False) -> int:
+        """Steady concentrations on the frozen flow; returns the iterations."""
+        ws = self._nps_ws()
+        it = C.c_int32()
+        rc = self.lib.cdi_np_steady(self.h, tol, max_iter, C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(it))
+        L.check(rc, "cdi_np_steady", (L.OK, L.E_NOT_CONVERGED) if allow_not_converged else (L.OK,))
+        return it.value
+
+    def np_implicit(self, dt: float, n: int, tol: float = 1e-10, max_iter: int = 100000) -> int:
+        """n backward-Euler ion steps of length dt; returns the total iterations."""
+        ws = self._nps_ws()
+        it = C.c_int32()
+        L.check(self.lib.cdi_np_implicit(self.h, dt, n, tol, max_iter, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                         C.byref(it)), "cdi_np_implicit")
+        return it.value
+
+    def np_rates(self) -> np.ndarray:
+        """(2, 3): adsorption, inflow, outflow rate per species."""
+        out = np.empty(6)
+        L.check(self.lib.cdi_np_rates(self.h, C.c_void_p(out.ctypes.data)), "cdi_np_rates")
+        return out.reshape(2, 3)
+
     # -------------------------------------------------------------- diagnostics (Sec. 4)
     def diagnostics(self) -> dict:
         d = L.CDiag()
