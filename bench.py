@@ -129,6 +129,24 @@ def potential_rates(coupled_steps: int = 10):
                               "kappa2": 0.5, "every": 1}
     except P.CdiError as exc:
         out["coupled_pnp"] = {"error": str(exc)}
+    # the steady ion state on this flow and potential (implicit scheme),
+    # BiCGSTAB to 1e-8; per iteration both species: direction 64 B, two
+    # operator applications 86 + 70 B (own vectors, diagonal, coordinates,
+    # map, flux and potential), s 48 B, update 120 B per fluid node
+    per_it_np = 64 + 86 + 48 + 70 + 120
+    try:
+        s.np_steady(tol=1e-8, max_iter=20, allow_not_converged=True)  # first launches
+        res = {}
+
+        def run_np():
+            res["it"] = s.np_steady(tol=1e-8, max_iter=4000, allow_not_converged=True)
+        sec = time_region(run_np, s.stream)
+        out["ion_steady"] = {"iterations": res["it"], "solve_ms": round(sec * 1e3, 2),
+                             "ms_per_iter": round(sec * 1e3 / max(res["it"], 1), 4),
+                             "algorithmic_bytes_per_node_iter": per_it_np,
+                             "gbs": round(per_it_np * nf * res["it"] / sec / 1e9, 1)}
+    except P.CdiError as exc:
+        out["ion_steady"] = {"error": str(exc)}
     del s
     torch.cuda.empty_cache()
     return out
