@@ -131,6 +131,30 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         }
     }
 
+    // FP32 storage, fused step: the ions' own and face-neighbour inputs are
+    // loaded here, with the flow's gathers still to come, so that their
+    // latency overlaps the flow's instead of following its stores (measured
+    // 12 % faster on the 512^3 electrode despite one wave less per SIMD;
+    // slower with FP16 and moment storage, which hold more registers)
+    constexpr bool kEarly = LBM && NP && ST == kF32;
+    float ec[2] = {0.f, 0.f}, ej[3] = {0.f, 0.f, 0.f};
+    float ecn[2 * D][2], ejn[2 * D];
+    if (kEarly && active) {
+        ec[0] = b.Cin[n];
+        ec[1] = b.Cin[P + n];
+        ej[0] = b.jin[n];
+        ej[1] = b.jin[P + n];
+        ej[2] = D == 3 ? b.jin[2 * P + n] : 0.f;
+#pragma unroll
+        for (int k = 0; k < 2 * D; ++k) {
+            const int m = nb[k + 1];
+            const bool fl = m >= 0;
+            ecn[k][0] = fl ? b.Cin[m] : 0.f;
+            ecn[k][1] = fl ? b.Cin[P + m] : 0.f;
+            ejn[k] = fl ? b.jin[(k >> 1) * P + m] : 0.f;
+        }
+    }
+
     // the flow: collide and stream (and the residual terms on request)
     {
         if (LBM && active) {
@@ -170,7 +194,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     // the ions: face fluxes of the explicit finite-volume update
     {
         if (NP && active) {
-            const float cP[2] = {b.Cin[n], b.Cin[P + n]};
+            const float cP[2] = {kEarly ? ec[0] : b.Cin[n], kEarly ? ec[1] : b.Cin[P + n]};
             float jP[3];
             const bool jm = ST != kF32 && (b.flags & kJFromM);
             if (jm) {
@@ -179,6 +203,10 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 jP[0] = r * m.y;
                 jP[1] = r * m.z;
                 jP[2] = r * m.w;
+            } else if (kEarly) {
+                jP[0] = ej[0];
+                jP[1] = ej[1];
+                jP[2] = ej[2];
             } else {
                 jP[0] = b.jin[n];
                 jP[1] = b.jin[P + n];
@@ -225,6 +253,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                     continue;
                 }
                 int m = nb[i];
+                const bool early = kEarly && !xb;  // the loaded neighbour (not a periodic re-lookup)
                 if (xb) m = nb_map<L>(g, x, y, z, i, true);  // periodic ions, open flow
                 if (m == kElectrode) {  // adsorbing face, Eq. (6)
 #pragma unroll
@@ -239,7 +268,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                         const float4 mm = ldu(b.Min, (uint32_t)m);
                         jN = (1.f + mm.x) * (axis == 0 ? mm.y : (axis == 1 ? mm.z : mm.w));
                     } else {
-                        jN = b.jin[axis * P + m];
+                        jN = early ? ejn[k] : b.jin[axis * P + m];
                     }
                     // half the face-normal drift: advection by the mean flux of the
                     // two cells, migration down the potential difference
@@ -249,7 +278,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
                         const float hw = mig ? hun - hzD[s] * dpsi : hun;
-                        out[s] += sg_flux(p.D[s], invD2[s], hw, cP[s], b.Cin[s * P + m]);
+                        out[s] += sg_flux(p.D[s], invD2[s], hw, cP[s], early ? ecn[k][s] : b.Cin[s * P + m]);
                     }
                 }
                 // inert wall: no flux
