@@ -182,31 +182,42 @@ __device__ inline void st(void *F, int P, int i, int n, float v)
         reinterpret_cast<float *>(F)[o] = v;
 }
 
+// Stored value behind the incoming population i of node n (FP32 f - w_i or
+// the scaled FP16 deviation; nothing with moment storage).
+template <class L, int ST, int ODD>
+__device__ inline float gather_raw(const void *F, int P, const int *nb, int n, int i)
+{
+    if (ST == kMom) return 0.f;
+    const int j = L::opp[i];
+    const bool fl = (i != 0) && nb[j] >= 0;
+    if (ODD == kPull) return fl ? ld<ST == kF16>(F, P, i, nb[j]) : ld<ST == kF16>(F, P, j, n);
+    if (!ODD || i == 0 || !fl) return ld<ST == kF16>(F, P, i, n);
+    return ld<ST == kF16>(F, P, j, nb[j]);
+}
+
+// FP16 and moment storage: f_i - w_i from the stored value and the emitter's
+// moments m. The emitter x - e_i sent it along e_i; a reflected one (fl
+// false) was sent by x along e_opp(i) = -e_i, which only flips the sign of
+// e.u (w_opp(i) = w_i).
+template <class L, int ST>
+__device__ inline float from_emitter(float raw, int i, bool fl, float4 m, const Phys &p)
+{
+    const float eu = L::ex[i] * m.y + L::ey[i] * m.z + L::ez[i] * m.w;
+    const float fe = feq_bar_eu(L::w[i], m.x, fl ? eu : -eu, m.y, m.z, m.w, p.linear_eq);
+    return ST == kMom ? fe : fe + raw * p.hs_inv;
+}
+
 // Incoming f_i - w_i of node n (nb: map values of n's neighbours; M: the
 // emitters' moments, FP16 and moment storage; ST: kF32, kF16 or kMom).
 template <class L, int ST, int ODD>
 __device__ inline float gather(const void *F, int P, const int *nb, int n, int i, const float4 *M,
                                const Phys &p)
 {
+    const float raw = gather_raw<L, ST, ODD>(F, P, nb, n, i);
+    if (ST == kF32) return raw;
     const int j = L::opp[i];
     const bool fl = (i != 0) && nb[j] >= 0;
-    float raw = 0.f;
-    if (ST != kMom) {
-        if (ODD == kPull)
-            raw = fl ? ld<ST == kF16>(F, P, i, nb[j]) : ld<ST == kF16>(F, P, j, n);
-        else if (!ODD || i == 0 || !fl)
-            raw = ld<ST == kF16>(F, P, i, n);
-        else
-            raw = ld<ST == kF16>(F, P, j, nb[j]);
-    }
-    if (ST == kF32) return raw;
-    // emitter x - e_i sent it along e_i; a reflected one was sent by x along
-    // e_opp(i) = -e_i, which only flips the sign of e.u (w_opp(i) = w_i)
-    const int e = fl ? nb[j] : n;
-    const float4 m = ldu(M, (uint32_t)e);
-    const float eu = L::ex[i] * m.y + L::ey[i] * m.z + L::ez[i] * m.w;
-    const float fe = feq_bar_eu(L::w[i], m.x, fl ? eu : -eu, m.y, m.z, m.w, p.linear_eq);
-    return ST == kMom ? fe : fe + raw * p.hs_inv;
+    return from_emitter<L, ST>(raw, i, fl, ldu(M, (uint32_t)(fl ? nb[j] : n)), p);
 }
 
 // Store the outgoing value of direction i (FP32: f* - w_i; FP16: scaled
