@@ -98,11 +98,9 @@ typedef struct {
  *   D[2], z[2]   diffusivity and valence of Na+ (index 0) and Cl- (index 1)
  *   c0           inlet and initial concentration ("initially saturated")
  *   c_out        outlet ghost concentration (CDI_NPX_DIRICHLET only)
- *   Ka           adsorption constant of Eq. (6); 0 selects
+ *   Ka           adsorption constant of Eq. (6); <= 0 selects
  *                Ka = (4.28e-3 / 1.03e-2) * u_in / porosity, the paper's
- *                Da/Pe ratio of its base case times the mean pore velocity;
- *                a negative value selects Ka = 0 (a blocking electrode, as
- *                the charged wall of the electromigration check, Sec. 3)
+ *                Da/Pe ratio of its base case times the mean pore velocity
  *   dpsi_vt      potential drop inlet minus outlet in thermal voltages; the
  *                potential is the ramp dpsi_vt * (1 - (x + 1/2)/nx) until a
  *                field is given or solved (cdi_solve_potential)
@@ -131,6 +129,8 @@ typedef struct {
  *                CDI_STREAM_PULL: two arrays; every step gathers from the
  *                neighbours' slots of one and writes the node's own slots of
  *                the other (twice the population memory, no scattered stores)
+ *   no_adsorption 1: K_a = 0 whatever Ka says (a blocking electrode, as the
+ *                charged wall of the electromigration check, Sec. 3); 0: Ka
  */
 typedef struct {
     double tau;
@@ -146,6 +146,7 @@ typedef struct {
     int32_t np_substeps;
     int32_t precision;
     int32_t streaming;
+    int32_t no_adsorption;
 } cdi_params;
 
 /* Sizes reported by cdi_plan. */

@@ -300,12 +300,12 @@ oracle_solver *oracle_create(const oracle_cfg *cfg, const uint8_t *labels, const
             s->psi[v] = cfg->dpsi * (1.0 - (x + 0.5) / c->nx);
         }
     }
-    /* Adsorption constant: given; zero selects the paper's Da/Pe ratio of its
+    /* Adsorption constant: given; <= 0 selects the paper's Da/Pe ratio of its
      * base case (Da = 4.28e-3 at Pe = 1.03e-2) times the mean pore velocity
-     * u_in/phi; negative selects none (a blocking electrode, as the charged
+     * u_in/phi; none with no_adsorption (a blocking electrode, as the charged
      * wall of the electromigration check of Sec. 3). */
     const double phi = (double)s->nf / (double)nv;
-    s->ka = cfg->Ka > 0 ? cfg->Ka : cfg->Ka < 0 ? 0.0 : (4.28e-3 / 1.03e-2) * cfg->u_in / phi;
+    s->ka = cfg->no_adsorption ? 0.0 : cfg->Ka > 0 ? cfg->Ka : (4.28e-3 / 1.03e-2) * cfg->u_in / phi;
     /* Robin law D dC/dn = Ka C (Eq. 6) across half a cell: the wall value is
      * eliminated, giving the face flux k_eff * C_P. */
     for (int sp = 0; sp < 2; ++sp) s->keff[sp] = s->ka * cfg->D[sp] / (cfg->D[sp] + 0.5 * s->ka);

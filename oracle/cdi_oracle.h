@@ -52,10 +52,11 @@ typedef struct {
     int z[2];                /* valences */
     double c0;               /* inlet / initial concentration */
     double c_out;            /* outlet ghost concentration (NPX_DIRICHLET only) */
-    double Ka;               /* adsorption constant; 0: derive 0.4155*u_in/phi; < 0: none */
+    double Ka;               /* adsorption constant; <= 0: derive 0.4155*u_in/phi */
     double dpsi;             /* potential drop (thermal voltages) inlet minus outlet */
     int np_x_bc;             /* ORACLE_NPX_* */
     int np_substeps;         /* sub-steps per NP step (>= 1) */
+    int no_adsorption;       /* 1: K_a = 0 (a blocking electrode) */
 } oracle_cfg;
 
 /* status codes */

@@ -37,7 +37,7 @@ class _Cfg(C.Structure):
         ("force", C.c_double * 3),
         ("D", C.c_double * 2), ("z", C.c_int * 2),
         ("c0", C.c_double), ("c_out", C.c_double), ("Ka", C.c_double), ("dpsi", C.c_double),
-        ("np_x_bc", C.c_int), ("np_substeps", C.c_int),
+        ("np_x_bc", C.c_int), ("np_substeps", C.c_int), ("no_adsorption", C.c_int),
     ]
 
 
@@ -220,6 +220,7 @@ class OracleCfg:
     dpsi: float = 0.0
     np_x_bc: int = NPX_INLET_OUTLET
     np_substeps: int = 1
+    no_adsorption: int = 0
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -233,6 +234,7 @@ class OracleCfg:
             c.z[s] = self.z[s]
         c.c0, c.c_out, c.Ka, c.dpsi = self.c0, self.c_out, self.Ka, self.dpsi
         c.np_x_bc, c.np_substeps = self.np_x_bc, self.np_substeps
+        c.no_adsorption = self.no_adsorption
         return c
 
 

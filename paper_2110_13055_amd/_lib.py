@@ -46,7 +46,7 @@ class CParams(C.Structure):
         ("c0", C.c_double), ("c_out", C.c_double), ("Ka", C.c_double), ("dpsi_vt", C.c_double),
         ("psi_field", C.c_void_p),
         ("np_x_bc", C.c_int32), ("np_substeps", C.c_int32), ("precision", C.c_int32),
-        ("streaming", C.c_int32),
+        ("streaming", C.c_int32), ("no_adsorption", C.c_int32),
     ]
 
 

@@ -681,9 +681,9 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     s->vox = V;
     s->node = N;
     s->porosity = (double)n_fluid / (double)nvox;
-    s->ka = params->Ka > 0   ? params->Ka
-            : params->Ka < 0 ? 0.0  // no adsorption: a blocking electrode
-                             : (4.28e-3 / 1.03e-2) * params->u_in / s->porosity;
+    s->ka = params->no_adsorption ? 0.0  // a blocking electrode
+            : params->Ka > 0      ? params->Ka
+                                  : (4.28e-3 / 1.03e-2) * params->u_in / s->porosity;
     for (int k = 0; k < 2; ++k) s->keff[k] = s->ka * params->D[k] / (params->D[k] + 0.5 * s->ka);
 
     Grid &g = s->g;

@@ -73,6 +73,7 @@ class Params:
     np_substeps: int = 1
     precision: int = L.FP32
     streaming: int = L.STREAM_AA
+    no_adsorption: int = 0       # 1: K_a = 0 (a blocking electrode)
 
     def to_c(self):
         p = L.CParams()
@@ -87,6 +88,7 @@ class Params:
         p.psi_field = None if self.psi_field is None else self.psi_field.data_ptr()
         p.np_x_bc, p.np_substeps, p.precision = self.np_x_bc, self.np_substeps, self.precision
         p.streaming = self.streaming
+        p.no_adsorption = self.no_adsorption
         return p
 
 

@@ -33,7 +33,7 @@ def oracle_cfg(geom, params) -> OracleCfg:
                      u_in=params.u_in, rho_out=params.rho_out, force=tuple(params.body_force),
                      D=tuple(params.D), z=tuple(params.z), c0=params.c0, c_out=params.c_out,
                      Ka=params.Ka, dpsi=params.dpsi_vt, np_x_bc=params.np_x_bc,
-                     np_substeps=params.np_substeps)
+                     np_substeps=params.np_substeps, no_adsorption=params.no_adsorption)
 
 
 def oracle_solver(geom, params, psi=None) -> OracleSolver:

@@ -134,7 +134,7 @@ def test_warm_start_and_ion_steps_on_the_solved_field():
 def test_coupled_pnp_matches_oracle():
     g, p = spheres(seed=5, n=32)
     p.u_in = 0.0
-    p.Ka = -1.0  # blocking electrode: the double layer forms without adsorption
+    p.no_adsorption = 1  # blocking electrode: the double layer forms without adsorption
     kw = dict(psi_electrode=-2.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), kappa2=0.5)
     s = Solver(g, p)
     o = oracle_solver(g, p)

@@ -112,7 +112,7 @@ def test_no_adsorption_removes_nothing():
     lab = np.zeros((ny, nx), np.uint8)
     lab[0, :] = lab[-1, :] = 1
     u = 2e-3
-    s = solver(lab, 2, nx, ny, D=(0.05, 0.05), Ka=-1.0, u_in=u)
+    s = solver(lab, 2, nx, ny, D=(0.05, 0.05), no_adsorption=1, u_in=u)
     s.set_velocity(np.vstack([np.full(s.nf, u), np.zeros(s.nf)]))
     b0 = s.balance().copy()
     assert s.np_steps(500) == 0

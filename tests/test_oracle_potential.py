@@ -166,10 +166,12 @@ def test_singular_problem_is_rejected():
     assert s.solve_potential(x_bc=(PSIX_PERIODIC, PSIX_DIRICHLET))[0] == oracle.oracle.E_INVALID
 
 
-def test_negative_ka_means_no_adsorption():
+def test_no_adsorption_flag():
     lab = np.zeros((1, 8, 12), np.uint8)
     lab[:, 0, :] = lab[:, -1, :] = 1
-    s = solver(lab, 2, 12, 8, Ka=-1.0)
+    derived = OracleSolver(OracleCfg(dim=2, nx=12, ny=8, u_in=1e-3, Ka=-1.0), lab.reshape(-1)).ka
+    assert derived > 0  # <= 0 still means the derived default
+    s = solver(lab, 2, 12, 8, Ka=0.3, no_adsorption=1)
     assert s.ka == 0.0
     assert s.np_steps(50) == 0
     assert np.all(s.adsorbed_total() == 0.0)
@@ -202,7 +204,7 @@ def test_coupled_pnp_half_channel_converges_to_gouy_chapman():
         dx = W / n
         lab = np.zeros(n + 1, np.uint8)
         lab[-1] = 1  # the charged wall; x = 0 is the centreline
-        cfg = OracleCfg(dim=2, nx=n + 1, ny=1, D=(0.2, 0.2), u_in=0.0, c0=1.0, Ka=-1.0)
+        cfg = OracleCfg(dim=2, nx=n + 1, ny=1, D=(0.2, 0.2), u_in=0.0, c0=1.0, no_adsorption=1)
         s = OracleSolver(cfg, lab)
         s.set_velocity(np.zeros((2, n)))
         rc = s.np_steps_coupled(int(10 * n * n / 0.2), every=20, psi_electrode=psi0 / VT,
