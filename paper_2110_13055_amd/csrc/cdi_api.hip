@@ -748,6 +748,9 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     chk(launch_fill_f64(N.acc, 0.0, 8ll * s->ntiles, st));
     chk(launch_fill_f64(N.resid, 0.0, 2ll * s->ntiles, st));
     chk(launch_build_nbr(s->dim, g, N.nbr, st));
+    // the ion-carrying steps read their neighbours from the list by default
+    g.nbr = N.nbr;
+    s->tuning.nbr_list = 1;
     if (err == CDI_OK) err = build_schedule(s, 0, 0);  // bricks already give locality
     if (err != CDI_OK) {
         delete s;
