@@ -11,10 +11,16 @@ initialisation happen once, before the timed region; all state is resident
 in HBM. MLUPS counts fluid nodes only.
 
 Prints one JSON line. ``value`` is the FP32-storage fused MLUPS; the FP16
-deviation-storage form, LBM-only and NP-only rates are reported beside it.
-``roofline`` prices the fused kernel's algorithmic bytes per node against
-8 TB/s; ``cpu_baseline`` is the FP64 reference on this host's cores, on a
-bounded sample (the seeded 64^3 sub-case).
+deviation and moment storage forms, LBM-only and NP-only rates are reported
+beside it. ``roofline`` prices the fused kernel's algorithmic bytes per node
+against 8 TB/s (``traffic``: the HBM bytes per launch the committed counter
+record holds for the current kernel sources); ``cpu_baseline`` is the FP64
+reference on this host's cores, on a bounded sample (the seeded 64^3
+sub-case). Beside them: ``potential`` (the Poisson solve of Eq. 4-5, a
+coupled PNP step, and the steady ion state by the implicit solver, on the
+same electrode), ``batched`` (64 uneven electrodes in one persistent launch
+per step) and ``serving`` (a Poisson arrival trace through the continuous-
+batching server). --potential-only runs the solver leg alone.
 """
 from __future__ import annotations
 
