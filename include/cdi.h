@@ -256,10 +256,12 @@ typedef struct {
                               8 XCDs, so the 8 layers at one (x, y) are processed together (the
                               layers above and below a tile meet in the memory-side cache);
                               takes precedence over band_rows. 0: off */
-    int32_t nbr_list;      /* 1 (the default): steps that advance the ions read each node's neighbours
-                              from a list built at init (4 (Q-1) bytes per node of extra reads) instead
-                              of looking them up through the voxel map after the node's coordinates
-                              (flow-only steps always look them up); 0: map lookups everywhere */
+    int32_t nbr_list;      /* 1 (the default): the ion-only steps and the fused steps with FP16 or moment
+                              storage read each node's neighbours from a list built at init (4 (Q-1)
+                              bytes per node of extra reads) instead of looking them up through the
+                              voxel map after the node's coordinates (flow-only and fused FP32 steps
+                              always look them up: measured no faster with the list); 0: map lookups
+                              everywhere */
 } cdi_tuning;
 
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t);

@@ -115,10 +115,13 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
         nb[0] = n;
         // the list, when the instance has one, for the steps that carry the ions
-        // (measured: ion-only -4 %, fused moments -5 %, FP16 -3 %, FP32 equal);
-        // flow-only steps stream their populations at the copy rate already and
-        // only pay for the list's extra bytes (+10 %), so they look neighbours up
-        if (NP && g.nbr) {  // precomputed: independent of the coordinates
+        // (measured: ion-only -4 %, fused moments -5 %, FP16 -3 %); the fused
+        // FP32 step runs equally fast either way and moves 59 B/node less
+        // without it, and flow-only steps stream their populations at the copy
+        // rate already and only pay for the list's bytes (+10 %): those two
+        // look their neighbours up
+        constexpr bool kList = NP && !(LBM && ST == kF32);
+        if (kList && g.nbr) {  // precomputed: independent of the coordinates
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
