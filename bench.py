@@ -231,10 +231,23 @@ def cpu_baseline(budget_s: float = 12.0):
         o.np_steps(10, fused=True)
         steps += 10
     dt = time.perf_counter() - t0
-    return {"value": o.nf * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.oracle.threads(),
+    cores = oracle.oracle.threads()
+    # the same steps on one thread, a shorter sample (results do not depend on the thread count)
+    oracle.oracle.set_threads(1)
+    try:
+        steps1, t1 = 0, time.perf_counter()
+        while time.perf_counter() - t1 < budget_s / 3:
+            o.np_steps(2, fused=True)
+            steps1 += 2
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.oracle.set_threads(cores)
+    return {"value": o.nf * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} fused LBM+NP steps (FP64) of the seeded 64^3 sub-case "
-                      f"({o.nf} fluid nodes), {dt:.1f} s"}
+                      f"({o.nf} fluid nodes), {dt:.1f} s",
+            "single_thread": {"value": o.nf * steps1 / dt1 / 1e6, "unit": "MLUPS",
+                              "sample": f"{steps1} more steps of the same case on 1 thread, {dt1:.1f} s"}}
 
 
 def main():

@@ -29,6 +29,15 @@ int oracle_threads(void)
 #endif
 }
 
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry (Sec. 2: every grid block is one voxel of the electrode image).  */
 /* ------------------------------------------------------------------------ */

@@ -195,6 +195,9 @@ void oracle_np_rates(const oracle_solver *s, double out[6]);
 
 /* Threads the OpenMP loops use (1 if built without OpenMP). */
 int oracle_threads(void);
+/* Threads for the following OpenMP loops (n > 0; no effect without OpenMP).
+   Results do not depend on it: every reduction is chunked in a fixed order. */
+void oracle_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -90,6 +90,7 @@ def library():
             "oracle_flow_step_count": (I64, [P]),
             "oracle_np_step_count": (I64, [P]),
             "oracle_threads": (I, []),
+            "oracle_set_threads": (None, [I]),
             "oracle_solve_potential": (I, [P, P, P, P]),
             "oracle_get_potential": (None, [P, P]),
             "oracle_np_steps_coupled": (I, [P, I64, I, P, I]),
@@ -406,3 +407,8 @@ class OracleSolver:
 
 def threads() -> int:
     return int(library().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the following OpenMP loops (results do not depend on it)."""
+    library().oracle_set_threads(int(n))

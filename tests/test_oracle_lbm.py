@@ -171,3 +171,25 @@ def test_flow_to_steady_residual_definition():
     assert abs(r2 - r) <= 1e-12 * r
     rc2, steps2, _ = OracleSolver(cfg, _channel_labels(nx, ny)).flow_to_steady(1e-30, 120, 50)
     assert rc2 == oracle.oracle.E_NOT_CONVERGED and steps2 == 120
+
+
+def test_results_do_not_depend_on_the_thread_count():
+    # fixed-order chunked reductions: the fused steps, the accumulators and the
+    # residual are bitwise the same on 1 thread and on all of them
+    import paper_2110_13055_amd as P
+    from oracle import oracle as lib
+    from helpers import oracle_solver
+    g, p, _ = P.preset("spheres3d_64")
+    n0 = lib.threads()
+    out = []
+    try:
+        for n in (1, max(2, n0)):
+            lib.set_threads(n)
+            o = oracle_solver(g, p)
+            o.flow_steps(6)
+            o.np_steps(4, fused=True)
+            out.append((o.velocity().copy(), o.conc().copy(), o.balance().copy()))
+    finally:
+        lib.set_threads(n0)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
