@@ -1,0 +1,118 @@
+"""Parity at the full 512^3 size, in the configuration the bench times (pull
+streaming, fused LBM + ion steps, default tuning; FP32, FP16 deviation and
+moment storage, which at tau = 1 meet the FP32 bars).
+
+The oracle cannot step 134M voxels, but one step of the method reads only a
+node's neighbours: after T steps from the rest state, a node's values depend on
+the initial state within T cells. So the oracle steps x-slabs of its own
+voxelisation of the full electrode (all 512 x 512 in y and z, the same ramp
+gradient) and the GPU's full-size fields are compared with them wherever the
+slab's artificial x ends cannot have reached: at the real inlet, in the middle
+and at the real outlet. Everywhere beyond the inlet's reach the GPU's velocity
+must be exactly zero (the rest state is a fixed point of the collision), which
+checks every node of the lattice.
+
+Bars: labels and fluid numbering bitwise; velocity rel L2 <= 1e-5; |C_gpu -
+C_oracle| <= 1e-5 (ten FP32 ion updates of values near c0 = 1 round to a few
+1e-7 each).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import oracle_cfg, oracle_labels, rel_l2
+from oracle import OracleSolver
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2110_13055_amd")
+from paper_2110_13055_amd import _lib as L  # noqa: E402
+
+FLOW, FUSED = 2, 10          # the bench's start: two flow steps, then fused steps
+T = FLOW + FUSED             # steps every field has taken
+REACH = T + 2                # cells a boundary's influence can travel, with a margin
+
+
+def _setup():
+    g, p, _ = P.preset("spheres3d_512", precision=L.FP32, streaming=L.STREAM_PULL)
+    lab = oracle_labels(g)
+    _, fl = oracle.compact(lab)
+    # the default K_a depends on the porosity of the whole electrode; both
+    # sides get the full electrode's value (a slab's own porosity differs)
+    p = dataclasses.replace(p, Ka=(4.28e-3 / 1.03e-2) * p.u_in * lab.size / fl.size)
+    return g, p, lab, fl
+
+
+def _slabs(g):
+    nx = g.nx
+    return {"inlet": (0, 2 * REACH + 2), "middle": (nx // 2 - REACH - 6, 2 * REACH + 12),
+            "outlet": (nx - 2 * REACH - 2, 2 * REACH + 2)}
+
+
+@pytest.fixture(scope="module")
+def reference():
+    """The oracle's velocity and concentrations on the compared nodes of each slab."""
+    g, p, lab, fl = _setup()
+    x = (fl % g.nx).astype(np.int32)
+    nx, ny, nz = g.nx, g.ny, g.nz
+    out = {}
+    for where, (x0, w) in _slabs(g).items():
+        sl = np.ascontiguousarray(lab.reshape(nz, ny, nx)[:, :, x0:x0 + w]).reshape(-1)
+        gs = dataclasses.replace(g, nx=w)
+        ps = dataclasses.replace(p, dpsi_vt=p.dpsi_vt * w / nx)  # the same potential drop per cell
+        o = OracleSolver(oracle_cfg(gs, ps), sl)
+        o.flow_steps(FLOW)
+        assert o.np_steps(FUSED, fused=True) == 0
+        sel = np.flatnonzero((x >= x0) & (x < x0 + w))  # the full lattice's nodes of the slab, in the slab's order
+        assert sel.size == o.nf
+        xs = x[sel] - x0
+        lo = 0 if x0 == 0 else REACH
+        hi = w - 1 if x0 + w == nx else w - 1 - REACH
+        keep = (xs >= lo) & (xs <= hi)
+        out[where] = (sel[keep], o.velocity()[:, keep], o.conc()[:, keep])
+        del o
+    return dict(g=g, p=p, lab=lab, fl=fl, x=x, slabs=out)
+
+
+@pytest.fixture(scope="module", params=[L.FP32, L.FP16_DEV, L.MOMENTS], ids=["fp32", "fp16_dev", "moments"])
+def gpu_run(request, reference):
+    g, p = reference["g"], dataclasses.replace(reference["p"], precision=request.param)
+    s = P.Solver(g, p)
+    if request.param == L.FP32:
+        assert np.array_equal(s.labels(), reference["lab"])
+        m, f = s.fluid_index()
+        del m
+        assert np.array_equal(f, reference["fl"])
+    s.flow_steps(FLOW)
+    s.np_step(FUSED, fused=True)
+    out = dict(u=s.velocity(), c=s.concentration())
+    del s
+    return out
+
+
+@pytest.mark.parametrize("where", ["inlet", "middle", "outlet"])
+def test_full_size_fused_step_against_oracle_slabs(reference, gpu_run, where):
+    idx, u_ref, c_ref = reference["slabs"][where]
+    u_gpu = gpu_run["u"][:, idx]
+    c_gpu = gpu_run["c"][:, idx].astype(np.float64)
+    assert np.abs(c_ref - 1.0).max() > 1e-3  # migration and adsorption have moved the ions
+    dc = np.abs(c_gpu - c_ref).max()
+    if where == "inlet":
+        assert np.abs(u_ref).max() > 1e-4  # the inlet flow has entered
+        du = rel_l2(u_gpu, u_ref)
+        print(f"{where}: {idx.size} nodes, velocity rel L2 {du:.2e}, max |dC| {dc:.2e}")
+        assert du <= 1e-5
+    else:
+        print(f"{where}: {idx.size} nodes, max |dC| {dc:.2e}")
+        assert not np.any(u_ref) and not np.any(u_gpu)
+    assert dc <= 1e-5
+    assert c_gpu.min() >= 0.0
+
+
+def test_full_size_rest_beyond_the_inlets_reach(reference, gpu_run):
+    far = reference["x"] > T + 1
+    assert far.sum() > 0.9 * far.size
+    assert not np.any(gpu_run["u"][:, far])
+    assert np.isfinite(gpu_run["c"]).all() and gpu_run["c"].min() >= 0.0
