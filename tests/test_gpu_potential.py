@@ -188,3 +188,60 @@ def test_snapshot_carries_the_solved_field():
     s.np_step(50)
     t.np_step(50)
     assert np.array_equal(t.concentration(), s.concentration())
+
+
+def _fv_residual(lab3, psi3, psi_e, x_bc, psi_x):
+    """Per fluid cell, the sum over its faces of the finite-volume fluxes of the
+    Laplace problem (no charge): psi_N - psi_P to a fluid neighbour,
+    2 (psi_e - psi_P) to an electrode face, 2 (psi_x - psi_P) at a Dirichlet x
+    end, nothing at inert and field-free faces; y and z wrap. Also returns the
+    norm of the known (Dirichlet) part of the system."""
+    fluid = lab3 == 0
+    psi = np.where(fluid, psi3, 0.0)
+    res = np.zeros_like(psi)
+    known = np.zeros_like(psi)
+    nx = lab3.shape[2]
+    for axis in (0, 1, 2):  # z, y, x of the (nz, ny, nx) arrays
+        for sh in (1, -1):
+            nlab = np.roll(lab3, sh, axis=axis)
+            npsi = np.roll(psi, sh, axis=axis)
+            if axis == 2:  # x does not wrap: the roll brought in the other end's plane
+                end = 0 if sh == 1 else nx - 1
+                nlab = nlab.copy()
+                nlab[:, :, end] = 255
+            res += np.where(nlab == 0, npsi - psi, 0.0)
+            res += np.where(nlab == 1, 2.0 * (psi_e - psi), 0.0)
+            known += np.where(nlab == 1, 2.0 * psi_e, 0.0)
+            if axis == 2:
+                side = 0 if sh == 1 else 1
+                if x_bc[side] == L.PSIX_DIRICHLET:
+                    sl = (slice(None), slice(None), 0 if side == 0 else nx - 1)
+                    res[sl] += 2.0 * (psi_x[side] - psi[sl])
+                    known[sl] += 2.0 * psi_x[side]
+    return res[fluid], float(np.linalg.norm(known[fluid]))
+
+
+def test_full_size_laplace_satisfies_the_discrete_equation():
+    # the bench's potential problem at the full 512^3 size, its launch shape:
+    # electrode at -20, inlet face 0, field-free outlet, Jacobi-PCG from zero
+    g, p, _ = preset("spheres3d_512")
+    s = Solver(g, p)
+    pot = Potential(psi_electrode=-20.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), tol=1e-10, warm_start=False,
+                    check_every=16)
+    it, res = s.solve_potential(pot)
+    assert res <= 1e-10 and it > 50
+    lab = s.labels()
+    _, fl = s.fluid_index()
+    psi = s.potential().astype(np.float64)
+    del s
+    assert psi.min() >= -20.0 - 1e-5 and psi.max() <= 1e-5  # maximum principle
+    assert np.mean((psi > -19.0) & (psi < -1.0)) > 0.01  # not a trivial field
+    dense = np.zeros(lab.size)
+    dense[fl] = psi
+    r, bnorm = _fv_residual(lab.reshape(g.nz, g.ny, g.nx), dense.reshape(g.nz, g.ny, g.nx), -20.0, pot.x_bc,
+                            pot.psi_x)
+    # the CG's FP64 residual is 1e-10 of |b|; what remains is the FP32 rounding
+    # of the stored field: at most 12 half-ulps of 20 per cell
+    print(f"512^3 Laplace: {it} iterations, |R|/|b| {np.linalg.norm(r) / bnorm:.2e}, max |R| {np.abs(r).max():.2e}")
+    assert np.linalg.norm(r) / bnorm <= 1e-6
+    assert np.abs(r).max() <= 1e-4
