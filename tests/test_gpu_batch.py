@@ -166,3 +166,38 @@ def test_unstable_member_is_reported():
     with pytest.raises(L.CdiError) as e:
         b.advance(2, [IONS, IONS])
     assert e.value.code == L.E_UNSTABLE and "member 1" in str(e.value)
+
+
+def test_full_size_batch_of_64_instances():
+    # the bench's batched workload at its full size (64 cubes of edge 48-160,
+    # 49.5M fluid nodes) in its launch configuration: FP32, pull streaming,
+    # autotuned grid, graph-replayed fused step pairs. Every member equals the
+    # same instance stepped alone, bit for bit; the smallest one also matches
+    # the oracle.
+    specs = P.batch_instances(64, precision=L.FP32, streaming=L.STREAM_PULL)
+    n = len(specs)
+    solvers = [Solver(g, p) for g, p in specs]
+    for s in solvers:
+        s.flow_steps(2)
+    b = Batch(solvers)
+    b.autotune(4, [FUSED] * n)
+    b.advance(12, [FUSED] * n)
+    b.synchronize()
+    got = [state(s) for s in solvers]
+    b.close()
+    del b, solvers
+    for k, (g, p) in enumerate(specs):
+        s = Solver(g, p)
+        s.flow_steps(2)
+        s.np_step(12, fused=True)
+        for a, c in zip(state(s), got[k]):
+            assert np.array_equal(a, c), f"member {k}"
+        del s
+    k = int(np.argmin([g.nx * g.ny * g.nz for g, _ in specs]))
+    g, p = specs[k]
+    o = oracle_solver(g, p)
+    o.flow_steps(2)
+    assert o.np_steps(12, fused=True) == 0
+    c, u = got[k][0], got[k][1]
+    assert rel_l2(u, o.velocity()) <= 1e-5
+    assert np.abs(c - o.conc()).max() <= 1e-4
