@@ -136,10 +136,12 @@ def potential_rates(coupled_steps: int = 10):
     except P.CdiError as exc:
         out["coupled_pnp"] = {"error": str(exc)}
     # the steady ion state on this flow and potential (implicit scheme),
-    # BiCGSTAB to 1e-8; per iteration both species: direction 64 B, two
-    # operator applications 86 + 70 B (own vectors, diagonal, coordinates,
-    # map, flux and potential), s 48 B, update 120 B per fluid node
-    per_it_np = 64 + 86 + 48 + 70 + 120
+    # BiCGSTAB to 1e-8; per iteration both species (directions stored
+    # preconditioned): direction 72 B (r, v, p^, diagonal; p^ written), two
+    # operator applications 78 + 70 B (own vectors, coordinates, map, flux
+    # and potential; the second also the diagonal), s^ 56 B, update 120 B per
+    # fluid node
+    per_it_np = 72 + 78 + 56 + 70 + 120
     try:
         s.np_steady(tol=1e-8, max_iter=20, allow_not_converged=True)  # first launches
         res = {}

@@ -16,14 +16,17 @@
 // every workgroup derives the same scalars, and the iterate does not depend
 // on timing or on how often the host checks.
 //
-// Iteration k (species s, K = diag):
+// Iteration k (species s, K = diag). The directions are stored
+// preconditioned, p^ = K^-1 p and s^ = K^-1 s, so that the operator gathers
+// no diagonals (measured on the 512^3 electrode, together with issuing every
+// load of a node before its per-face branches: 7.33 -> 5.89 ms per iteration):
 //   dir     stop test on |r_k|; beta = (rho_k / rho_{k-1}) (alpha / omega);
-//           p = r + beta (p - omega v)
-//   apply   v = A K^-1 p; partial rhat . v
-//   sdir    alpha = rho_k / (rhat . v); s = r - alpha v
-//   apply   t = A K^-1 s; partials t . s, t . t
-//   update  omega = (t . s) / (t . t); x += alpha K^-1 p + omega K^-1 s;
-//           r = s - omega t; partials rho_{k+1} = rhat . r, |r|^2
+//           p^ = K^-1 (r - beta omega v) + beta p^
+//   apply   v = A p^; partial rhat . v
+//   sdir    alpha = rho_k / (rhat . v); s^ = K^-1 (r - alpha v)
+//   apply   t = A s^; partials t . s (s = K s^), t . t
+//   update  omega = (t . s) / (t . t); x += alpha p^ + omega s^;
+//           r = K s^ - omega t; partials rho_{k+1} = rhat . r, |r|^2
 // A species whose residual met the tolerance is frozen (its partials stop
 // changing, so every later test repeats the decision).
 #include "cdi_internal.h"
@@ -80,11 +83,23 @@ __device__ inline void np_node(const Grid &g, const Phys &p, const float *j, int
     unpack_xyz(g, ldu(g.fluid, (uint32_t)n), x, y, z);
     NbCtx ctx;
     nb_ctx<L>(g, x, y, z, p.npx == kNpxPeriodic, ctx);
-    float jP[3];
-    jP[0] = j[n];
-    jP[1] = j[P + n];
-    jP[2] = D == 3 ? j[2 * P + n] : 0.f;
+    // every load is issued before the per-face branches (a load inside a
+    // divergent branch waits for its data before the next face starts): the
+    // six neighbours, then the flux (and potential) of each, at the node
+    // itself where the face is not fluid
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) c.m[k] = nb_get<L>(g, ctx, k + 1);
+    float jP[3], jN[2 * D], psiN[2 * D];
+    jP[0] = ldu(j, (uint32_t)n);
+    jP[1] = ldu(j + P, (uint32_t)n);
+    jP[2] = D == 3 ? ldu(j + (size_t)2 * P, (uint32_t)n) : 0.f;
     const float psiP = p.psi ? ldu(p.psi, (uint32_t)n) : 0.f;
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+        const uint32_t q = (uint32_t)(c.m[k] >= 0 ? c.m[k] : n);
+        jN[k] = ldu(j + (size_t)(k >> 1) * P, q);
+        psiN[k] = p.psi ? ldu(p.psi, q) : 0.f;
+    }
     const float invD2[2] = {2.f * p.invD[0], 2.f * p.invD[1]};
     const float hzD[2] = {0.5f * p.z[0] * p.D[0], 0.5f * p.z[1] * p.D[1]};
     c.b[0] = c.b[1] = 0.0;
@@ -94,8 +109,7 @@ __device__ inline void np_node(const Grid &g, const Phys &p, const float *j, int
         const int axis = k >> 1;
         const int sgi = (k & 1) ? -1 : 1;
         const float sg = (float)sgi;
-        const int m = nb_get<L>(g, ctx, i);
-        c.m[k] = m;
+        const int m = c.m[k];
 #pragma unroll
         for (int s = 0; s < 2; ++s) c.al[s][k] = c.be[s][k] = 0.f;
         if (m == kOutside) {  // an open x end (the ions are not periodic)
@@ -123,10 +137,9 @@ __device__ inline void np_node(const Grid &g, const Phys &p, const float *j, int
 #pragma unroll
             for (int s = 0; s < 2; ++s) c.al[s][k] = p.keff[s];
         } else if (m >= 0) {
-            const float jN = j[axis * P + m];
-            const float hun = 0.25f * (jP[axis] + jN) * sg;
+            const float hun = 0.25f * (jP[axis] + jN[k]) * sg;
             const bool mig = p.psi || axis == 0;  // the ramp has no y/z gradient
-            const float dpsi = p.psi ? ldu(p.psi, (uint32_t)m) - psiP : -sg * p.dpsi_dx;
+            const float dpsi = p.psi ? psiN[k] - psiP : -sg * p.dpsi_dx;
 #pragma unroll
             for (int s = 0; s < 2; ++s) sg_coef(p.D[s], invD2[s], mig ? hun - hzD[s] * dpsi : hun, c.al[s][k], c.be[s][k]);
         }
@@ -268,15 +281,17 @@ __global__ __launch_bounds__(kTile) void nps_dir_kernel(NpsArgs a, int k)
         for (int s = 0; s < 2; ++s) {
             if (!act[s]) continue;
             const uint32_t q = (uint32_t)(s * P + n);
-            const double pn = k == 0 ? ldu(a.r, q)
-                                     : ldu(a.r, q) + beta[s] * (ldu(a.pv, q) - omega[s] * ldu(a.v, q));
+            const double d = (double)ldu(a.dg, q);
+            const double pn = k == 0 ? ldu(a.r, q) / d
+                                     : (ldu(a.r, q) - beta[s] * omega[s] * ldu(a.v, q)) / d + beta[s] * ldu(a.pv, q);
             stu(a.pv, q, pn);
         }
     }
 }
 
-// y = (idt I + A) K^-1 in for the active species, with partials:
-// WHICH 0 (in = p, y = v): rhat . v; WHICH 1 (in = s, y = t): t . s, t . t.
+// y = (idt I + A) in for the active species (in = p^ or s^, already
+// preconditioned), with partials: WHICH 0 (y = v): rhat . v; WHICH 1 (y = t):
+// t . s with s = K s^, t . t.
 template <class L, int WHICH>
 __global__ __launch_bounds__(kTile) void nps_apply_kernel(NpsArgs a)
 {
@@ -295,24 +310,31 @@ __global__ __launch_bounds__(kTile) void nps_apply_kernel(NpsArgs a)
         if (n >= a.g.n_f) continue;
         NpNode<L> c;
         np_node<L>(a.g, a.p, a.j, n, c);
+        // both species' neighbour values (stored preconditioned), all
+        // gathered before any is used (the node's own where the face is not
+        // fluid; not applied there)
+        double vN[2][2 * L::D], vP[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int f = 0; f < 2 * L::D; ++f)
+                vN[s][f] = ldu(in, (uint32_t)(s * P + (c.m[f] >= 0 ? c.m[f] : n)));
+            vP[s] = ldu(in, (uint32_t)(s * P + n));
+        }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             if (!act[s]) continue;
             const uint32_t q = (uint32_t)(s * P + n);
-            const double yP = ldu(in, q) / (double)ldu(a.dg, q);
+            const double yP = vP[s];
             double y = ((double)c.diag[s] + a.idt) * yP;
 #pragma unroll
-            for (int f = 0; f < 2 * L::D; ++f) {
-                const int m = c.m[f];
-                if (m < 0) continue;
-                const uint32_t qm = (uint32_t)(s * P + m);
-                y -= (double)c.be[s][f] * (ldu(in, qm) / (double)ldu(a.dg, qm));
-            }
+            for (int f = 0; f < 2 * L::D; ++f)
+                if (c.m[f] >= 0) y -= (double)c.be[s][f] * vN[s][f];
             stu(out, q, y);
             if (WHICH == 0) {
                 d0[s] += ldu(a.rh, q) * y;
             } else {
-                d0[s] += y * ldu(a.sv, q);
+                d0[s] += y * (yP * (double)ldu(a.dg, q));
                 d1[s] += y * y;
             }
         }
@@ -334,7 +356,7 @@ __global__ __launch_bounds__(kTile) void nps_apply_kernel(NpsArgs a)
     }
 }
 
-// s = r - alpha v
+// s^ = K^-1 (r - alpha v)
 __global__ __launch_bounds__(kTile) void nps_sdir_kernel(NpsArgs a, int k)
 {
     __shared__ double sm[kTile / 64];
@@ -356,12 +378,12 @@ __global__ __launch_bounds__(kTile) void nps_sdir_kernel(NpsArgs a, int k)
         for (int s = 0; s < 2; ++s) {
             if (!act[s]) continue;
             const uint32_t q = (uint32_t)(s * P + n);
-            stu(a.sv, q, ldu(a.r, q) - alpha[s] * ldu(a.v, q));
+            stu(a.sv, q, (ldu(a.r, q) - alpha[s] * ldu(a.v, q)) / (double)ldu(a.dg, q));
         }
     }
 }
 
-// x += alpha K^-1 p + omega K^-1 s; r = s - omega t; partials rho_{k+1}, |r|^2
+// x += alpha p^ + omega s^; r = K s^ - omega t; partials rho_{k+1}, |r|^2
 __global__ __launch_bounds__(kTile) void nps_update_kernel(NpsArgs a, int k)
 {
     __shared__ double sm[kTile / 64];
@@ -386,10 +408,9 @@ __global__ __launch_bounds__(kTile) void nps_update_kernel(NpsArgs a, int k)
         for (int s = 0; s < 2; ++s) {
             if (!act[s]) continue;
             const uint32_t q = (uint32_t)(s * P + n);
-            const double d = (double)ldu(a.dg, q);
-            const double sn = ldu(a.sv, q);
-            stu(a.x, q, ldu(a.x, q) + alpha[s] * (ldu(a.pv, q) / d) + omega[s] * (sn / d));
-            const double rn = sn - omega[s] * ldu(a.t, q);
+            const double sh = ldu(a.sv, q);
+            stu(a.x, q, ldu(a.x, q) + alpha[s] * ldu(a.pv, q) + omega[s] * sh);
+            const double rn = sh * (double)ldu(a.dg, q) - omega[s] * ldu(a.t, q);
             stu(a.r, q, rn);
             rho[s] += ldu(a.rh, q) * rn;
             rr[s] += rn * rn;

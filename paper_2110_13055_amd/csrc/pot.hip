@@ -332,6 +332,11 @@ hipError_t pot_workgroups(int dim, int ntiles, bool nbr, int *G)
                                     : (const void *)pot_dirspmv_kernel<D3Q19, 0, kPotNodes>);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTile, 0);
     if (e != hipSuccess) return e;
+    // at most 4 per CU: with more, one tile step of all resident workgroups
+    // outgrows an XCD's L2 before the neighbouring tiles are read again
+    // (measured on the 512^3 electrode: 1.49 ms per iteration at 4, 1.55 at
+    // the occupancy limit, 1.60 at 3)
+    if (per_cu > kPotWorkgroupsPerCU) per_cu = kPotWorkgroupsPerCU;
     long long g = (long long)cus * (per_cu > 0 ? per_cu : 1);
     g = g < kPotMaxWorkgroups ? g : kPotMaxWorkgroups;
     *G = (int)(ntiles < g ? ntiles : g);

@@ -12,6 +12,7 @@ constexpr int kPsixDirichlet = 0, kPsixNeumann = 1, kPsixPeriodic = 2;
 
 // upper bound of the persistent workgroups of the solve kernels
 constexpr int kPotMaxWorkgroups = 4096;
+constexpr int kPotWorkgroupsPerCU = 4;  // cap on resident solver workgroups per compute unit
 
 // Solver state in device memory (doubles): stop code, iterations done,
 // |r|^2 of the last check, |b|^2, tol^2 |b|^2, Dirichlet faces counted.

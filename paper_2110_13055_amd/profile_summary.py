@@ -168,24 +168,36 @@ def main():
 
 # ---------------------------------------------------------------- potential solve
 
-POT_KERNELS = {"pot_dirspmv_kernel": "direction + A p (stencil)", "pot_axpy_kernel": "x, r update"}
+# per-iteration kernels of the two iterative solvers: role and algorithmic
+# bytes per fluid node (the bench's byte model)
+POT_KERNELS = {"pot_dirspmv_kernel": ("direction + A p (stencil)", 57),
+               "pot_axpy_kernel": ("x, r update", 49)}
+NPS_KERNELS = {"nps_dir_kernel": ("direction p^ = K^-1 p", 72),
+               "nps_apply_kernel<0>": ("v = A p^", 78),
+               "nps_sdir_kernel": ("s^ = K^-1 (r - alpha v)", 56),
+               "nps_apply_kernel<1>": ("t = A s^", 70),
+               "nps_update_kernel": ("x, r update", 120)}
 
 
-def _pot_kernel(name: str):
-    for k in POT_KERNELS:
-        if k in name:
+def _solver_kernel(name: str):
+    m = re.search(r"nps_apply_kernel<[^,>]+, (\d)>", name)
+    if m:
+        return f"nps_apply_kernel<{m.group(1)}>"
+    for k in list(POT_KERNELS) + list(NPS_KERNELS):
+        if "<" not in k and k in name:
             return k
     return None
 
 
 def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
-    """Per-iteration kernels of the potential solve: mean duration, HBM bytes
-    per fluid node and GB/s over the dispatches that did work (launches after
-    the device-side stop return at once and are left out: below 5% of the
-    kernel's longest dispatch)."""
+    """Per-iteration kernels of the potential solve (Jacobi-PCG) and of the
+    implicit ion solve (BiCGSTAB): mean duration, HBM bytes per fluid node and
+    GB/s over the dispatches that did work (launches after the device-side
+    stop return at once and are left out: below 5% of the kernel's longest
+    dispatch)."""
     durs = defaultdict(list)
     for r in _csv(_find(trace, "kernel_trace.csv")):
-        k = _pot_kernel(r["Kernel_Name"])
+        k = _solver_kernel(r["Kernel_Name"])
         if k:
             durs[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
     n_fluid = None
@@ -206,7 +218,7 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
             if "copyBuffer" in r["Kernel_Name"]:
                 copy = v if copy is None or v > copy else copy
                 continue
-            k = _pot_kernel(r["Kernel_Name"])
+            k = _solver_kernel(r["Kernel_Name"])
             if k:
                 per[k].append(v)
         out = {}
@@ -220,31 +232,49 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
     wr, wcopy = counters(write, "WRITE_SIZE")
     copy_bytes = copy_mib * 1024.0 * 1024.0
     fscale, wscale = copy_bytes / fcopy, copy_bytes / wcopy
-    rows = []
-    for k in POT_KERNELS:
-        if k not in durs:
-            continue
-        top = max(durs[k])
-        work = [x for x in durs[k] if x >= 0.05 * top]
-        dur = sum(work) / len(work)
-        fb, wb = fr.get(k, float("nan")) * fscale, wr.get(k, float("nan")) * wscale
-        rows.append(dict(kernel=k, role=POT_KERNELS[k], dispatches=len(work), avg_ms=dur * 1e3,
-                         read_per_node=fb / n_fluid, write_per_node=wb / n_fluid, gbs=(fb + wb) / dur / 1e9))
-    per_iter_ms = sum(r["avg_ms"] for r in rows)
-    per_iter_bytes = sum((r["read_per_node"] + r["write_per_node"]) for r in rows)
+
+    def group(kernels):
+        rows = []
+        for k, (role, alg) in kernels.items():
+            if k not in durs:
+                continue
+            top = max(durs[k])
+            work = [x for x in durs[k] if x >= 0.05 * top]
+            dur = sum(work) / len(work)
+            fb, wb = fr.get(k, float("nan")) * fscale, wr.get(k, float("nan")) * wscale
+            rows.append(dict(kernel=k, role=role, dispatches=len(work), avg_ms=dur * 1e3, alg_per_node=alg,
+                             read_per_node=fb / n_fluid, write_per_node=wb / n_fluid, gbs=(fb + wb) / dur / 1e9,
+                             alg_gbs=alg * n_fluid / dur / 1e9))
+        return rows
+
     record = dict(n_fluid=n_fluid, counter_scale={"FETCH_SIZE": fscale, "WRITE_SIZE": wscale},
-                  kernels=rows, iteration_ms=per_iter_ms, iteration_bytes_per_node=per_iter_bytes,
                   commands=list(commands))
-    md = [f"# Potential solve (Jacobi-PCG) on the 512^3 electrode ({n_fluid} fluid nodes)", "",
+    md = [f"# Iterative solvers on the 512^3 electrode ({n_fluid} fluid nodes)", "",
           "Counter scale from the copy probe: FETCH_SIZE x "
-          f"{fscale:.1f} B, WRITE_SIZE x {wscale:.1f} B per unit.", "",
-          "| kernel | role | working dispatches | avg ms | HBM read B/node | HBM write B/node | GB/s |",
-          "|---|---|---:|---:|---:|---:|---:|"]
-    for r in rows:
-        md.append(f"| {r['kernel']} | {r['role']} | {r['dispatches']} | {r['avg_ms']:.3f} | "
-                  f"{r['read_per_node']:.1f} | {r['write_per_node']:.1f} | {r['gbs']:.0f} |")
-    md += ["", f"One CG iteration: {per_iter_ms:.3f} ms, {per_iter_bytes:.1f} HBM bytes per fluid node.", "",
-           "Commands (repository root; the three runs of the same bench command):", ""]
+          f"{fscale:.1f} B, WRITE_SIZE x {wscale:.1f} B per unit. Algorithmic bytes: what each kernel must move "
+          "per fluid node; measured: the HBM counters.", ""]
+    for key, title, kernels in (("cg", "Potential, Eq. 4-5: Jacobi-PCG, FP64", POT_KERNELS),
+                                ("bicgstab", "Steady ion state (implicit scheme): BiCGSTAB, both species, FP64",
+                                 NPS_KERNELS)):
+        rows = group(kernels)
+        if not rows:
+            continue
+        it_ms = sum(r["avg_ms"] for r in rows)
+        it_bytes = sum(r["read_per_node"] + r["write_per_node"] for r in rows)
+        it_alg = sum(r["alg_per_node"] for r in rows)
+        record[key] = dict(kernels=rows, iteration_ms=it_ms, iteration_bytes_per_node=it_bytes,
+                           iteration_alg_bytes_per_node=it_alg)
+        md += [f"## {title}", "",
+               "| kernel | role | working dispatches | avg ms | algorithmic B/node | HBM read B/node | "
+               "HBM write B/node | measured GB/s | algorithmic GB/s |",
+               "|---|---|---:|---:|---:|---:|---:|---:|---:|"]
+        for r in rows:
+            md.append(f"| {r['kernel']} | {r['role']} | {r['dispatches']} | {r['avg_ms']:.3f} | "
+                      f"{r['alg_per_node']} | {r['read_per_node']:.1f} | {r['write_per_node']:.1f} | "
+                      f"{r['gbs']:.0f} | {r['alg_gbs']:.0f} |")
+        md += ["", f"One iteration: {it_ms:.3f} ms, {it_bytes:.1f} measured vs {it_alg} algorithmic HBM bytes per "
+               f"fluid node ({it_alg * n_fluid / (it_ms * 1e-3) / 1e9:.0f} GB/s algorithmic).", ""]
+    md += ["Commands (repository root; the three runs of the same bench command):", ""]
     md += [f"    {c}" for c in commands]
     return record, "\n".join(md) + "\n"
 
