@@ -147,14 +147,18 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     // storage the face neighbours' moments are loaded once for both parts
     // (the flow's emitters, the ions' mass flux). Measured on the 512^3
     // electrode against loading the ions' inputs after the flow's stores:
-    // FP32 -16 %, moments -17 %, FP16 -16 % per fused step.
-    constexpr bool kEarly = LBM && NP;
+    // FP32 -16 %, moments -17 %, FP16 -16 % per fused step. An ion-only step
+    // loads them the same way, all before its face loop, where a load inside
+    // a divergent branch would wait for its data before the next face starts
+    // (its flux is always the stored one): -27 % per ion-only step.
+    constexpr bool kEarly = NP;
+    constexpr bool kEarlyJ = kEarly && (ST == kF32 || !LBM);
     float ec[2] = {0.f, 0.f}, ej[3] = {0.f, 0.f, 0.f};
     float ecn[2 * D][2], ejn[2 * D];
     if (kEarly && active) {
         ec[0] = b.Cin[n];
         ec[1] = b.Cin[P + n];
-        if (ST == kF32) {
+        if (kEarlyJ) {
             ej[0] = b.jin[n];
             ej[1] = b.jin[P + n];
             ej[2] = D == 3 ? b.jin[2 * P + n] : 0.f;
@@ -165,7 +169,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
             const bool fl = m >= 0;
             ecn[k][0] = fl ? b.Cin[m] : 0.f;
             ecn[k][1] = fl ? b.Cin[P + m] : 0.f;
-            ejn[k] = (fl && ST == kF32) ? b.jin[(k >> 1) * P + m] : 0.f;
+            ejn[k] = (fl && kEarlyJ) ? b.jin[(k >> 1) * P + m] : 0.f;
         }
     }
     // FP16 / moment storage, fused: the node's own and its face neighbours' moments
@@ -216,7 +220,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 jP[0] = r * m.y;
                 jP[1] = r * m.z;
                 jP[2] = r * m.w;
-            } else if (kEarly && ST == kF32) {
+            } else if (kEarlyJ) {
                 jP[0] = ej[0];
                 jP[1] = ej[1];
                 jP[2] = ej[2];
@@ -281,7 +285,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                         const float4 mm = (have_m && !xb) ? mface[k] : ldu(b.Min, (uint32_t)m);
                         jN = (1.f + mm.x) * (axis == 0 ? mm.y : (axis == 1 ? mm.z : mm.w));
                     } else {
-                        jN = (early && ST == kF32) ? ejn[k] : b.jin[axis * P + m];
+                        jN = (early && kEarlyJ) ? ejn[k] : b.jin[axis * P + m];
                     }
                     // half the face-normal drift: advection by the mean flux of the
                     // two cells, migration down the potential difference
