@@ -509,6 +509,10 @@ hipError_t nps_workgroups(int dim, int ntiles, int *G)
     const void *k = dim == 2 ? (const void *)nps_apply_kernel<D2Q9, 1> : (const void *)nps_apply_kernel<D3Q19, 1>;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTile, 0);
     if (e != hipSuccess) return e;
+    // at most 4 per CU (measured on the 512^3 electrode: 5.68 ms per
+    // iteration at 4, 5.90 at the occupancy limit of 5, 6.05 at 3): fewer
+    // tiles in flight per XCD leave more of its L2 to the neighbours' lines
+    if (per_cu > kNpsWorkgroupsPerCU) per_cu = kNpsWorkgroupsPerCU;
     long long g = (long long)cus * (per_cu > 0 ? per_cu : 1);
     g = g < kNpsMaxWorkgroups ? g : kNpsMaxWorkgroups;
     *G = (int)(ntiles < g ? ntiles : g);

@@ -8,6 +8,7 @@
 namespace cdi {
 
 constexpr int kNpsMaxWorkgroups = 4096;
+constexpr int kNpsWorkgroupsPerCU = 4;  // cap on resident solver workgroups per compute unit
 
 // Solver state (doubles): per species s, active flag (1 while iterating),
 // iterations done, |r|^2 of the last test, |rhs|^2, tol^2 |rhs|^2; then a
