@@ -9,7 +9,10 @@
  *     rho = sum f, u = sum e f / rho; viscosity nu = (tau - 1/2)/3; no-flow
  *     by bounce-back at solid faces (Sec. 2);
  *   - ions: Nernst-Planck, Eq. (3), advection + diffusion + migration in a
- *     prescribed potential (thermal voltages, psi~ = e psi / k_B T);
+ *     prescribed potential or the solution of Poisson's equation with its
+ *     charge density, Eq. (4)-(5) (thermal voltages, psi~ = e psi / k_B T);
+ *     explicit steps, or the implicit scheme of Sec. 2 (backward Euler and
+ *     the steady state);
  *   - adsorption: linear law D dC/dn = K_a C at electrode faces, Eq. (6);
  *   - geometry: one lattice node per image voxel (Sec. 2, MAC grid).
  *
