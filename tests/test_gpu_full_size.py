@@ -116,3 +116,24 @@ def test_full_size_rest_beyond_the_inlets_reach(reference, gpu_run):
     assert far.sum() > 0.9 * far.size
     assert not np.any(gpu_run["u"][:, far])
     assert np.isfinite(gpu_run["c"]).all() and gpu_run["c"].min() >= 0.0
+
+
+def test_full_size_128_sphere_electrode_against_oracle():
+    # the 128^3 overlapping-sphere electrode (porosity 0.5, inlet/outlet, periodic y/z,
+    # 20 thermal voltages) at its full size in its own configuration: every node
+    # against the oracle after flow and fused steps
+    g, p, _ = P.preset("spheres3d_128")
+    s = P.Solver(g, p)
+    o = OracleSolver(oracle_cfg(g, p), oracle_labels(g))
+    s.flow_steps(300)
+    o.flow_steps(300)
+    s.np_step(150, fused=True)
+    assert o.np_steps(150, fused=True) == 0
+    du = rel_l2(s.velocity(), o.velocity())
+    c_ref = o.conc()
+    dc = float(np.abs(s.concentration() - c_ref).max())
+    a_ref = o.adsorbed_total()
+    da = float(np.max(np.abs(s.adsorbed_total() - a_ref) / np.abs(a_ref)))
+    print(f"128^3: {s.n_fluid} nodes, velocity rel L2 {du:.2e}, max |dC| {dc:.2e}, adsorbed rel {da:.2e}")
+    assert np.abs(c_ref - 1.0).max() > 1e-2
+    assert du <= 1e-5 and dc <= 1e-4 and da <= 1e-4
