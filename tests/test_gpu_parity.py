@@ -118,11 +118,13 @@ def test_flow_to_steady_residual_sequence_matches_oracle():
         assert abs(r - ro) <= 1e-3 * ro
 
 
-def test_flow_to_steady_fp32_steady_state():
-    # FP32 storage of f - w_i resolves velocity changes down to about
-    # ulp(w_i * |rho - 1|) / |u|; below that the residual stops falling and
-    # the call reports STAGNATED with the reached residual. The state it
-    # reaches is compared with the FP64 steady state at r <= 1e-8.
+def test_flow_to_steady_fp32_steady_state_then_5k_ion_steps():
+    # The 2D channel's whole protocol: flow to a residual of 1e-8, then 5000
+    # ion steps on the frozen flow. FP32 storage of f - w_i resolves velocity
+    # changes down to about ulp(w_i * |rho - 1|) / |u|; below that the
+    # residual stops falling and the call reports STAGNATED with the reached
+    # residual. The state it reaches is compared with the FP64 steady state at
+    # r <= 1e-8, and the ions after 5000 steps on each with the parity bars.
     g, p, _ = preset("channel2d_128x64")
     s = Solver(g, p)
     rc, steps, r = s.flow_to_steady(tol=1e-8, max_steps=400000, check_every=100)
@@ -133,6 +135,11 @@ def test_flow_to_steady_fp32_steady_state():
     assert rco == 0
     assert rc in (L.OK, L.STAGNATED)
     assert err <= 1e-4
+    o.freeze_velocity()
+    s.np_step(5000)
+    assert o.np_steps(5000) == 0
+    assert np.abs(o.conc() - 1.0).max() > 0.1
+    _check_np(s, o)
 
 
 # ------------------------------------------------------------------ Nernst-Planck
