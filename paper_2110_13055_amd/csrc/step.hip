@@ -95,7 +95,7 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
 
 // One 256-node tile of one instance (all threads of the workgroup call it;
 // sm: (kTile/64)*6 doubles of LDS).
-template <class L, int ST, int ODD, int LBM, int NP>
+template <class L, int ST, int ODD, int LBM, int NP, int BATCH = 0>
 __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, const Phys &p, const Bufs &b, int tile, double *sm)
 {
     constexpr int Q = L::Q, D = L::D;
@@ -153,8 +153,15 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     // (its flux is always the stored one): -27 % per ion-only step.
     constexpr bool kEarly = NP;
     constexpr bool kEarlyJ = kEarly && (ST == kF32 || !LBM);
+    // with a potential field, the neighbours' potential too, where the flux
+    // is loaded early (ion-only step 1.18 -> 0.96 ms, FP32 fused 3.50 ->
+    // 3.27 ms on the 512^3 electrode, same waves per SIMD); not in the
+    // batched kernels, whose per-instance descriptor leaves no registers to
+    // spare (their ion-only and FP16 / moment fused forms lose a wave per
+    // SIMD, which costs the served requests, all in the ramp, 10 %)
+    constexpr bool kEarlyPsi = kEarlyJ && !BATCH;
     float ec[2] = {0.f, 0.f}, ej[3] = {0.f, 0.f, 0.f};
-    float ecn[2 * D][2], ejn[2 * D];
+    float ecn[2 * D][2], ejn[2 * D], epsi[2 * D];
     if (kEarly && active) {
         ec[0] = b.Cin[n];
         ec[1] = b.Cin[P + n];
@@ -170,6 +177,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
             ecn[k][0] = fl ? b.Cin[m] : 0.f;
             ecn[k][1] = fl ? b.Cin[P + m] : 0.f;
             ejn[k] = (fl && kEarlyJ) ? b.jin[(k >> 1) * P + m] : 0.f;
+            epsi[k] = (kEarlyPsi && p.psi) ? ldu(p.psi, (uint32_t)(fl ? m : n)) : 0.f;
         }
     }
     // FP16 / moment storage, fused: the node's own and its face neighbours' moments
@@ -341,7 +349,8 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                     // two cells, migration down the potential difference
                     const float hun = 0.25f * (jP[axis] + jN) * sg;
                     const bool mig = p.psi || axis == 0;  // the ramp has no y/z gradient
-                    const float dpsi = p.psi ? ldu(p.psi, (uint32_t)m) - psiP : -sg * p.dpsi_dx;
+                    const float dpsi = p.psi ? (kEarlyPsi && early ? epsi[k] : ldu(p.psi, (uint32_t)m)) - psiP
+                                             : -sg * p.dpsi_dx;
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
                         const float hw = mig ? hun - hzD[s] * dpsi : hun;
@@ -438,7 +447,7 @@ __global__ __launch_bounds__(kTile) void batch_kernel(const BatchInst *__restric
         const Grid g = inst[e.x].g;
         const Phys p = inst[e.x].p;
         const Bufs b = inst[e.x].b;
-        step_tile<L, ST, ODD, LBM, NP>(g, p, b, e.y, sm);
+        step_tile<L, ST, ODD, LBM, NP, 1>(g, p, b, e.y, sm);
     }
 }
 
