@@ -664,7 +664,12 @@ static double cell_outflow(const oracle_solver *s, int64_t v, int sp, const doub
                 dg += s->keff[sp];
             } else if (L == 0) {
                 const double un = 0.5 * (s->u[(int64_t)axis * s->nvox + v] + s->u[(int64_t)axis * s->nvox + vn]) * sgn;
-                const double w = un - z * D * (s->psi[vn] - psip);
+                /* The applied ramp is a uniform field: across the seam of
+                 * periodic ions its step is the same as on every x face (the
+                 * stored ramp values would jump by the whole drop there). */
+                const int seam = axis == 0 && (x + sgn < 0 || x + sgn >= c->nx);
+                const double dpsi = (seam && !s->psi_is_field) ? -sgn * c->dpsi / c->nx : s->psi[vn] - psip;
+                const double w = un - z * D * dpsi;
                 out += sg_flux(D, w, cp, C[(int64_t)sp * s->nvox + vn]);
                 dg += D * bern(-w / D);
             }

@@ -363,3 +363,34 @@ def test_two_runs_are_bitwise_identical():
         outs.append((s.concentration(), s.velocity(), s.adsorbed_total()))
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("npx", [L.NPX_PERIODIC, L.NPX_CLOSED], ids=["periodic", "closed"])
+@pytest.mark.parametrize("fused", [False, True])
+def test_np_x_ends_with_open_flow(npx, fused):
+    # the ions' x ends differ from the flow's (inlet/outlet): periodic ions
+    # look the wrapped neighbour up again, closed ends carry no flux
+    g, p = small3d(seed=11)
+    p.np_x_bc = npx
+    s, o = _flow_then_np(g, p, 300, 201, fused)
+    _check_np(s, o)
+    if fused:
+        assert rel_l2(s.velocity(), o.velocity()) <= 1e-5
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_periodic_ions_in_a_potential_field(fused):
+    import torch
+    g, p = small3d(seed=12)
+    p.np_x_bc = L.NPX_PERIODIC
+    lab = oracle_labels(g)
+    _, fl = oracle.compact(lab)
+    psi = np.random.default_rng(6).normal(0.0, 0.3, fl.size)
+    p.psi_field = torch.tensor(psi, dtype=torch.float32, device="cuda")
+    s = Solver(g, p)
+    o = oracle_solver(g, p, psi=psi.astype(np.float32).astype(np.float64))
+    s.flow_steps(300)
+    o.flow_steps(300)
+    s.np_step(201, fused=fused)
+    assert o.np_steps(201, fused=fused) == 0
+    _check_np(s, o)

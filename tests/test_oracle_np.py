@@ -256,3 +256,24 @@ def test_explicit_steady_state_equals_sparse_direct_solve():
     s2.np_steps(6000)
     e2 = np.abs(s2.conc() - cstar).max()
     assert e2 < 0.5 * e1
+
+
+def test_periodic_ions_in_the_applied_ramp_see_a_uniform_field():
+    # The applied ramp is a uniform field. On a periodic line without flow it
+    # drives each species with the uniform drift w = z D dpsi / N, across the
+    # periodic seam too, so the transient is the Fourier closed form of a
+    # uniform drift (opposite for the two species).
+    N, D, dpsi, n = 32, 0.08, 4.0, 60
+    cfg = OracleCfg(dim=2, nx=N, ny=1, D=(D, D), u_in=0.0, dpsi=dpsi, np_x_bc=NPX_PERIODIC)
+    s = OracleSolver(cfg, _line(N))
+    s.set_velocity(np.zeros((2, N)))
+    rng = np.random.default_rng(3)
+    c0 = 1.0 + 0.5 * rng.random((2, N))
+    s.set_conc(c0)
+    assert s.np_steps(n) == 0
+    k = 2 * np.pi * np.fft.fftfreq(N)
+    for sp, z in ((0, 1), (1, -1)):
+        pe = z * D * dpsi / N / D
+        G = 1 - D * (bern(-pe) + bern(pe)) + D * bern(pe) * np.exp(1j * k) + D * bern(-pe) * np.exp(-1j * k)
+        ref = np.real(np.fft.ifft(G ** n * np.fft.fft(c0[sp])))
+        assert np.abs(s.conc()[sp] - ref).max() < 1e-12
