@@ -394,3 +394,20 @@ def test_periodic_ions_in_a_potential_field(fused):
     s.np_step(201, fused=fused)
     assert o.np_steps(201, fused=fused) == 0
     _check_np(s, o)
+
+
+@pytest.mark.parametrize("npx", [L.NPX_INLET_OUTLET, L.NPX_DIRICHLET], ids=["open", "dirichlet"])
+@pytest.mark.parametrize("fused", [False, True])
+def test_open_ion_ends_in_a_periodic_flow(npx, fused):
+    # the flow is periodic in x (body force) while the ions enter at c0 and
+    # leave through an open or Dirichlet end: the wrapped lattice neighbour
+    # is not an ion neighbour
+    g, p = small3d(seed=13, drive=L.BODY_FORCE, body_force=(2e-6, 0.0, 0.0))
+    p.u_in = 0.0
+    p.np_x_bc = npx
+    p.c_out = 0.4
+    p.Ka = 1e-3
+    s, o = _flow_then_np(g, p, 400, 201, fused)
+    _check_np(s, o)
+    if fused:
+        assert rel_l2(s.velocity(), o.velocity()) <= 1e-5
