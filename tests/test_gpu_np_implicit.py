@@ -200,3 +200,19 @@ def test_full_size_steady_state_balances_every_cell():
           f"max gross face flux {gross.max():.2e}, max C {c.max():.3g}")
     assert np.abs(out).max() <= 1e-5 * gross.max()
     assert np.abs(c - p.c0).max() > 1e-2  # the ions have moved
+
+
+@pytest.mark.parametrize("npx", [L.NPX_PERIODIC, L.NPX_CLOSED], ids=["periodic", "closed"])
+def test_backward_euler_with_periodic_or_closed_ion_ends(npx):
+    # the implicit operator with the ions' x ends periodic (the ramp's
+    # uniform field across the seam) or closed, under the open flow
+    g, p = spheres(np_x_bc=npx)
+    s, o = pair(g, p, 400)
+    m0 = s.mass_balance()[:, 0].copy()
+    s.np_implicit(5.0, 8, tol=1e-11)
+    assert o.np_implicit(5.0, 8, tol=1e-13)[0] == 0
+    assert np.abs(s.concentration() - o.conc()).max() <= 1e-4
+    b = s.mass_balance()
+    M, A, In, Out = b[:, 0], b[:, 1], b[:, 2], b[:, 3]
+    assert np.all(np.abs(In) == 0) and np.all(np.abs(Out) == 0)  # nothing crosses the x ends
+    assert np.all(np.abs(M + A - m0) <= 1e-5 * m0)
