@@ -25,6 +25,7 @@ import hashlib
 import json
 import os
 import re
+import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -143,7 +144,71 @@ def summarise(trace, fetch, write, bench_log, copy_mib, commands=()):
     return record, "\n".join(md) + "\n"
 
 
+STALL_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_LDS")
+
+
+def summarise_stalls(dirs, commands=()):
+    """Per step-kernel variant, from SQ counter passes (each directory one
+    rocprofv3 --pmc run, each holding SQ_WAVES): instructions issued per wave
+    (VALU, SALU, vector-memory reads and writes, LDS), the fraction of wave
+    cycles spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES). A wave covers 64
+    fluid nodes. Totals over all dispatches of a
+    variant, divided by that pass's total of SQ_WAVES."""
+    tot = defaultdict(lambda: defaultdict(float))
+    waves = defaultdict(lambda: defaultdict(float))
+    for d in dirs:
+        for r in _csv(_find(d, "counter_collection.csv")):
+            k = _variant(r["Kernel_Name"])
+            if not k:
+                continue
+            v = float(r["Counter_Value"])
+            if r["Counter_Name"] == "SQ_WAVES":
+                waves[k][d] += v
+            else:
+                tot[k][(r["Counter_Name"], d)] += v
+    rows = []
+    for k in sorted(tot):
+        row = {"variant": k}
+        for (cn, d), v in tot[k].items():
+            w = waves[k].get(d)
+            if w:
+                row[cn] = v / w
+        if "SQ_WAIT_ANY" in row and "SQ_WAVE_CYCLES" in row:
+            row["wait_fraction"] = row["SQ_WAIT_ANY"] / row["SQ_WAVE_CYCLES"]
+        rows.append(row)
+    md = ["# Step kernels on the 512^3 electrode: instructions per wave and waiting", "",
+          "Per wave (64 fluid nodes), from the SQ counters; waiting = SQ_WAIT_ANY / SQ_WAVE_CYCLES.", "",
+          "| kernel | VALU | SALU | VMEM read | VMEM write | LDS | waiting |",
+          "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        def f(c):
+            return f"{r[c]:.0f}" if c in r else "-"
+        wf = f"{100 * r['wait_fraction']:.0f} %" if "wait_fraction" in r else "-"
+        md.append(f"| {r['variant']} | {f('SQ_INSTS_VALU')} | {f('SQ_INSTS_SALU')} | "
+                  f"{f('SQ_INSTS_VMEM_RD')} | {f('SQ_INSTS_VMEM_WR')} | {f('SQ_INSTS_LDS')} | {wf} |")
+    md += ["", "Commands (repository root):", ""] + [f"    {c}" for c in commands]
+    return {"kernels": rows, "commands": list(commands)}, "\n".join(md) + "\n"
+
+
+def main_stalls(argv):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stalls", action="store_true")
+    ap.add_argument("--pmc", action="append", required=True, help="a rocprofv3 --pmc output directory")
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--json", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    a = ap.parse_args(argv)
+    rec, md = summarise_stalls(a.pmc, a.command)
+    with open(a.json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    with open(a.md, "w") as fh:
+        fh.write(md)
+
+
 def main():
+    if "--stalls" in sys.argv[1:]:
+        return main_stalls(sys.argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
