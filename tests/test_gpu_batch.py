@@ -201,3 +201,34 @@ def test_full_size_batch_of_64_instances():
     c, u = got[k][0], got[k][1]
     assert rel_l2(u, o.velocity()) <= 1e-5
     assert np.abs(c - o.conc()).max() <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [L.FP32, L.MOMENTS])
+def test_batch_members_in_a_solved_potential_equal_members_alone(precision):
+    # members whose ions migrate in a solved potential field (the batched
+    # kernels read the neighbours' potential in the face loop, the
+    # single-instance kernels with their other early loads): the same numbers
+    from paper_2110_13055_amd import Potential
+    specs = members(precision, n=3)
+    pot = Potential(psi_electrode=-1.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), tol=1e-12)
+
+    def prepared():
+        out = []
+        for g, p in specs:
+            s = Solver(g, p)
+            s.flow_steps(20)
+            s.solve_potential(pot)
+            out.append(s)
+        return out
+    alone = prepared()
+    for s in alone:
+        s.np_step(9, fused=True)
+        s.np_step(6)
+    batched = prepared()
+    b = Batch(batched)
+    b.advance(9, [FUSED] * 3)
+    b.advance(6, [IONS] * 3)
+    b.synchronize()
+    for k, (a, c) in enumerate(zip(alone, batched)):
+        for x, y in zip(state(a), state(c)):
+            assert np.array_equal(x, y), f"member {k}"
