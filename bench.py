@@ -99,16 +99,19 @@ def potential_rates(coupled_steps: int = 10):
     1e-8. Coupled: fused LBM + ion steps with the potential re-solved from the
     current charge (electrode at -4, kappa2 = 0.5, warm start, 1e-6) before
     every step.
-    Algorithmic bytes of one CG iteration per fluid node: the stencil kernel
+    Algorithmic bytes of one CG iteration per fluid node (the iterations of
+    the mixed-precision refinement run on FP32 vectors): the stencil kernel
     reads r, the old direction, the diagonal byte and the six face-neighbour
-    indices and writes the new direction and q = A p (57 B); the update
-    kernel reads x, r, p, q and the diagonal byte and writes x, r (49 B)."""
+    indices and writes the new direction and q = A p (41 B); the update
+    kernel reads x, r, p, q and the diagonal byte and writes x, r (25 B). The
+    refinement rounds' FP64 residuals (two or three per solve) are inside the
+    timed solve but not in this per-iteration count."""
     import torch
     import paper_2110_13055_amd as P
     g, p, _ = P.preset(WORKLOAD)
     s = P.Solver(g, p)
     nf = s.n_fluid
-    per_iter = (8 + 8 + 1 + 24 + 8 + 8) + (32 + 1 + 16)
+    per_iter = (4 + 4 + 1 + 24 + 4 + 4) + (16 + 1 + 8)
     out = {"n_fluid": nf, "algorithmic_bytes_per_node_iter": round(per_iter, 1)}
     pot = P.Potential(psi_electrode=-20.0, x_bc=(P.PSIX_DIRICHLET, P.PSIX_NEUMANN), tol=1e-8,
                       warm_start=False, check_every=16)

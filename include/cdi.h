@@ -337,9 +337,13 @@ int cdi_batch_autotune(cdi_batch *b, int32_t steps, const int32_t *modes, int32_
  * psi_N - psi_P, an electrode face 2 (psi_electrode - psi_P) (the value holds
  * on the face, half a cell from the centre), an inert face nothing, and each
  * x-end face is Dirichlet (value psi_x), field-free, or periodic (both ends).
- * The symmetric positive definite system is solved by Jacobi-preconditioned
- * conjugate gradients in FP64 on the GPU; the result (stored as FP32) becomes
- * the potential of every later ion step. */
+ * The symmetric positive definite system is solved on the GPU by mixed-
+ * precision iterative refinement: each round forms the FP64 residual of the
+ * FP64 iterate and solves for the correction by Jacobi-preconditioned
+ * conjugate gradients on FP32 vectors (sums in FP64), until the FP64
+ * residual meets tol; a round that gains less than 4x hands over to the same
+ * CG on FP64 vectors (fp64 = 1: that CG alone). The result (stored as FP32) becomes the potential of
+ * every later ion step. */
 enum { CDI_PSIX_DIRICHLET = 0, CDI_PSIX_NEUMANN = 1, CDI_PSIX_PERIODIC = 2 };
 
 typedef struct {
@@ -351,14 +355,16 @@ typedef struct {
     int32_t max_iter;      /* iteration cap */
     int32_t check_every;   /* iterations between convergence read-backs (0 = 32) */
     int32_t warm_start;    /* 1: start from the field in use (if any), 0: from zero */
+    int32_t fp64;          /* 1: CG on FP64 vectors throughout (no FP32 rounds);
+                              0: mixed-precision refinement */
 } cdi_potential;
 
 typedef struct {
-    int32_t iterations;    /* CG iterations taken */
+    int32_t iterations;    /* CG iterations taken (over all refinement rounds) */
     double residual;       /* final |b - A psi|_2 / |b|_2 */
 } cdi_potential_result;
 
-/* Device workspace of the solve (5 FP64 vectors and a byte per node, plus
+/* Device workspace of the solve (5 FP64 and 5 FP32 vectors and a byte per node, plus
  * per-workgroup sums); needed only during the call. The solve reads face
  * neighbours from the solver's neighbour list when the potential's x ends
  * are periodic exactly when the lattice's are, else through the voxel map;

@@ -75,7 +75,8 @@ class CTuning(C.Structure):
 class CPotential(C.Structure):
     _fields_ = [("psi_electrode", C.c_double), ("x_bc", C.c_int32 * 2), ("psi_x", C.c_double * 2),
                 ("kappa2", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("check_every", C.c_int32), ("warm_start", C.c_int32)]
+                ("check_every", C.c_int32), ("warm_start", C.c_int32),
+                ("fp64", C.c_int32)]
 
 
 class CPotentialResult(C.Structure):

@@ -960,6 +960,7 @@ namespace {
 
 struct PotLayout {
     double *x, *r, *p, *p2, *q, *part, *state;
+    float *xf, *rf, *pf, *pf2, *qf;
     uint8_t *dg;
     uint64_t bytes;
 };
@@ -973,6 +974,11 @@ PotLayout pot_layout(void *ws, int P)
     L.p = c.take<double>(8ull * P);
     L.p2 = c.take<double>(8ull * P);
     L.q = c.take<double>(8ull * P);
+    L.xf = c.take<float>(4ull * P);
+    L.rf = c.take<float>(4ull * P);
+    L.pf = c.take<float>(4ull * P);
+    L.pf2 = c.take<float>(4ull * P);
+    L.qf = c.take<float>(4ull * P);
     L.dg = c.take<uint8_t>((uint64_t)P);
     L.part = c.take<double>(8ull * pot_part_doubles());
     L.state = c.take<double>(8ull * kStSlots);
@@ -1024,6 +1030,11 @@ int solve_potential(cdi_solver *s, const cdi_potential *pc, void *ws, uint64_t w
     a.p = W.p;
     a.p2 = W.p2;
     a.q = W.q;
+    a.xf = W.xf;
+    a.rf = W.rf;
+    a.pf = W.pf;
+    a.pf2 = W.pf2;
+    a.qf = W.qf;
     // the neighbour list (built at init, one gather round trip fewer than the
     // map lookup; measured 6% faster per iteration on the 512^3 electrode)
     // follows the lattice's x ends: usable when the potential treats them alike
@@ -1045,13 +1056,43 @@ int solve_potential(cdi_solver *s, const cdi_potential *pc, void *ws, uint64_t w
         st[kStDone] = kDoneConverged;
         st[kStRr] = 0;
     } else {
+        // Mixed-precision refinement: each round forms the FP64 residual of x,
+        // solves for the correction by CG on FP32 vectors (half the bytes of
+        // an FP64 iteration) and adds it in FP64, until the FP64 residual
+        // meets tol. A round that gains less than kPotRefineMinGain (the FP32
+        // correction has reached its accuracy) hands over to CG on the FP64
+        // vectors from the current x (pc->fp64: from the start). `iters`
+        // counts CG iterations of both.
         const int chunk = pc->check_every > 0 ? pc->check_every : 32;
-        while (st[kStDone] == 0 && iters < pc->max_iter) {
-            const int n = std::min(chunk, pc->max_iter - iters);
-            for (int k = iters; k < iters + n; ++k) HIPCHK(launch_pot_iter(s->dim, a, G, k, s->stream));
-            HIPCHK(launch_pot_check(a, G, iters + n, s->stream));  // the next iteration's stop test
+        bool f64 = pc->fp64 != 0;
+        double prev = INFINITY;
+        for (;;) {
+            HIPCHK(launch_pot_refine(s->dim, a, G, pc->tol, f64 ? 0.0 : kPotInnerTol, f64, s->stream));
             if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
-            iters = st[kStDone] != 0 ? (int)st[kStIters] : iters + n;
+            if (st[kStDone] != 0 || iters >= pc->max_iter) break;
+            if (!f64 && st[kStRr] * kPotRefineMinGain * kPotRefineMinGain > prev) {
+                f64 = true;
+                HIPCHK(launch_pot_refine(s->dim, a, G, pc->tol, 0.0, true, s->stream));
+                if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
+            }
+            prev = st[kStRr];
+            int kin = 0;
+            while (st[kStDone] == 0 && iters < pc->max_iter) {
+                const int n = std::min(chunk, pc->max_iter - iters);
+                for (int k = kin; k < kin + n; ++k) HIPCHK(launch_pot_iter(s->dim, a, G, k, !f64, s->stream));
+                HIPCHK(launch_pot_check(a, G, kin + n, s->stream));  // the next iteration's stop test
+                if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
+                const int kend = st[kStDone] != 0 ? (int)st[kStIters] : kin + n;
+                iters += kend - kin;
+                kin = kend;
+            }
+            const bool bad = st[kStDone] == kDoneDiverged || st[kStDone] == kDoneBreakdown;
+            if (f64) break;
+            if (bad) {  // an FP32 correction that broke down is dropped; FP64 CG takes over
+                prev = 0.0;
+                continue;
+            }
+            HIPCHK(launch_pot_correct(a, s->stream));
         }
         if (st[kStDone] == kDoneDiverged || st[kStDone] == kDoneBreakdown)
             return fail(CDI_E_DIVERGED, "potential solve %s after %d iterations",

@@ -38,7 +38,29 @@ namespace cdi {
 namespace {
 
 // Partial-sum regions, G doubles each.
-enum { kRz0 = 0, kRz1 = 1, kRr = 2, kPq = 3, kBb = 4, kNd = 5, kRegions = 6 };
+// kRo: |r|^2 of the FP64 residual of a refinement round.
+enum { kRz0 = 0, kRz1 = 1, kRr = 2, kPq = 3, kBb = 4, kNd = 5, kRo = 6, kRegions = 7 };
+
+// The vectors a CG iteration works on: FP64 (x, r, q, p, p2) or the FP32
+// set of a refinement round's correction (xf, rf, qf, pf, pf2).
+template <class T>
+struct Vecs;
+template <>
+struct Vecs<double> {
+    __device__ static double *x(const PotArgs &a) { return a.x; }
+    __device__ static double *r(const PotArgs &a) { return a.r; }
+    __device__ static double *q(const PotArgs &a) { return a.q; }
+    __device__ static double *p(const PotArgs &a) { return a.p; }
+    __device__ static double *p2(const PotArgs &a) { return a.p2; }
+};
+template <>
+struct Vecs<float> {
+    __device__ static float *x(const PotArgs &a) { return a.xf; }
+    __device__ static float *r(const PotArgs &a) { return a.rf; }
+    __device__ static float *q(const PotArgs &a) { return a.qf; }
+    __device__ static float *p(const PotArgs &a) { return a.pf; }
+    __device__ static float *p2(const PotArgs &a) { return a.pf2; }
+};
 
 // Whether the solve has stopped, read once per workgroup so that all its
 // waves take the same branch (a stop may be recorded by workgroup 0 of the
@@ -169,9 +191,10 @@ __device__ inline bool stop_test(const PotArgs &a, int k, double *sm)
 // of its fluid neighbours, which it forms from their r, diagonal and old p.
 // NN nodes per thread (tiles t and t + 1 of the range), all loads issued
 // before any arithmetic.
-template <class L, int NBR, int NN>
+template <class L, int NBR, int NN, class T>
 __global__ __launch_bounds__(kTile) void pot_dirspmv_kernel(PotArgs a, int k)
 {
+    using V = Vecs<T>;
     constexpr int F = 2 * L::D;
     __shared__ double sm[kTile / 64];
     __shared__ int stop;
@@ -183,8 +206,9 @@ __global__ __launch_bounds__(kTile) void pot_dirspmv_kernel(PotArgs a, int k)
         beta = region_sum(a.part + (k & 1 ? kRz1 : kRz0) * G, G, sm) /
                region_sum(a.part + (k & 1 ? kRz0 : kRz1) * G, G, sm);
     }
-    const double *pold = k & 1 ? a.p2 : a.p;
-    double *pnew = k & 1 ? a.p : a.p2;
+    const T *pold = k & 1 ? V::p2(a) : V::p(a);
+    T *pnew = k & 1 ? V::p(a) : V::p2(a);
+    const T *rv = V::r(a);
     int t0, t1;
     tile_range(a.g.P / kTile, t0, t1);
     double pq = 0;
@@ -201,32 +225,38 @@ __global__ __launch_bounds__(kTile) void pot_dirspmv_kernel(PotArgs a, int k)
 #pragma unroll
                 for (int f = 0; f < F; ++f) m[j][f] = kInert;
         }
-        double r0[NN], p0[NN], rm[NN][F], pm[NN][F];
+        T r0[NN], p0[NN], rm[NN][F], pm[NN][F];
         int d0[NN], dm[NN][F];
+        // every load unconditional (index 0 where there is no node or no
+        // fluid neighbour; the value is not used there): inside a divergent
+        // branch each gather would wait for its data before the next
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
-            r0[j] = act[j] ? ldu(a.r, (uint32_t)n[j]) : 0.0;
-            p0[j] = act[j] ? ldu(pold, (uint32_t)n[j]) : 0.0;
-            d0[j] = act[j] ? a.dg[n[j]] : 0;
+            const uint32_t q0 = act[j] ? (uint32_t)n[j] : 0u;
+            r0[j] = ldu(rv, q0);
+            p0[j] = ldu(pold, q0);
+            d0[j] = act[j] ? a.dg[q0] : 0;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                const bool fl = m[j][f] >= 0;
-                rm[j][f] = fl ? ldu(a.r, (uint32_t)m[j][f]) : 0.0;
-                pm[j][f] = fl ? ldu(pold, (uint32_t)m[j][f]) : 0.0;
-                dm[j][f] = fl ? a.dg[m[j][f]] : 0;
+                const uint32_t qm = m[j][f] >= 0 ? (uint32_t)m[j][f] : 0u;
+                rm[j][f] = ldu(rv, qm);
+                pm[j][f] = ldu(pold, qm);
+                dm[j][f] = a.dg[qm];
             }
         }
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
             if (!act[j]) continue;
-            const double pn = new_dir(r0[j], d0[j], p0[j], beta);
+            const double pn = new_dir((double)r0[j], d0[j], (double)p0[j], beta);
             double q = d0[j] * pn;
 #pragma unroll
             for (int f = 0; f < F; ++f)
-                if (m[j][f] >= 0) q -= new_dir(rm[j][f], dm[j][f], pm[j][f], beta);
-            stu(pnew, (uint32_t)n[j], pn);
-            stu(a.q, (uint32_t)n[j], q);
-            pq += pn * q;
+                if (m[j][f] >= 0) q -= new_dir((double)rm[j][f], dm[j][f], (double)pm[j][f], beta);
+            // stored in T; the partial is formed from the stored values
+            const T pt = (T)pn, qt = (T)q;
+            stu(pnew, (uint32_t)n[j], pt);
+            stu(V::q(a), (uint32_t)n[j], qt);
+            pq += (double)pt * (double)qt;
         }
     }
     const double s = wg_sum(pq, sm);
@@ -235,8 +265,10 @@ __global__ __launch_bounds__(kTile) void pot_dirspmv_kernel(PotArgs a, int k)
 
 // Iteration k, second half: alpha = rz_k / (p_k . q); x += alpha p_k;
 // r -= alpha q; partials rz_{k+1} (into the other r.z slot) and |r_{k+1}|^2.
+template <class T>
 __global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
 {
+    using V = Vecs<T>;
     __shared__ double sm[kTile / 64];
     __shared__ int stop;
     if (stopped(a.state, &stop)) return;
@@ -248,17 +280,20 @@ __global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
         return;
     }
     const double alpha = rz / pq;
-    const double *pk = k & 1 ? a.p : a.p2;
+    const T *pk = k & 1 ? V::p(a) : V::p2(a);
+    T *xv = V::x(a), *rv = V::r(a);
+    const T *qv = V::q(a);
     int t0, t1;
     tile_range(a.g.P / kTile, t0, t1);
     double rz1 = 0, rr = 0;
     for (int t = t0; t < t1; ++t) {
         const int n = t * kTile + threadIdx.x;
         if (n >= a.g.n_f) continue;
-        const double pn = ldu(pk, (uint32_t)n), qn = ldu(a.q, (uint32_t)n);
-        stu(a.x, (uint32_t)n, ldu(a.x, (uint32_t)n) + alpha * pn);
-        const double rn = ldu(a.r, (uint32_t)n) - alpha * qn;
-        stu(a.r, (uint32_t)n, rn);
+        const double pn = ldu(pk, (uint32_t)n), qn = ldu(qv, (uint32_t)n);
+        stu(xv, (uint32_t)n, (T)(ldu(xv, (uint32_t)n) + alpha * pn));
+        const T rt = (T)(ldu(rv, (uint32_t)n) - alpha * qn);
+        stu(rv, (uint32_t)n, rt);
+        const double rn = rt;
         const int d = a.dg[n];
         const double zn = d > 0 ? rn / d : 0.0;
         rz1 += rn * zn;
@@ -304,6 +339,99 @@ __global__ __launch_bounds__(kTile) void pot_state_kernel(PotArgs a, int G, doub
     }
 }
 
+// Refinement round: the FP64 residual r = b - A x of the current x, its
+// partial |r|^2 (kRo), and the start of an FP32 correction solve A d = r:
+// rf = r, xf = 0, p = z = rf / diag, partial rf . z (kRz0). F64: instead the
+// start of FP64 CG iterations on x itself (r, p = z in FP64).
+template <class L, int F64>
+__global__ __launch_bounds__(kTile) void pot_refine_kernel(PotArgs a)
+{
+    __shared__ double sm[kTile / 64];
+    int t0, t1;
+    tile_range(a.g.P / kTile, t0, t1);
+    const int P = a.g.P;
+    double rz = 0, ro = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int n = t * kTile + threadIdx.x;
+        float rf = 0.f, zf = 0.f;
+        if (n < a.g.n_f) {
+            int m[2 * L::D], diag = 0;
+            node_faces<L>(a, n, m, diag);
+            double b = a.src * ((double)a.z[0] * ldu(a.C, (uint32_t)n) + (double)a.z[1] * ldu(a.C, (uint32_t)(P + n)));
+            double ax = diag * ldu(a.x, (uint32_t)n);
+            double xm[2 * L::D];  // loaded before use (index 0 where not fluid: unused)
+#pragma unroll
+            for (int k = 0; k < 2 * L::D; ++k) xm[k] = ldu(a.x, (uint32_t)(m[k] >= 0 ? m[k] : 0));
+#pragma unroll
+            for (int k = 0; k < 2 * L::D; ++k) {
+                if (m[k] >= 0)
+                    ax -= xm[k];
+                else if (m[k] == kElectrode)
+                    b += 2.0 * a.psi_e;
+                else if (m[k] == kOutside && a.xbc[k & 1 ? 0 : 1] == kPsixDirichlet)
+                    b += 2.0 * a.psi_x[k & 1 ? 0 : 1];
+            }
+            const double r = b - ax;
+            ro += r * r;
+            if (F64) {
+                const double zd = diag > 0 ? r / diag : 0.0;
+                stu(a.r, (uint32_t)n, r);
+                stu(a.p, (uint32_t)n, zd);
+                rz += r * zd;
+            } else {
+                rf = (float)r;
+                const double zd = diag > 0 ? (double)rf / diag : 0.0;  // the z the stencil kernel forms
+                zf = (float)zd;
+                rz += (double)rf * zd;
+            }
+        } else if (F64) {
+            stu(a.r, (uint32_t)n, 0.0);
+            stu(a.p, (uint32_t)n, 0.0);
+        }
+        if (!F64) {
+            stu(a.rf, (uint32_t)n, rf);
+            stu(a.xf, (uint32_t)n, 0.f);
+            stu(a.pf, (uint32_t)n, zf);
+        }
+    }
+    const double s_rz = wg_sum(rz, sm), s_ro = wg_sum(ro, sm);
+    if (threadIdx.x == 0) {
+        const int G = gridDim.x;
+        a.part[kRz0 * G + blockIdx.x] = s_rz;
+        a.part[kRo * G + blockIdx.x] = s_ro;
+    }
+}
+
+// After a refinement kernel (one workgroup): the outer stop test on the FP64
+// residual, |r|^2 <= tol^2 |b|^2 (recorded in kStRr); else the correction
+// solve runs until its residual falls by max(tol_min, tol |b| / |r|).
+__global__ __launch_bounds__(kTile) void pot_refine_state_kernel(PotArgs a, int G, double tol, double tol_min)
+{
+    __shared__ double sm[kTile / 64];
+    const double ro = region_sum(a.part + kRo * G, G, sm);
+    if (threadIdx.x == 0) {
+        const double bb = a.state[kStBb];
+        a.state[kStRr] = ro;
+        a.state[kStIters] = 0;
+        if (!isfinite(ro)) {
+            a.state[kStDone] = kDoneDiverged;
+        } else if (ro <= tol * tol * bb) {
+            a.state[kStDone] = kDoneConverged;
+        } else {
+            const double f2 = fmax(tol_min * tol_min, tol * tol * bb / ro);
+            a.state[kStTol2Bb] = f2 * ro;
+            a.state[kStDone] = 0.0;
+        }
+    }
+}
+
+// x += xf: the correction of a refinement round.
+__global__ __launch_bounds__(kTile) void pot_correct_kernel(double *x, const float *xf, int n_f)
+{
+    const int n = blockIdx.x * kTile + threadIdx.x;
+    if (n < n_f) x[n] += (double)xf[n];
+}
+
 __global__ __launch_bounds__(kTile) void pot_store_kernel(const double *x, float *psi, int n_f)
 {
     const int n = blockIdx.x * kTile + threadIdx.x;
@@ -326,10 +454,10 @@ hipError_t pot_workgroups(int dim, int ntiles, bool nbr, int *G)
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const void *k = dim == 2 ? (nbr ? (const void *)pot_dirspmv_kernel<D2Q9, 1, kPotNodes>
-                                    : (const void *)pot_dirspmv_kernel<D2Q9, 0, kPotNodes>)
-                             : (nbr ? (const void *)pot_dirspmv_kernel<D3Q19, 1, kPotNodes>
-                                    : (const void *)pot_dirspmv_kernel<D3Q19, 0, kPotNodes>);
+    const void *k = dim == 2 ? (nbr ? (const void *)pot_dirspmv_kernel<D2Q9, 1, kPotNodes, double>
+                                    : (const void *)pot_dirspmv_kernel<D2Q9, 0, kPotNodes, double>)
+                             : (nbr ? (const void *)pot_dirspmv_kernel<D3Q19, 1, kPotNodes, double>
+                                    : (const void *)pot_dirspmv_kernel<D3Q19, 0, kPotNodes, double>);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTile, 0);
     if (e != hipSuccess) return e;
     // at most 4 per CU: with more, one tile step of all resident workgroups
@@ -353,22 +481,39 @@ hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStr
     return hipGetLastError();
 }
 
-template <class L>
+template <class L, class T>
 void pot_iter_l(const PotArgs &a, int G, int k, hipStream_t s)
 {
     if (a.nbr)
-        pot_dirspmv_kernel<L, 1, kPotNodes><<<G, kTile, 0, s>>>(a, k);
+        pot_dirspmv_kernel<L, 1, kPotNodes, T><<<G, kTile, 0, s>>>(a, k);
     else
-        pot_dirspmv_kernel<L, 0, kPotNodes><<<G, kTile, 0, s>>>(a, k);
-    pot_axpy_kernel<<<G, kTile, 0, s>>>(a, k);
+        pot_dirspmv_kernel<L, 0, kPotNodes, T><<<G, kTile, 0, s>>>(a, k);
+    pot_axpy_kernel<T><<<G, kTile, 0, s>>>(a, k);
 }
 
-hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, hipStream_t s)
+hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, bool f32, hipStream_t s)
 {
     if (dim == 2)
-        pot_iter_l<D2Q9>(a, G, k, s);
+        f32 ? pot_iter_l<D2Q9, float>(a, G, k, s) : pot_iter_l<D2Q9, double>(a, G, k, s);
     else
-        pot_iter_l<D3Q19>(a, G, k, s);
+        f32 ? pot_iter_l<D3Q19, float>(a, G, k, s) : pot_iter_l<D3Q19, double>(a, G, k, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pot_refine(int dim, const PotArgs &a, int G, double tol, double tol_min, bool f64, hipStream_t s)
+{
+    if (dim == 2)
+        f64 ? pot_refine_kernel<D2Q9, 1><<<G, kTile, 0, s>>>(a) : pot_refine_kernel<D2Q9, 0><<<G, kTile, 0, s>>>(a);
+    else
+        f64 ? pot_refine_kernel<D3Q19, 1><<<G, kTile, 0, s>>>(a) : pot_refine_kernel<D3Q19, 0><<<G, kTile, 0, s>>>(a);
+    pot_refine_state_kernel<<<1, kTile, 0, s>>>(a, G, tol, tol_min);
+    return hipGetLastError();
+}
+
+hipError_t launch_pot_correct(const PotArgs &a, hipStream_t s)
+{
+    const int tiles = a.g.P / kTile;
+    if (tiles > 0) pot_correct_kernel<<<tiles, kTile, 0, s>>>(a.x, a.xf, a.g.n_f);
     return hipGetLastError();
 }
 

@@ -13,6 +13,11 @@ constexpr int kPsixDirichlet = 0, kPsixNeumann = 1, kPsixPeriodic = 2;
 // upper bound of the persistent workgroups of the solve kernels
 constexpr int kPotMaxWorkgroups = 4096;
 constexpr int kPotWorkgroupsPerCU = 4;  // cap on resident solver workgroups per compute unit
+// A refinement round's FP32 correction solve reduces its residual by this
+// factor (or to the overall tolerance, if that is nearer); a round that cuts
+// the FP64 residual by less than kPotRefineMinGain hands over to FP64 CG.
+constexpr double kPotInnerTol = 1e-4;
+constexpr double kPotRefineMinGain = 4.0;
 
 // Solver state in device memory (doubles): stop code, iterations done,
 // |r|^2 of the last check, |b|^2, tol^2 |b|^2, Dirichlet faces counted.
@@ -30,6 +35,8 @@ struct PotArgs {
     const float *psi0;   // start (the field in use) or nullptr (zero)
     double *x, *r, *q;   // CG vectors, P each
     double *p, *p2;      // search direction, alternating between two buffers
+    float *xf, *rf, *qf; // the FP32 vectors of a refinement round's correction solve
+    float *pf, *pf2;
     const int *nbr;      // face neighbours (planes 0 .. 2D-1 of the node list) or nullptr
     uint8_t *dg;         // diagonal of A per node (0 .. 12)
     double *part;        // per-workgroup partial sums (pot_part_doubles)
@@ -44,9 +51,16 @@ uint64_t pot_part_doubles();
 // r = b - A x0, z, p = z, the diagonal, and the state (stop code set when the
 // start already meets tol).
 hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStream_t s);
-// CG iteration k (stop test, direction and A p; then the x and r updates);
-// returns at once after a stop.
-hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, hipStream_t s);
+// CG iteration k (stop test, direction and A p; then the x and r updates) on
+// the FP64 vectors or (f32) on the FP32 set; returns at once after a stop.
+hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, bool f32, hipStream_t s);
+// Refinement round: the FP64 residual of x, the outer stop test (tol), and
+// the start of the FP32 correction solve with its own stop threshold (its
+// residual falls by max(tol_min, tol |b| / |r|)); f64: the start of FP64 CG
+// iterations on x itself instead (tol_min = 0 then stops them at tol).
+hipError_t launch_pot_refine(int dim, const PotArgs &a, int G, double tol, double tol_min, bool f64, hipStream_t s);
+// x += the FP32 correction.
+hipError_t launch_pot_correct(const PotArgs &a, hipStream_t s);
 // The stop test of iteration k alone (after iterations up to k - 1).
 hipError_t launch_pot_check(const PotArgs &a, int G, int k, hipStream_t s);
 // psi[n] = (float) x[n] for the fluid nodes.

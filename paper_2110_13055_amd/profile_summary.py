@@ -235,8 +235,11 @@ def main():
 
 # per-iteration kernels of the two iterative solvers: role and algorithmic
 # bytes per fluid node (the bench's byte model)
-POT_KERNELS = {"pot_dirspmv_kernel": ("direction + A p (stencil)", 57),
-               "pot_axpy_kernel": ("x, r update", 49)}
+POT_KERNELS = {"pot_dirspmv_kernel": ("direction + A p (stencil), FP32 vectors", 41),
+               "pot_axpy_kernel": ("x, r update, FP32 vectors", 25)}
+# once per refinement round of the potential solve (not per iteration)
+POT_ROUND_KERNELS = {"pot_refine_kernel": ("FP64 residual b - A x, FP32 correction start", 52),
+                     "pot_correct_kernel": ("x += FP32 correction", 20)}
 NPS_KERNELS = {"nps_dir_kernel": ("direction p^ = K^-1 p", 72),
                "nps_apply_kernel<0>": ("v = A p^", 78),
                "nps_sdir_kernel": ("s^ = K^-1 (r - alpha v)", 56),
@@ -248,7 +251,7 @@ def _solver_kernel(name: str):
     m = re.search(r"nps_apply_kernel<[^,>]+, (\d)>", name)
     if m:
         return f"nps_apply_kernel<{m.group(1)}>"
-    for k in list(POT_KERNELS) + list(NPS_KERNELS):
+    for k in list(POT_KERNELS) + list(POT_ROUND_KERNELS) + list(NPS_KERNELS):
         if "<" not in k and k in name:
             return k
     return None
@@ -318,7 +321,8 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
           "Counter scale from the copy probe: FETCH_SIZE x "
           f"{fscale:.1f} B, WRITE_SIZE x {wscale:.1f} B per unit. Algorithmic bytes: what each kernel must move "
           "per fluid node; measured: the HBM counters.", ""]
-    for key, title, kernels in (("cg", "Potential, Eq. 4-5: Jacobi-PCG, FP64", POT_KERNELS),
+    for key, title, kernels in (("cg", "Potential, Eq. 4-5: Jacobi-PCG iterations of the mixed-precision refinement",
+                                 POT_KERNELS),
                                 ("bicgstab", "Steady ion state (implicit scheme): BiCGSTAB, both species, FP64",
                                  NPS_KERNELS)):
         rows = group(kernels)
@@ -339,6 +343,17 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
                       f"{r['gbs']:.0f} | {r['alg_gbs']:.0f} |")
         md += ["", f"One iteration: {it_ms:.3f} ms, {it_bytes:.1f} measured vs {it_alg} algorithmic HBM bytes per "
                f"fluid node ({it_alg * n_fluid / (it_ms * 1e-3) / 1e9:.0f} GB/s algorithmic).", ""]
+        rounds = group(POT_ROUND_KERNELS) if key == "cg" else []
+        if rounds:
+            record["cg_round"] = dict(kernels=rounds)
+            md += ["Once per refinement round:", "",
+                   "| kernel | role | dispatches | avg ms | algorithmic B/node | HBM read B/node | "
+                   "HBM write B/node | measured GB/s | algorithmic GB/s |",
+                   "|---|---|---:|---:|---:|---:|---:|---:|---:|"]
+            md += [f"| {r['kernel']} | {r['role']} | {r['dispatches']} | {r['avg_ms']:.3f} | {r['alg_per_node']} | "
+                   f"{r['read_per_node']:.1f} | {r['write_per_node']:.1f} | {r['gbs']:.0f} | {r['alg_gbs']:.0f} |"
+                   for r in rounds]
+            md.append("")
     md += ["Commands (repository root; the three runs of the same bench command):", ""]
     md += [f"    {c}" for c in commands]
     return record, "\n".join(md) + "\n"

@@ -113,6 +113,7 @@ class Potential:
     max_iter: int = 100000
     check_every: int = 0
     warm_start: bool = True
+    fp64: bool = False  # CG on FP64 vectors throughout instead of FP32 refinement rounds
 
     def to_c(self) -> L.CPotential:
         c = L.CPotential()
@@ -121,6 +122,7 @@ class Potential:
         c.psi_x[0], c.psi_x[1] = self.psi_x
         c.kappa2, c.tol, c.max_iter = self.kappa2, self.tol, self.max_iter
         c.check_every, c.warm_start = self.check_every, 1 if self.warm_start else 0
+        c.fp64 = 1 if self.fp64 else 0
         return c
 
 

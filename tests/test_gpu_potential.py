@@ -49,9 +49,10 @@ def both(g, p, pot, conc=None):
 
 @pytest.mark.parametrize("x_bc", [(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), (L.PSIX_DIRICHLET, L.PSIX_DIRICHLET),
                                   (L.PSIX_NEUMANN, L.PSIX_NEUMANN), (L.PSIX_PERIODIC, L.PSIX_PERIODIC)])
-def test_laplace_3d_matches_oracle(x_bc):
+@pytest.mark.parametrize("fp64", [False, True], ids=["refined", "fp64"])
+def test_laplace_3d_matches_oracle(x_bc, fp64):
     g, p = spheres()
-    pot = Potential(psi_electrode=-1.5, x_bc=x_bc, psi_x=(0.0, 2.0), tol=TOL_GPU)
+    pot = Potential(psi_electrode=-1.5, x_bc=x_bc, psi_x=(0.0, 2.0), tol=TOL_GPU, fp64=fp64)
     s, o, it = both(g, p, pot)
     assert s.n_fluid % 256 != 0 and s.n_fluid > 8 * 256  # several tiles and a ragged tail
     ref = o.potential()
@@ -59,13 +60,15 @@ def test_laplace_3d_matches_oracle(x_bc):
 
 
 @pytest.mark.parametrize("kappa2", [0.05, 2.0])
-def test_poisson_2d_with_charge_matches_oracle(kappa2):
+@pytest.mark.parametrize("fp64", [False, True], ids=["refined", "fp64"])
+def test_poisson_2d_with_charge_matches_oracle(kappa2, fp64):
     g, p, _ = preset("channel2d_128x64")
     rng = np.random.default_rng(11)
     s0 = Solver(g, p)
     conc = rng.uniform(0.2, 1.8, size=(2, s0.n_fluid)).astype(np.float32)
     s0.close()
-    pot = Potential(psi_electrode=-3.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), kappa2=kappa2, tol=TOL_GPU)
+    pot = Potential(psi_electrode=-3.0, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), kappa2=kappa2, tol=TOL_GPU,
+                    fp64=fp64)
     s, o, _ = both(g, p, pot, conc)
     ref = o.potential()
     assert np.abs(s.potential() - ref).max() <= bar(ref)
