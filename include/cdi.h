@@ -258,7 +258,10 @@ typedef struct {
     int32_t columns;       /* 3D, 1: tiles of each group of 8 brick layers dealt round-robin over the
                               8 XCDs, so the 8 layers at one (x, y) are processed together (the
                               layers above and below a tile meet in the memory-side cache);
-                              takes precedence over band_rows. 0: off */
+                              2: tiles in the Morton (Z-order) order of their bricks, each XCD
+                              walking a contiguous run of the curve (a brick's neighbours along
+                              every axis are mostly a few bricks away in that XCD's sweep);
+                              either takes precedence over band_rows. 0: off */
     int32_t nbr_list;      /* 1 (the default): the ion-only steps and the fused steps with FP16 or moment
                               storage read each node's neighbours from a list built at init (4 (Q-1)
                               bytes per node of extra reads) instead of looking them up through the

@@ -415,7 +415,20 @@ int64_t xcd_position(int64_t b, int64_t nb)
 //    column, layer in the group) and dealt to workgroups in that order, so
 //    the 8 XCDs work at once on the 8 layers of a group at the same (x, y):
 //    the layers above and below a tile are being fetched by the neighbouring
-//    XCDs and are met in the memory-side cache.
+//    XCDs and are met in the memory-side cache;
+//  * columns == 2: tiles sorted by the Morton (Z-order) index of their brick
+//    and each XCD walks a contiguous run of that curve, so that a brick's
+//    face neighbours along every axis are mostly a few bricks away in the
+//    XCD's own sweep (in the plain order the brick above is a whole layer
+//    of bricks later).
+uint64_t morton3(uint64_t x, uint64_t y, uint64_t z)
+{
+    uint64_t m = 0;
+    for (int b = 0; b < 21; ++b)
+        m |= ((x >> b) & 1) << (3 * b) | ((y >> b) & 1) << (3 * b + 1) | ((z >> b) & 1) << (3 * b + 2);
+    return m;
+}
+
 int build_schedule(cdi_solver *s, int band_rows, int columns)
 {
     const int T = s->ntiles;
@@ -438,7 +451,9 @@ int build_schedule(cdi_solver *s, int band_rows, int columns)
         const int64_t x = c & ((1u << k.cbx) - 1);
         const int64_t y = (c >> k.cbx) & ((1u << k.cby) - 1);
         const int64_t z = c >> (k.cbx + k.cby);
-        if (columns) {
+        if (columns == 2) {
+            key[t] = (int64_t)morton3(x >> k.bsx, y >> k.bsy, z >> k.bsz);
+        } else if (columns) {
             const int64_t bx = x >> k.bsx, by = y >> k.bsy, bz = z >> k.bsz;
             key[t] = (((bz >> 3) * k.nby + by) * k.nbx + bx) * 8 + (bz & 7);
         } else {
@@ -448,7 +463,7 @@ int build_schedule(cdi_solver *s, int band_rows, int columns)
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
     std::vector<int> sched(T);
-    if (columns) {
+    if (columns == 1) {
         for (int64_t b = 0; b < T; ++b) sched[xcd_position(b, T)] = order[b];
     } else {
         sched = order;
@@ -457,7 +472,7 @@ int build_schedule(cdi_solver *s, int band_rows, int columns)
     HIPCHK(hipStreamSynchronize(s->stream));
     s->g.sched = s->node.sched;
     s->tuning.band_rows = columns ? 0 : band_rows;
-    s->tuning.columns = columns ? 1 : 0;
+    s->tuning.columns = columns;
     return CDI_OK;
 }
 
@@ -1379,7 +1394,7 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
 
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t)
 {
-    if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0 || t->columns < 0 || t->columns > 1 ||
+    if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0 || t->columns < 0 || t->columns > 2 ||
         t->nbr_list < 0 || t->nbr_list > 1)
         return fail(CDI_E_INVALID, "bad tuning");
     int pad = 0;
@@ -1419,7 +1434,10 @@ int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *c
         for (int k : occ) {
             for (int r : bands)
                 if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r, 0, nl});
-            if (s->dim == 3) cands.push_back(cdi_tuning{k, 0, 1, nl});
+            if (s->dim == 3) {
+                cands.push_back(cdi_tuning{k, 0, 1, nl});
+                cands.push_back(cdi_tuning{k, 0, 2, nl});
+            }
         }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));

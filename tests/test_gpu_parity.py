@@ -315,7 +315,7 @@ def test_snapshot_restore_continues_bitwise(precision, streaming):
 def test_results_do_not_depend_on_tuning_and_autotune_restores_state():
     outs = []
     for occ, band, cols, nl in ((0, 0, 0, 0), (3, 8, 0, 0), (6, 32, 0, 1), (0, 0, 1, 0), (4, 0, 1, 1),
-                                (0, 0, 0, 1)):
+                                (0, 0, 0, 1), (0, 0, 2, 1), (3, 0, 2, 0)):
         g, p = small3d(seed=13)
         s = Solver(g, p)
         s.set_tuning(occ, band, cols, nl)
