@@ -475,6 +475,14 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes);
 
 const char *cdi_last_error(void);
 
+/* sizeof of the public struct called name ("cdi_geometry", "cdi_params",
+ * "cdi_plan_info", "cdi_solver_info", "cdi_tuning", "cdi_potential",
+ * "cdi_potential_result", "cdi_diag") as this library was compiled, so that a
+ * binding can check its own layout before the first call. Host only (no
+ * device call). Returns OK, or INVALID for an unknown name or a null
+ * argument. */
+int cdi_struct_size(const char *name, uint64_t *bytes);
+
 #ifdef __cplusplus
 }
 #endif

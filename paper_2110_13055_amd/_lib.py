@@ -137,7 +137,13 @@ SIGNATURES = {
     "cdi_snapshot": (C.c_int, [P, P, U64]),
     "cdi_restore": (C.c_int, [P, P, U64]),
     "cdi_last_error": (C.c_char_p, []),
+    "cdi_struct_size": (C.c_int, [C.c_char_p, P]),
 }
+
+# the public structs and their ctypes mirrors (layouts checked at load)
+STRUCTS = {"cdi_geometry": CGeometry, "cdi_params": CParams, "cdi_plan_info": CPlanInfo,
+           "cdi_solver_info": CSolverInfo, "cdi_tuning": CTuning, "cdi_potential": CPotential,
+           "cdi_potential_result": CPotentialResult, "cdi_diag": CDiag}
 
 _lib = None
 
@@ -160,6 +166,11 @@ def load():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
+        for cname, cls in STRUCTS.items():  # a stale build with another layout fails here, not in a kernel
+            n = C.c_uint64()
+            if lib.cdi_struct_size(cname.encode(), C.byref(n)) != OK or n.value != C.sizeof(cls):
+                raise RuntimeError(f"{LIB_PATH}: {cname} is {n.value} bytes in the library, {C.sizeof(cls)} in "
+                                   "the binding: rebuild with `python -m paper_2110_13055_amd.build`")
         _lib = lib
     return _lib
 

@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstring>
 #include <new>
 #include <algorithm>
 #include <vector>
@@ -534,6 +535,24 @@ int planes_h2d(cdi_solver *s, float *dev, const float *host, int d)
 extern "C" {
 
 const char *cdi_last_error(void) { return g_err; }
+
+int cdi_struct_size(const char *name, uint64_t *bytes)
+{
+    if (!name || !bytes) return fail(CDI_E_INVALID, "null argument");
+    static const struct {
+        const char *name;
+        uint64_t size;
+    } table[] = {{"cdi_geometry", sizeof(cdi_geometry)},     {"cdi_params", sizeof(cdi_params)},
+                 {"cdi_plan_info", sizeof(cdi_plan_info)},   {"cdi_solver_info", sizeof(cdi_solver_info)},
+                 {"cdi_tuning", sizeof(cdi_tuning)},         {"cdi_potential", sizeof(cdi_potential)},
+                 {"cdi_potential_result", sizeof(cdi_potential_result)}, {"cdi_diag", sizeof(cdi_diag)}};
+    for (const auto &e : table)
+        if (std::strcmp(e.name, name) == 0) {
+            *bytes = e.size;
+            return CDI_OK;
+        }
+    return fail(CDI_E_INVALID, "unknown struct %s", name);
+}
 
 int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *out)
 {

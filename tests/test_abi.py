@@ -83,3 +83,18 @@ def test_last_error_is_a_string():
     from paper_2110_13055_amd import _lib as L
     lib = L.load()
     assert isinstance(lib.cdi_last_error(), bytes)
+
+
+def test_struct_layouts_match_the_binding():
+    """Every public struct has the size the ctypes mirror gives it (the
+    loader checks this too); an unknown name is rejected."""
+    import ctypes as C
+    from paper_2110_13055_amd import _lib as L
+    lib = L.load()
+    for name, cls in L.STRUCTS.items():
+        n = C.c_uint64()
+        assert lib.cdi_struct_size(name.encode(), C.byref(n)) == L.OK
+        assert n.value == C.sizeof(cls), name
+    n = C.c_uint64()
+    assert lib.cdi_struct_size(b"cdi_nothing", C.byref(n)) == L.E_INVALID
+    assert lib.cdi_struct_size(None, C.byref(n)) == L.E_INVALID
