@@ -124,7 +124,17 @@ def potential_rates(coupled_steps: int = 10):
     it = res["it"]
     out["laplace"] = {"iterations": it, "residual": res["r"], "solve_ms": round(sec * 1e3, 2),
                       "ms_per_iter": round(sec * 1e3 / max(it, 1), 4),
-                      "gbs": round(per_iter * nf * it / sec / 1e9, 1)}
+                      "gbs": round(per_iter * nf * it / sec / 1e9, 1),
+                      "fp32_rounds": s.potential_stats["fp32_rounds"],
+                      "fp64_iterations": s.potential_stats["fp64_iterations"]}
+    # the same solve by CG on FP64 vectors alone, for comparison
+    pot64 = P.Potential(psi_electrode=-20.0, x_bc=(P.PSIX_DIRICHLET, P.PSIX_NEUMANN), tol=1e-8,
+                        warm_start=False, check_every=16, fp64=True)
+
+    def run64():
+        res["it"], res["r"] = s.solve_potential(pot64)
+    sec = time_region(run64, s.stream)
+    out["laplace_fp64"] = {"iterations": res["it"], "residual": res["r"], "solve_ms": round(sec * 1e3, 2)}
     # -4 thermal voltages (about -100 mV) keeps the explicit ion update within
     # its positivity bound on this lattice; -20 would not
     cp = P.Potential(psi_electrode=-4.0, x_bc=(P.PSIX_DIRICHLET, P.PSIX_NEUMANN), kappa2=0.5, tol=1e-6,

@@ -365,6 +365,8 @@ typedef struct {
 typedef struct {
     int32_t iterations;    /* CG iterations taken (over all refinement rounds) */
     double residual;       /* final |b - A psi|_2 / |b|_2 */
+    int32_t fp32_rounds;   /* refinement rounds with an FP32 correction solve */
+    int32_t fp64_iterations; /* of the iterations, those on FP64 vectors */
 } cdi_potential_result;
 
 /* Device workspace of the solve (5 FP64 and 5 FP32 vectors and a byte per node, plus

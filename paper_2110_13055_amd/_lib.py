@@ -80,7 +80,8 @@ class CPotential(C.Structure):
 
 
 class CPotentialResult(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("residual", C.c_double)]
+    _fields_ = [("iterations", C.c_int32), ("residual", C.c_double), ("fp32_rounds", C.c_int32),
+                ("fp64_iterations", C.c_int32)]
 
 
 class CDiag(C.Structure):

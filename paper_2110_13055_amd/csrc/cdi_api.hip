@@ -1084,7 +1084,7 @@ int solve_potential(cdi_solver *s, const cdi_potential *pc, void *ws, uint64_t w
     if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
     if (st[kStNdir] == 0)
         return fail(CDI_E_INVALID, "no Dirichlet face (electrode or x end): the potential is not determined");
-    int iters = 0;
+    int iters = 0, iters64 = 0, rounds = 0;
     if (st[kStBb] == 0) {  // b = 0: the solution is zero
         HIPCHK(launch_fill_f32(s->node.psi, 0.f, s->P, s->stream));
         st[kStDone] = kDoneConverged;
@@ -1110,6 +1110,7 @@ int solve_potential(cdi_solver *s, const cdi_potential *pc, void *ws, uint64_t w
                 if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
             }
             prev = st[kStRr];
+            if (!f64) ++rounds;
             int kin = 0;
             while (st[kStDone] == 0 && iters < pc->max_iter) {
                 const int n = std::min(chunk, pc->max_iter - iters);
@@ -1118,6 +1119,7 @@ int solve_potential(cdi_solver *s, const cdi_potential *pc, void *ws, uint64_t w
                 if ((rc = d2h(s, st, W.state, sizeof st)) != CDI_OK) return rc;
                 const int kend = st[kStDone] != 0 ? (int)st[kStIters] : kin + n;
                 iters += kend - kin;
+                if (f64) iters64 += kend - kin;
                 kin = kend;
             }
             const bool bad = st[kStDone] == kDoneDiverged || st[kStDone] == kDoneBreakdown;
@@ -1136,6 +1138,8 @@ int solve_potential(cdi_solver *s, const cdi_potential *pc, void *ws, uint64_t w
     s->p.psi = s->node.psi;
     if (out) {
         out->iterations = iters;
+        out->fp32_rounds = rounds;
+        out->fp64_iterations = iters64;
         out->residual = st[kStBb] > 0 ? std::sqrt(st[kStRr] / st[kStBb]) : 0.0;
     }
     if (st[kStDone] == 0)

@@ -259,11 +259,14 @@ class Solver:
 
     def solve_potential(self, pot: "Potential", allow_not_converged: bool = False):
         """Solve Eq. (4)-(5) for the current concentrations; the result is the
-        potential of later ion steps. Returns (iterations, relative residual)."""
+        potential of later ion steps. Returns (iterations, relative residual);
+        potential_stats holds those and the refinement counts."""
         ws = self._pot_ws()
         c, out = pot.to_c(), L.CPotentialResult()
         rc = self.lib.cdi_solve_potential(self.h, C.byref(c), C.c_void_p(ws.data_ptr()), ws.numel(),
                                           C.byref(out))
+        self.potential_stats = dict(iterations=out.iterations, residual=out.residual,
+                                    fp32_rounds=out.fp32_rounds, fp64_iterations=out.fp64_iterations)
         L.check(rc, "cdi_solve_potential", (L.OK, L.E_NOT_CONVERGED) if allow_not_converged else (L.OK,))
         return out.iterations, out.residual
 

@@ -55,6 +55,32 @@ def test_laplace_3d_matches_oracle(x_bc, fp64):
     pot = Potential(psi_electrode=-1.5, x_bc=x_bc, psi_x=(0.0, 2.0), tol=TOL_GPU, fp64=fp64)
     s, o, it = both(g, p, pot)
     assert s.n_fluid % 256 != 0 and s.n_fluid > 8 * 256  # several tiles and a ragged tail
+    st = s.potential_stats
+    if fp64:
+        assert st["fp32_rounds"] == 0 and st["fp64_iterations"] == it
+    else:
+        assert st["fp32_rounds"] >= 2  # tol 1e-12 is beyond one FP32 correction solve
+    ref = o.potential()
+    assert np.abs(s.potential() - ref).max() <= bar(ref)
+
+
+def test_refinement_hands_over_to_fp64_cg_at_the_rounding_floor():
+    """Asked for a residual below what FP64 arithmetic can certify, the FP32
+    rounds stop gaining once the FP64 residual is rounding noise and CG on the
+    FP64 vectors continues from the refined iterate; whichever way that ends
+    (its recursive residual may pass the threshold, or the cap is reached),
+    the field is the oracle's."""
+    g, p = spheres()
+    pot = Potential(psi_electrode=-1.5, x_bc=(L.PSIX_DIRICHLET, L.PSIX_NEUMANN), psi_x=(0.0, 2.0), tol=1e-19,
+                    max_iter=1500)
+    s = Solver(g, p)
+    it, res = s.solve_potential(pot, allow_not_converged=True)
+    st = s.potential_stats
+    assert st["fp32_rounds"] >= 3 and 0 < st["fp64_iterations"] < it <= pot.max_iter
+    assert res < 1e-12
+    o = oracle_solver(g, p)
+    rc, _, _ = o.solve_potential(pot.psi_electrode, pot.x_bc, pot.psi_x, pot.kappa2, TOL_ORACLE)
+    assert rc == 0
     ref = o.potential()
     assert np.abs(s.potential() - ref).max() <= bar(ref)
 
