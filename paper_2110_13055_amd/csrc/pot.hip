@@ -169,6 +169,19 @@ __device__ inline double new_dir(double r, int d, double p, double beta)
     return z + beta * p;
 }
 
+// The FP32 correction solves precondition with the hardware FP32 reciprocal
+// of the diagonal (one instruction instead of an FP64 division; the
+// preconditioner is diag(inv_diag_f(d))^-1, the same in every kernel that
+// applies it, so CG stays consistent) and form the direction in FP32, the
+// precision it is stored in: every copy of a node's direction, its own and
+// its neighbours', is the same FP32 number, the one stored.
+__device__ inline float inv_diag_f(int d) { return d > 0 ? __builtin_amdgcn_rcpf((float)d) : 0.f; }
+
+__device__ inline float new_dir_f(float r, int d, float p, float beta)
+{
+    return __builtin_fmaf(beta, p, __fmul_rn(r, inv_diag_f(d)));
+}
+
 // Stop test on |r_k|^2 (the r.r partials of the last axpy); the same
 // decision in every workgroup. Workgroup 0 records it.
 __device__ inline bool stop_test(const PotArgs &a, int k, double *sm)
@@ -247,13 +260,25 @@ __global__ __launch_bounds__(kTile) void pot_dirspmv_kernel(PotArgs a, int k)
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
             if (!act[j]) continue;
-            const double pn = new_dir((double)r0[j], d0[j], (double)p0[j], beta);
-            double q = d0[j] * pn;
+            T pt;
+            double q;
+            if constexpr (sizeof(T) == 4) {
+                const float bf = (float)beta;
+                pt = new_dir_f(r0[j], d0[j], p0[j], bf);
+                q = (double)d0[j] * (double)pt;  // A p accumulated in FP64 (it cancels)
 #pragma unroll
-            for (int f = 0; f < F; ++f)
-                if (m[j][f] >= 0) q -= new_dir((double)rm[j][f], dm[j][f], (double)pm[j][f], beta);
+                for (int f = 0; f < F; ++f)
+                    if (m[j][f] >= 0) q -= (double)new_dir_f(rm[j][f], dm[j][f], pm[j][f], bf);
+            } else {
+                const double pn = new_dir(r0[j], d0[j], p0[j], beta);
+                q = d0[j] * pn;
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+                    if (m[j][f] >= 0) q -= new_dir(rm[j][f], dm[j][f], pm[j][f], beta);
+                pt = pn;
+            }
             // stored in T; the partial is formed from the stored values
-            const T pt = (T)pn, qt = (T)q;
+            const T qt = (T)q;
             stu(pnew, (uint32_t)n[j], pt);
             stu(V::q(a), (uint32_t)n[j], qt);
             pq += (double)pt * (double)qt;
@@ -295,7 +320,11 @@ __global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
         stu(rv, (uint32_t)n, rt);
         const double rn = rt;
         const int d = a.dg[n];
-        const double zn = d > 0 ? rn / d : 0.0;
+        double zn;
+        if constexpr (sizeof(T) == 4)
+            zn = __fmul_rn((float)rt, inv_diag_f(d));  // the z the stencil kernel forms
+        else
+            zn = d > 0 ? rn / d : 0.0;
         rz1 += rn * zn;
         rr += rn * rn;
     }
@@ -341,7 +370,7 @@ __global__ __launch_bounds__(kTile) void pot_state_kernel(PotArgs a, int G, doub
 
 // Refinement round: the FP64 residual r = b - A x of the current x, its
 // partial |r|^2 (kRo), and the start of an FP32 correction solve A d = r:
-// rf = r, xf = 0, p = z = rf / diag, partial rf . z (kRz0). F64: instead the
+// rf = r, xf = 0, p = z = rf inv_diag_f(diag), partial rf . z (kRz0). F64: instead the
 // start of FP64 CG iterations on x itself (r, p = z in FP64).
 template <class L, int F64>
 __global__ __launch_bounds__(kTile) void pot_refine_kernel(PotArgs a)
@@ -380,9 +409,8 @@ __global__ __launch_bounds__(kTile) void pot_refine_kernel(PotArgs a)
                 rz += r * zd;
             } else {
                 rf = (float)r;
-                const double zd = diag > 0 ? (double)rf / diag : 0.0;  // the z the stencil kernel forms
-                zf = (float)zd;
-                rz += (double)rf * zd;
+                zf = __fmul_rn(rf, inv_diag_f(diag));  // the z the stencil kernel forms
+                rz += (double)rf * (double)zf;
             }
         } else if (F64) {
             stu(a.r, (uint32_t)n, 0.0);

@@ -237,6 +237,9 @@ def main():
 # bytes per fluid node (the bench's byte model)
 POT_KERNELS = {"pot_dirspmv_kernel": ("direction + A p (stencil), FP32 vectors", 41),
                "pot_axpy_kernel": ("x, r update, FP32 vectors", 25)}
+# the same CG on FP64 vectors (cdi_potential.fp64 = 1, or a round handed over)
+POT64_KERNELS = {"pot_dirspmv_kernel<double>": ("direction + A p (stencil), FP64 vectors", 57),
+                 "pot_axpy_kernel<double>": ("x, r update, FP64 vectors", 49)}
 # once per refinement round of the potential solve (not per iteration)
 POT_ROUND_KERNELS = {"pot_refine_kernel": ("FP64 residual b - A x, FP32 correction start", 52),
                      "pot_correct_kernel": ("x += FP32 correction", 20)}
@@ -251,6 +254,9 @@ def _solver_kernel(name: str):
     m = re.search(r"nps_apply_kernel<[^,>]+, (\d)>", name)
     if m:
         return f"nps_apply_kernel<{m.group(1)}>"
+    m = re.search(r"(pot_dirspmv_kernel|pot_axpy_kernel)<(?:[^<>]*, )?double>", name)
+    if m:
+        return f"{m.group(1)}<double>"
     for k in list(POT_KERNELS) + list(POT_ROUND_KERNELS) + list(NPS_KERNELS):
         if "<" not in k and k in name:
             return k
@@ -323,6 +329,7 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
           "per fluid node; measured: the HBM counters.", ""]
     for key, title, kernels in (("cg", "Potential, Eq. 4-5: Jacobi-PCG iterations of the mixed-precision refinement",
                                  POT_KERNELS),
+                                ("cg64", "Potential: the same CG on FP64 vectors alone (fp64 = 1)", POT64_KERNELS),
                                 ("bicgstab", "Steady ion state (implicit scheme): BiCGSTAB, both species, FP64",
                                  NPS_KERNELS)):
         rows = group(kernels)
