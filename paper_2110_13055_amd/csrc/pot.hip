@@ -1,7 +1,10 @@
 // pot.hip -- the electric potential of Poisson's equation, Eq. (4), with the
 // charge density of Eq. (5) and the electrode's Dirichlet value (Sec. 2),
 // solved on the compacted fluid lattice by Jacobi-preconditioned conjugate
-// gradients.
+// gradients inside mixed-precision iterative refinement: the iterate x and
+// each round's residual b - A x are FP64, each round's correction solve runs
+// CG on FP32 vectors (dot products and alpha, beta in FP64), and a round that
+// no longer gains hands over to CG on the FP64 vectors.
 //
 // Discretisation (finite volumes, one unknown per fluid cell centre, psi in
 // thermal voltages): a face between two fluid cells carries psi_N - psi_P; a
@@ -12,7 +15,7 @@
 // kappa2 / (2 c0). As A psi = b: A_PP = number of fluid faces + 2 per
 // Dirichlet face, A_PN = -1 per fluid face, b_P = src sum z C + 2 sum psi_face.
 //
-// The CG vectors are FP64 in internal node order (stride P). Every kernel
+// The CG vectors are in internal node order (stride P). Every kernel
 // runs G persistent workgroups; workgroup c (its XCD-contiguous position)
 // owns the contiguous tile range [c T / G, (c + 1) T / G), so an XCD sweeps
 // one contiguous eighth of the lattice and finds the tiles above and below
@@ -89,6 +92,9 @@ __device__ inline void node_faces(const PotArgs &a, int n, int (&m)[2 * L::D], i
     }
 }
 
+// Set-up of a solve: x = the start field (or 0), the diagonal byte per
+// node, and the partials |b|^2 and the count of Dirichlet faces. The start's
+// residual is formed by the first refinement round.
 template <class L>
 __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
 {
@@ -96,10 +102,10 @@ __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
     int t0, t1;
     tile_range(a.g.P / kTile, t0, t1);
     const int P = a.g.P;
-    double rz = 0, rr = 0, bb = 0, nd = 0;
+    double bb = 0, nd = 0;
     for (int t = t0; t < t1; ++t) {
         const int n = t * kTile + threadIdx.x;
-        double xv = 0, rv = 0, zv = 0;
+        double xv = 0;
         int diag = 0;
         if (n < a.g.n_f) {
             int m[2 * L::D];
@@ -107,12 +113,9 @@ __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
             double b = a.src * ((double)a.z[0] * ldu(a.C, (uint32_t)n) +
                                 (double)a.z[1] * ldu(a.C, (uint32_t)(P + n)));
             xv = a.psi0 ? (double)ldu(a.psi0, (uint32_t)n) : 0.0;
-            double ax = diag * xv;
 #pragma unroll
             for (int k = 0; k < 2 * L::D; ++k) {
-                if (m[k] >= 0) {
-                    if (a.psi0) ax -= (double)ldu(a.psi0, (uint32_t)m[k]);
-                } else if (m[k] == kElectrode) {
+                if (m[k] == kElectrode) {
                     b += 2.0 * a.psi_e;
                     nd += 1;
                 } else if (m[k] == kOutside && a.xbc[k & 1 ? 0 : 1] == kPsixDirichlet) {
@@ -120,23 +123,14 @@ __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
                     nd += 1;
                 }
             }
-            rv = b - ax;
-            zv = diag > 0 ? rv / diag : 0.0;
-            rz += rv * zv;
-            rr += rv * rv;
             bb += b * b;
         }
         stu(a.x, (uint32_t)n, xv);
-        stu(a.r, (uint32_t)n, rv);
-        stu(a.p, (uint32_t)n, zv);
         a.dg[n] = (uint8_t)diag;
     }
-    const double s_rz = wg_sum(rz, sm), s_rr = wg_sum(rr, sm), s_bb = wg_sum(bb, sm);
-    const double s_nd = wg_sum(nd, sm);
+    const double s_bb = wg_sum(bb, sm), s_nd = wg_sum(nd, sm);
     if (threadIdx.x == 0) {
         const int G = gridDim.x;
-        a.part[kRz0 * G + blockIdx.x] = s_rz;
-        a.part[kRr * G + blockIdx.x] = s_rr;
         a.part[kBb * G + blockIdx.x] = s_bb;
         a.part[kNd * G + blockIdx.x] = s_nd;
     }
@@ -351,20 +345,19 @@ __global__ __launch_bounds__(kTile) void pot_check_kernel(PotArgs a, int k, int 
     }
 }
 
-// Totals of the start (one workgroup): |b|^2, |r0|^2, Dirichlet faces.
+// Totals of the set-up (one workgroup): |b|^2 and the Dirichlet faces.
 __global__ __launch_bounds__(kTile) void pot_state_kernel(PotArgs a, int G, double tol)
 {
     __shared__ double sm[kTile / 64];
     const double bb = region_sum(a.part + kBb * G, G, sm);
-    const double rr = region_sum(a.part + kRr * G, G, sm);
     const double nd = region_sum(a.part + kNd * G, G, sm);
     if (threadIdx.x == 0) {
         a.state[kStBb] = bb;
         a.state[kStTol2Bb] = tol * tol * bb;
-        a.state[kStRr] = rr;
+        a.state[kStRr] = 0.0;  // the first refinement round measures it
         a.state[kStNdir] = nd;
         a.state[kStIters] = 0;
-        a.state[kStDone] = rr <= tol * tol * bb ? kDoneConverged : 0.0;
+        a.state[kStDone] = 0.0;
     }
 }
 

@@ -48,8 +48,8 @@ struct PotArgs {
 hipError_t pot_workgroups(int dim, int ntiles, bool nbr, int *G);
 // Doubles of the partial-sum area (sized for kPotMaxWorkgroups).
 uint64_t pot_part_doubles();
-// r = b - A x0, z, p = z, the diagonal, and the state (stop code set when the
-// start already meets tol).
+// x = x0, the diagonal, |b|^2 and the Dirichlet face count into the state;
+// the residual of x0 and the stop test come with the first refinement round.
 hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStream_t s);
 // CG iteration k (stop test, direction and A p; then the x and r updates) on
 // the FP64 vectors or (f32) on the FP32 set; returns at once after a stop.
