@@ -44,6 +44,9 @@ namespace {
 // kRo: |r|^2 of the FP64 residual of a refinement round.
 enum { kRz0 = 0, kRz1 = 1, kRr = 2, kPq = 3, kBb = 4, kNd = 5, kRo = 6, kRegions = 7 };
 
+// nodes per thread (tiles per pass) of the stencil and update kernels
+constexpr int kPotNodes = 2;
+
 // The vectors a CG iteration works on: FP64 (x, r, q, p, p2) or the FP32
 // set of a refinement round's correction (xf, rf, qf, pf, pf2).
 template <class T>
@@ -305,22 +308,39 @@ __global__ __launch_bounds__(kTile) void pot_axpy_kernel(PotArgs a, int k)
     int t0, t1;
     tile_range(a.g.P / kTile, t0, t1);
     double rz1 = 0, rr = 0;
-    for (int t = t0; t < t1; ++t) {
-        const int n = t * kTile + threadIdx.x;
-        if (n >= a.g.n_f) continue;
-        const double pn = ldu(pk, (uint32_t)n), qn = ldu(qv, (uint32_t)n);
-        stu(xv, (uint32_t)n, (T)(ldu(xv, (uint32_t)n) + alpha * pn));
-        const T rt = (T)(ldu(rv, (uint32_t)n) - alpha * qn);
-        stu(rv, (uint32_t)n, rt);
-        const double rn = rt;
-        const int d = a.dg[n];
-        double zn;
-        if constexpr (sizeof(T) == 4)
-            zn = __fmul_rn((float)rt, inv_diag_f(d));  // the z the stencil kernel forms
-        else
-            zn = d > 0 ? rn / d : 0.0;
-        rz1 += rn * zn;
-        rr += rn * rn;
+    // kPotNodes tiles per pass, all loads issued before any store (more
+    // loads in flight per wave; index 0 where there is no node, not stored)
+    for (int t = t0; t < t1; t += kPotNodes) {
+        int n[kPotNodes];
+        bool act[kPotNodes];
+        T pv[kPotNodes], qv_[kPotNodes], xo[kPotNodes], ro[kPotNodes];
+        int dv[kPotNodes];
+#pragma unroll
+        for (int j = 0; j < kPotNodes; ++j) {
+            n[j] = (t + j) * kTile + threadIdx.x;
+            act[j] = t + j < t1 && n[j] < a.g.n_f;
+            const uint32_t q = act[j] ? (uint32_t)n[j] : 0u;
+            pv[j] = ldu(pk, q);
+            qv_[j] = ldu(qv, q);
+            xo[j] = ldu(xv, q);
+            ro[j] = ldu(rv, q);
+            dv[j] = a.dg[q];
+        }
+#pragma unroll
+        for (int j = 0; j < kPotNodes; ++j) {
+            if (!act[j]) continue;
+            stu(xv, (uint32_t)n[j], (T)(xo[j] + alpha * (double)pv[j]));
+            const T rt = (T)(ro[j] - alpha * (double)qv_[j]);
+            stu(rv, (uint32_t)n[j], rt);
+            const double rn = rt;
+            double zn;
+            if constexpr (sizeof(T) == 4)
+                zn = __fmul_rn((float)rt, inv_diag_f(dv[j]));  // the z the stencil kernel forms
+            else
+                zn = dv[j] > 0 ? rn / dv[j] : 0.0;
+            rz1 += rn * zn;
+            rr += rn * rn;
+        }
     }
     const double s_rz = wg_sum(rz1, sm), s_rr = wg_sum(rr, sm);
     if (threadIdx.x == 0) {
@@ -460,9 +480,6 @@ __global__ __launch_bounds__(kTile) void pot_store_kernel(const double *x, float
 }
 
 }  // namespace
-
-// nodes per thread of the stencil kernel
-constexpr int kPotNodes = 2;
 
 uint64_t pot_part_doubles() { return (uint64_t)kRegions * kPotMaxWorkgroups; }
 
