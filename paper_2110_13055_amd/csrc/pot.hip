@@ -384,8 +384,9 @@ __global__ __launch_bounds__(kTile) void pot_state_kernel(PotArgs a, int G, doub
 // Refinement round: the FP64 residual r = b - A x of the current x, its
 // partial |r|^2 (kRo), and the start of an FP32 correction solve A d = r:
 // rf = r, xf = 0, p = z = rf inv_diag_f(diag), partial rf . z (kRz0). F64: instead the
-// start of FP64 CG iterations on x itself (r, p = z in FP64).
-template <class L, int F64>
+// start of FP64 CG iterations on x itself (r, p = z in FP64). Faces from the
+// neighbour list where there is one (NBR), the diagonal from the set-up.
+template <class L, int F64, int NBR>
 __global__ __launch_bounds__(kTile) void pot_refine_kernel(PotArgs a)
 {
     __shared__ double sm[kTile / 64];
@@ -397,8 +398,9 @@ __global__ __launch_bounds__(kTile) void pot_refine_kernel(PotArgs a)
         const int n = t * kTile + threadIdx.x;
         float rf = 0.f, zf = 0.f;
         if (n < a.g.n_f) {
-            int m[2 * L::D], diag = 0;
-            node_faces<L>(a, n, m, diag);
+            int m[2 * L::D];
+            face_maps<L, NBR>(a, n, m);
+            const int diag = a.dg[n];
             double b = a.src * ((double)a.z[0] * ldu(a.C, (uint32_t)n) + (double)a.z[1] * ldu(a.C, (uint32_t)(P + n)));
             double ax = diag * ldu(a.x, (uint32_t)n);
             double xm[2 * L::D];  // loaded before use (index 0 where not fluid: unused)
@@ -538,12 +540,21 @@ hipError_t launch_pot_iter(int dim, const PotArgs &a, int G, int k, bool f32, hi
     return hipGetLastError();
 }
 
+template <class L>
+void refine_l(const PotArgs &a, int G, bool f64, hipStream_t s)
+{
+    if (a.nbr)
+        f64 ? pot_refine_kernel<L, 1, 1><<<G, kTile, 0, s>>>(a) : pot_refine_kernel<L, 0, 1><<<G, kTile, 0, s>>>(a);
+    else
+        f64 ? pot_refine_kernel<L, 1, 0><<<G, kTile, 0, s>>>(a) : pot_refine_kernel<L, 0, 0><<<G, kTile, 0, s>>>(a);
+}
+
 hipError_t launch_pot_refine(int dim, const PotArgs &a, int G, double tol, double tol_min, bool f64, hipStream_t s)
 {
     if (dim == 2)
-        f64 ? pot_refine_kernel<D2Q9, 1><<<G, kTile, 0, s>>>(a) : pot_refine_kernel<D2Q9, 0><<<G, kTile, 0, s>>>(a);
+        refine_l<D2Q9>(a, G, f64, s);
     else
-        f64 ? pot_refine_kernel<D3Q19, 1><<<G, kTile, 0, s>>>(a) : pot_refine_kernel<D3Q19, 0><<<G, kTile, 0, s>>>(a);
+        refine_l<D3Q19>(a, G, f64, s);
     pot_refine_state_kernel<<<1, kTile, 0, s>>>(a, G, tol, tol_min);
     return hipGetLastError();
 }

@@ -241,7 +241,7 @@ POT_KERNELS = {"pot_dirspmv_kernel": ("direction + A p (stencil), FP32 vectors",
 POT64_KERNELS = {"pot_dirspmv_kernel<double>": ("direction + A p (stencil), FP64 vectors", 57),
                  "pot_axpy_kernel<double>": ("x, r update, FP64 vectors", 49)}
 # once per refinement round of the potential solve (not per iteration)
-POT_ROUND_KERNELS = {"pot_refine_kernel": ("FP64 residual b - A x, FP32 correction start", 52),
+POT_ROUND_KERNELS = {"pot_refine_kernel": ("FP64 residual b - A x, FP32 correction start", 53),
                      "pot_correct_kernel": ("x += FP32 correction", 20)}
 NPS_KERNELS = {"nps_dir_kernel": ("direction p^ = K^-1 p", 72),
                "nps_apply_kernel<0>": ("v = A p^", 78),
