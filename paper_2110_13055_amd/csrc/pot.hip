@@ -73,32 +73,29 @@ struct Vecs<float> {
 // running kernel; every workgroup then skips the same update either way).
 __device__ inline bool stopped(const double *state, int *flag) { return stopped_at(state, kStDone, flag); }
 
-// Map values of the 2D face neighbours of node n, and its diagonal.
-template <class L>
-__device__ inline void node_faces(const PotArgs &a, int n, int (&m)[2 * L::D], int &diag)
+// Face neighbours (map values) of node n: from the neighbour list, or
+// looked up through the voxel map after the node's coordinates.
+template <class L, int NBR>
+__device__ inline void face_maps(const PotArgs &a, int n, int (&m)[2 * L::D])
 {
+    if (NBR) {
+#pragma unroll
+        for (int k = 0; k < 2 * L::D; ++k) m[k] = ldu(a.nbr, (uint32_t)(k * a.g.P + n));
+        return;
+    }
     int x, y, z;
     unpack_xyz(a.g, ldu(a.g.fluid, (uint32_t)n), x, y, z);
     NbCtx c;
     nb_ctx<L>(a.g, x, y, z, a.xbc[0] == kPsixPeriodic, c);
-    diag = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * L::D; ++k) {
-        // directions 1 .. 2D are the faces +x, -x, +y, -y (, +z, -z)
-        m[k] = nb_get<L>(a.g, c, k + 1);
-        if (m[k] >= 0)
-            diag += 1;
-        else if (m[k] == kElectrode)
-            diag += 2;
-        else if (m[k] == kOutside && a.xbc[k & 1 ? 0 : 1] == kPsixDirichlet)
-            diag += 2;
-    }
+    for (int k = 0; k < 2 * L::D; ++k) m[k] = nb_get<L>(a.g, c, k + 1);
 }
 
 // Set-up of a solve: x = the start field (or 0), the diagonal byte per
 // node, and the partials |b|^2 and the count of Dirichlet faces. The start's
-// residual is formed by the first refinement round.
-template <class L>
+// residual is formed by the first refinement round. Faces from the
+// neighbour list where there is one (NBR).
+template <class L, int NBR>
 __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
 {
     __shared__ double sm[kTile / 64];
@@ -112,7 +109,12 @@ __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
         int diag = 0;
         if (n < a.g.n_f) {
             int m[2 * L::D];
-            node_faces<L>(a, n, m, diag);
+            face_maps<L, NBR>(a, n, m);
+#pragma unroll
+            for (int k = 0; k < 2 * L::D; ++k)
+                diag += m[k] >= 0 ? 1
+                                  : (m[k] == kElectrode ||
+                                     (m[k] == kOutside && a.xbc[k & 1 ? 0 : 1] == kPsixDirichlet)) ? 2 : 0;
             double b = a.src * ((double)a.z[0] * ldu(a.C, (uint32_t)n) +
                                 (double)a.z[1] * ldu(a.C, (uint32_t)(P + n)));
             xv = a.psi0 ? (double)ldu(a.psi0, (uint32_t)n) : 0.0;
@@ -137,24 +139,6 @@ __global__ __launch_bounds__(kTile) void pot_setup_kernel(PotArgs a)
         a.part[kBb * G + blockIdx.x] = s_bb;
         a.part[kNd * G + blockIdx.x] = s_nd;
     }
-}
-
-// Face neighbours (map values) of node n: from the neighbour list, or
-// looked up through the voxel map after the node's coordinates.
-template <class L, int NBR>
-__device__ inline void face_maps(const PotArgs &a, int n, int (&m)[2 * L::D])
-{
-    if (NBR) {
-#pragma unroll
-        for (int k = 0; k < 2 * L::D; ++k) m[k] = ldu(a.nbr, (uint32_t)(k * a.g.P + n));
-        return;
-    }
-    int x, y, z;
-    unpack_xyz(a.g, ldu(a.g.fluid, (uint32_t)n), x, y, z);
-    NbCtx c;
-    nb_ctx<L>(a.g, x, y, z, a.xbc[0] == kPsixPeriodic, c);
-#pragma unroll
-    for (int k = 0; k < 2 * L::D; ++k) m[k] = nb_get<L>(a.g, c, k + 1);
 }
 
 // The new search direction at one node: z + beta p with z = r / diag. Node n
@@ -514,9 +498,9 @@ hipError_t pot_workgroups(int dim, int ntiles, bool nbr, int *G)
 hipError_t launch_pot_setup(int dim, const PotArgs &a, int G, double tol, hipStream_t s)
 {
     if (dim == 2)
-        pot_setup_kernel<D2Q9><<<G, kTile, 0, s>>>(a);
+        a.nbr ? pot_setup_kernel<D2Q9, 1><<<G, kTile, 0, s>>>(a) : pot_setup_kernel<D2Q9, 0><<<G, kTile, 0, s>>>(a);
     else
-        pot_setup_kernel<D3Q19><<<G, kTile, 0, s>>>(a);
+        a.nbr ? pot_setup_kernel<D3Q19, 1><<<G, kTile, 0, s>>>(a) : pot_setup_kernel<D3Q19, 0><<<G, kTile, 0, s>>>(a);
     pot_state_kernel<<<1, kTile, 0, s>>>(a, G, tol);
     return hipGetLastError();
 }
