@@ -13,7 +13,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of the same source (the sanitizer build)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 DRIVE_INLET_OUTLET, DRIVE_BODY_FORCE = 0, 1
 EQ_QUADRATIC, EQ_LINEAR = 0, 1
