@@ -92,6 +92,30 @@ def gpu_rates(precision: int, steps: int, warmup: int, streaming: int):
     return res
 
 
+def hbm_probe(mib: int = 2048, reps: int = 5):
+    """Attainable HBM bandwidth: the library's streaming kernels (128-bit
+    accesses, a flat grid) over two buffers of `mib` MiB each: a copy (reads
+    and writes mib MiB), a read-only checksum pass and a fill. GB/s of
+    bytes moved, best of `reps` launches timed with HIP events on the stream
+    they run on."""
+    import torch
+    import paper_2110_13055_amd as P
+    n = mib << 18
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    chk = torch.empty(n // 512 + 4, dtype=torch.int32, device="cuda")  # 16 B per 8 KiB block
+    st = torch.cuda.current_stream()
+    out = {"buffer_mib": mib}
+    for name, mode, d, sr, moved in (("copy", P.PROBE_COPY, dst, src, 2), ("read", P.PROBE_READ, chk, src, 1),
+                                     ("fill", P.PROBE_FILL, dst, None, 1)):
+        P.bandwidth_probe(mode, d, sr, stream=st)
+        best = min(time_region(lambda: P.bandwidth_probe(mode, d, sr, stream=st), st) for _ in range(reps))
+        out[f"{name}_gbs"] = round(moved * n * 4 / best / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def potential_rates(coupled_steps: int = 10):
     """The potential (Poisson, Eq. 4-5) on the bench electrode. Static solve:
     Laplace with the electrode at -20 thermal voltages, the inlet face at 0
@@ -274,13 +298,14 @@ def main():
     ap.add_argument("--streaming", choices=("pull", "aa"), default="pull",
                     help="population streaming of the FP32 / FP16 forms")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--no-probe", action="store_true", help="skip the streaming bandwidth probe")
     ap.add_argument("--no-potential", action="store_true", help="skip the potential-solve leg")
     ap.add_argument("--potential-only", action="store_true",
                     help="run only the potential-solve leg and print its record (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the serving trace (0 skips the serving leg)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="first run one device-to-device copy of this size (a kernel of known "
+                    help="first run the probe's copy kernel over this size (a kernel of known "
                          "traffic, to calibrate HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -294,11 +319,12 @@ def main():
     import paper_2110_13055_amd as P
 
     if args.copy_probe_mib > 0:
-        a = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        a = torch.ones(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        P.bandwidth_probe(P.PROBE_COPY, b, a)
         torch.cuda.synchronize()
         del a, b
+        torch.cuda.empty_cache()
     if args.potential_only:
         print(json.dumps({"workload": WORKLOAD, "potential": potential_rates()}), flush=True)
         return
@@ -349,6 +375,8 @@ def main():
         "moments": form("moments", rmo),
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_probe:
+        out["hbm_probe"] = hbm_probe()
     if not args.no_potential:
         out["potential"] = potential_rates()
     if not args.no_batch:

@@ -475,6 +475,23 @@ int cdi_snapshot_bytes(cdi_solver *s, uint64_t *bytes);
 int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes);
 int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes);
 
+/* ------------------------------------------------------------ bandwidth probe
+ * Streaming kernels of exactly known traffic with 128-bit accesses, one or
+ * two 16-byte words per thread over a grid sized to the data. They give the
+ * HBM bandwidth a kernel attains on the device, the yardstick beside the
+ * 8 TB/s peak for the step kernels' bytes per update, and a launch of known
+ * size to calibrate profiler byte counters. Not part of the model.
+ *   CDI_PROBE_COPY  dst[0, bytes) = src[0, bytes): reads and writes bytes
+ *   CDI_PROBE_READ  16-byte word k of dst = XOR of the 16-byte words of
+ *                   src[8192 k, 8192 (k + 1)) (dst holds 16 ceil(bytes / 8192)
+ *                   bytes): reads bytes, writes 1/512 of that
+ *   CDI_PROBE_FILL  dst[0, bytes) = the 32-bit value repeated: writes bytes
+ * dst and src are device pointers, 16-byte aligned; bytes a multiple of 16;
+ * the ranges must not overlap. Asynchronous on stream. INVALID on a bad
+ * argument, DEVICE on a launch error. */
+enum { CDI_PROBE_COPY = 0, CDI_PROBE_READ = 1, CDI_PROBE_FILL = 2 };
+int cdi_bandwidth_probe(int32_t mode, void *dst, const void *src, uint64_t bytes, uint32_t value, void *stream);
+
 const char *cdi_last_error(void);
 
 /* sizeof of the public struct called name ("cdi_geometry", "cdi_params",

@@ -11,7 +11,7 @@ from ._lib import (  # noqa: F401
     BODY_FORCE, DISKS, FIBRES, EQ_LINEAR, EQ_QUADRATIC, FP16_DEV, FP32, INLET_OUTLET, MOMENTS, NPX_CLOSED,
     NPX_DIRICHLET, NPX_INLET_OUTLET, NPX_PERIODIC, SPHERES, USER_LABELS, CdiError,
     MODE_FLOW, MODE_FUSED, MODE_IDLE, MODE_IONS, STREAM_AA, STREAM_PULL, PSIX_DIRICHLET, PSIX_NEUMANN,
-    PSIX_PERIODIC,
+    PSIX_PERIODIC, PROBE_COPY, PROBE_READ, PROBE_FILL,
 )
-from .solver import Batch, Geometry, Params, Potential, Solver, plan  # noqa: F401
+from .solver import Batch, Geometry, Params, Potential, Solver, bandwidth_probe, plan  # noqa: F401
 from .presets import PRESETS, batch_instances, fibre_case, fibre_sweep, preset, serving_requests  # noqa: F401

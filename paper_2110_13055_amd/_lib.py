@@ -21,6 +21,7 @@ FP32, FP16_DEV, MOMENTS = 0, 1, 2
 STREAM_AA, STREAM_PULL = 0, 1
 MODE_IDLE, MODE_FLOW, MODE_IONS, MODE_FUSED = 0, 1, 2, 3
 PSIX_DIRICHLET, PSIX_NEUMANN, PSIX_PERIODIC = 0, 1, 2
+PROBE_COPY, PROBE_READ, PROBE_FILL = 0, 1, 2
 
 STATUS_NAMES = {
     0: "OK", 1: "STAGNATED", -1: "INVALID", -2: "GEOMETRY", -3: "UNSTABLE", -4: "NOT_CONVERGED",
@@ -137,6 +138,7 @@ SIGNATURES = {
     "cdi_snapshot_bytes": (C.c_int, [P, P]),
     "cdi_snapshot": (C.c_int, [P, P, U64]),
     "cdi_restore": (C.c_int, [P, P, U64]),
+    "cdi_bandwidth_probe": (C.c_int, [I32, P, P, U64, C.c_uint32, P]),
     "cdi_last_error": (C.c_char_p, []),
     "cdi_struct_size": (C.c_int, [C.c_char_p, P]),
 }

@@ -536,6 +536,22 @@ extern "C" {
 
 const char *cdi_last_error(void) { return g_err; }
 
+int cdi_bandwidth_probe(int32_t mode, void *dst, const void *src, uint64_t bytes, uint32_t value, void *stream)
+{
+    if (mode != CDI_PROBE_COPY && mode != CDI_PROBE_READ && mode != CDI_PROBE_FILL)
+        return fail(CDI_E_INVALID, "unknown probe mode %d", mode);
+    if (!dst || (mode != CDI_PROBE_FILL && !src)) return fail(CDI_E_INVALID, "null buffer");
+    if (bytes % 16 || ((uintptr_t)dst | (uintptr_t)(src ? src : dst)) % 16)
+        return fail(CDI_E_INVALID, "buffers must be 16-byte aligned and bytes a multiple of 16");
+    const uint64_t out_bytes = mode == CDI_PROBE_READ ? 16 * ((bytes + kStreamReadBlock - 1) / kStreamReadBlock) : bytes;
+    if (mode != CDI_PROBE_FILL && bytes && (const uint8_t *)src < (uint8_t *)dst + out_bytes &&
+        (uint8_t *)dst < (const uint8_t *)src + bytes)
+        return fail(CDI_E_INVALID, "source and destination overlap");
+    const int k = mode == CDI_PROBE_COPY ? kStreamCopy : mode == CDI_PROBE_READ ? kStreamRead : kStreamFill;
+    HIPCHK(launch_stream(k, dst, src, bytes, value, (hipStream_t)stream));
+    return CDI_OK;
+}
+
 int cdi_struct_size(const char *name, uint64_t *bytes)
 {
     if (!name || !bytes) return fail(CDI_E_INVALID, "null argument");

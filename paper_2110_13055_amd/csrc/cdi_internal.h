@@ -182,6 +182,13 @@ int64_t brick_enum_size(const Bricks &bk);
 hipError_t launch_permute(const float *src, float *dst, const int *lex2int, int n_f, int P, int d,
                           int to_lex, hipStream_t s);
 
+// Streaming kernels of known traffic over bytes (a multiple of 16): copy,
+// XOR checksum of every 8 KiB block of src into dst (16 bytes per block),
+// fill with a 32-bit value.
+constexpr int kStreamCopy = 0, kStreamRead = 1, kStreamFill = 2;
+constexpr uint64_t kStreamReadBlock = 8192;
+hipError_t launch_stream(int mode, void *dst, const void *src, uint64_t bytes, uint32_t value, hipStream_t s);
+
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);

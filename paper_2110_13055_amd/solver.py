@@ -101,6 +101,20 @@ def plan(geom: Geometry, params: Optional[Params] = None) -> L.CPlanInfo:
     return info
 
 
+def bandwidth_probe(mode: int, dst, src=None, value: int = 0, stream=None) -> None:
+    """One streaming kernel of known traffic (cdi_bandwidth_probe): PROBE_COPY
+    dst <- src, PROBE_READ 16-byte word k of dst <- XOR of the 16-byte words of
+    src's k-th 8 KiB block, PROBE_FILL dst <- value repeated. dst / src: CUDA tensors (the byte size
+    of src for COPY and READ, of dst for FILL); stream: a torch stream or None
+    (the current one). Asynchronous."""
+    import torch
+    lib = L.load()
+    nbytes = (src if mode != L.PROBE_FILL else dst).numel() * (src if mode != L.PROBE_FILL else dst).element_size()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    L.check(lib.cdi_bandwidth_probe(mode, dst.data_ptr(), None if src is None else src.data_ptr(), nbytes,
+                                    value & 0xFFFFFFFF, st.cuda_stream), "cdi_bandwidth_probe")
+
+
 @dataclass
 class Potential:
     """Settings of the potential solve (Poisson, Eq. 4-5; see cdi_potential in
