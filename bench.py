@@ -36,12 +36,15 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "spheres3d_512"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per fluid-node update (D3Q19): populations read + write,
-# concentrations read + write (2 species), ion-advecting flux read + write
-# (FP32: j, 3 floats; FP16 and moment storage: the moments rho-1, u as one
+# concentrations read + write (2 species, FP32 values and FP16 remainders:
+# 2 x (8 + 4) B), ion-advecting flux read + write (FP32 and FP16 populations:
+# j, 3 floats; FP16 deviations and moment storage: the moments rho-1, u as one
 # float4, which also carry j)
-BYTES_FUSED = {"fp32": 19 * 4 * 2 + 16 + 24, "fp16_dev": 19 * 2 * 2 + 16 + 32, "moments": 16 + 32}
-BYTES_LBM = {"fp32": 19 * 4 * 2, "fp16_dev": 19 * 2 * 2 + 32, "moments": 32}
-BYTES_NP = 16 + 12  # C read + write, frozen j read
+BYTES_C = 2 * (8 + 4)
+BYTES_FUSED = {"fp32": 19 * 4 * 2 + BYTES_C + 24, "fp16": 19 * 2 * 2 + BYTES_C + 24,
+               "fp16_dev": 19 * 2 * 2 + BYTES_C + 32, "moments": BYTES_C + 32}
+BYTES_LBM = {"fp32": 19 * 4 * 2, "fp16": 19 * 2 * 2, "fp16_dev": 19 * 2 * 2 + 32, "moments": 32}
+BYTES_NP = BYTES_C + 12  # C and remainders read + write, frozen j read
 
 
 def measured_traffic(kind: str):
@@ -330,6 +333,7 @@ def main():
         return
     strm = P.STREAM_PULL if args.streaming == "pull" else P.STREAM_AA
     r32 = gpu_rates(P.FP32, args.steps, args.warmup, strm)
+    rh16 = gpu_rates(P.FP16, args.steps, args.warmup, strm)
     r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup, strm)
     rmo = gpu_rates(P.MOMENTS, args.steps, args.warmup, strm)
     nf = r32["n_fluid"]
@@ -371,6 +375,7 @@ def main():
                      "traffic": traffic,
                      "algorithmic_bytes_per_node": BYTES_FUSED["fp32"]},
         "fp32": form("fp32", r32),
+        "fp16": form("fp16", rh16),
         "fp16_dev": form("fp16_dev", r16),
         "moments": form("moments", rmo),
         "device": torch.cuda.get_device_name(0),

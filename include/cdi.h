@@ -55,7 +55,7 @@ enum { CDI_DISKS = 0, CDI_SPHERES = 1, CDI_USER_LABELS = 2, CDI_FIBRES = 3 };
 enum { CDI_INLET_OUTLET = 0, CDI_BODY_FORCE = 1 };
 enum { CDI_EQ_QUADRATIC = 0, CDI_EQ_LINEAR = 1 };
 enum { CDI_NPX_INLET_OUTLET = 0, CDI_NPX_PERIODIC = 1, CDI_NPX_CLOSED = 2, CDI_NPX_DIRICHLET = 3 };
-enum { CDI_FP32 = 0, CDI_FP16_DEV = 1, CDI_MOMENTS = 2 };
+enum { CDI_FP32 = 0, CDI_FP16_DEV = 1, CDI_MOMENTS = 2, CDI_FP16 = 3 };
 enum { CDI_STREAM_AA = 0, CDI_STREAM_PULL = 1 };
 
 /*
@@ -114,7 +114,15 @@ typedef struct {
  *   np_x_bc      treatment of the two x-end faces for Nernst-Planck
  *   np_substeps  Nernst-Planck sub-steps per step (dt = 1/np_substeps);
  *                fused steps need 1
- *   precision    CDI_FP32: populations stored as f - w_i in FP32;
+ *   precision    CDI_FP32: populations stored in FP32 relative to the rest
+ *                equilibrium of a reference density per x plane,
+ *                f - w_i (1 + R[x]), with R[x] the plane mean of rho - 1,
+ *                renewed at every residual check of cdi_flow_step_to_steady
+ *                (zero until then): the stored values carry only the local
+ *                fluctuations, which FP32 rounds finely;
+ *                CDI_FP16: the same values stored in FP16 (times 2^12), all
+ *                arithmetic FP32: half the population bytes, at an accuracy
+ *                set by FP16's 11-bit significand;
  *                CDI_FP16_DEV: post-collision populations stored as FP16
  *                deviations from the local equilibrium, with the
  *                equilibrium's moments kept in FP32; all arithmetic FP32;

@@ -8,7 +8,7 @@ adsorption law as a face flux (Liu, Waugh, Komini Babu, Spendelow, Kang,
 """
 from . import _lib  # noqa: F401
 from ._lib import (  # noqa: F401
-    BODY_FORCE, DISKS, FIBRES, EQ_LINEAR, EQ_QUADRATIC, FP16_DEV, FP32, INLET_OUTLET, MOMENTS, NPX_CLOSED,
+    BODY_FORCE, DISKS, FIBRES, EQ_LINEAR, EQ_QUADRATIC, FP16, FP16_DEV, FP32, INLET_OUTLET, MOMENTS, NPX_CLOSED,
     NPX_DIRICHLET, NPX_INLET_OUTLET, NPX_PERIODIC, SPHERES, USER_LABELS, CdiError,
     MODE_FLOW, MODE_FUSED, MODE_IDLE, MODE_IONS, STREAM_AA, STREAM_PULL, PSIX_DIRICHLET, PSIX_NEUMANN,
     PSIX_PERIODIC, PROBE_COPY, PROBE_READ, PROBE_FILL,

@@ -17,7 +17,7 @@ DISKS, SPHERES, USER_LABELS, FIBRES = 0, 1, 2, 3
 INLET_OUTLET, BODY_FORCE = 0, 1
 EQ_QUADRATIC, EQ_LINEAR = 0, 1
 NPX_INLET_OUTLET, NPX_PERIODIC, NPX_CLOSED, NPX_DIRICHLET = 0, 1, 2, 3
-FP32, FP16_DEV, MOMENTS = 0, 1, 2
+FP32, FP16_DEV, MOMENTS, FP16 = 0, 1, 2, 3
 STREAM_AA, STREAM_PULL = 0, 1
 MODE_IDLE, MODE_FLOW, MODE_IONS, MODE_FUSED = 0, 1, 2, 3
 PSIX_DIRICHLET, PSIX_NEUMANN, PSIX_PERIODIC = 0, 1, 2

@@ -13,7 +13,8 @@ namespace {
 // neighbour. rho, u, j are optional outputs.
 template <class L, int ST, int ODD>
 __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, const void *F,
-                                                      const float4 *M, float *rho, float *u, float *j)
+                                                      const float4 *M, const float *rref, float *rho, float *u,
+                                                      float *j)
 {
     constexpr int Q = L::Q, D = L::D;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -34,13 +35,21 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
     nb[0] = src;
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-        nb[i] = (ODD || ST != kF32) ? nb_map<L>(g, sx, y, z, i, g.periodic_x) : kOutside;
+        nb[i] = (ODD || !kPlain<ST>) ? nb_map<L>(g, sx, y, z, i, g.periodic_x) : kOutside;
     float f[Q];
+    // FP32 storage: relative to the plane reference of the node read (see PlaneRef)
+    const PlaneRef pr = kPlain<ST> ? plane_ref<0>(g, rref, rref, sx) : PlaneRef{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float ref = pr.rout;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = gather<L, ST, ODD>(F, g.P, nb, src, i, M, p);
+    for (int i = 0; i < Q; ++i) {
+        f[i] = gather<L, ST, ODD>(F, g.P, nb, src, i, M, p);
+        if (kPlain<ST>) f[i] = rel_pop<L, ODD>(f[i], i, nb, pr);
+    }
     if (src != n) {
         float fb[Q];
-        nee_populations<L>(p, inlet, f, fb);
+        const float rb = kPlain<ST> ? plane_ref<0>(g, rref, rref, x).rout : 0.f;
+        nee_populations<L>(p, inlet, f, fb, ref, rb);
+        ref = rb;
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = fb[i];
     }
@@ -57,9 +66,10 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
         jy += 0.5f * p.F[1];
         jz += 0.5f * p.F[2];
     }
-    const float ri = 1.f / (1.f + drho);
+    const float rh = 1.f + ref + drho;
+    const float ri = __builtin_amdgcn_rcpf(rh);
     const int P = g.P;
-    if (rho) rho[n] = 1.f + drho;
+    if (rho) rho[n] = rh;
     if (u) {
         u[n] = jx * ri;
         u[P + n] = jy * ri;
@@ -70,6 +80,38 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
         j[P + n] = jy;
         if (D == 3) j[2 * P + n] = jz;
     }
+}
+
+// One workgroup per x plane: the mean of drho over the plane's fluid voxels,
+// summed in FP64 in a fixed order (each thread a fixed set of voxels, then a
+// fixed tree over the threads).
+__global__ __launch_bounds__(256) void plane_means_kernel(Grid g, const float *drho, float *rref)
+{
+    __shared__ double ss[256];
+    __shared__ int sc[256];
+    const int x = blockIdx.x;
+    const int64_t cells = (int64_t)g.ny * g.nz;
+    double sum = 0;
+    int cnt = 0;
+    for (int64_t k = threadIdx.x; k < cells; k += 256) {
+        const int y = (int)(k % g.ny), z = (int)(k / g.ny);
+        const int m = g.map[brick_index(g.bk, x, y, z)];
+        if (m >= 0) {
+            sum += (double)ldu(drho, (uint32_t)m);
+            ++cnt;
+        }
+    }
+    ss[threadIdx.x] = sum;
+    sc[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            ss[threadIdx.x] += ss[threadIdx.x + h];
+            sc[threadIdx.x] += sc[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rref[x] = sc[0] > 0 ? (float)(ss[0] / sc[0]) : 0.f;
 }
 
 template <class L>
@@ -136,13 +178,14 @@ __global__ __launch_bounds__(1024) void max_tiles_kernel(const double *in, int n
     if (threadIdx.x == 0) out[0] = sm[0];
 }
 
-__global__ __launch_bounds__(kTile) void mass_kernel(Grid g, const float *C, double *part)
+__global__ __launch_bounds__(kTile) void mass_kernel(Grid g, const float *C, const __half2 *Clo, double *part)
 {
     const int n = blockIdx.x * kTile + threadIdx.x;
     double v[2] = {0, 0};
     if (n < g.n_f) {
-        v[0] = C[n];
-        v[1] = C[g.P + n];
+        const __half2 lo = Clo[n];
+        v[0] = (double)C[n] + lo_decode(__low2half(lo));
+        v[1] = (double)C[g.P + n] + lo_decode(__high2half(lo));
     }
     __shared__ double sm[(kTile / 64) * 2];
     double s[2];
@@ -236,11 +279,13 @@ namespace {
 
 template <class L>
 void launch_moments_l(int st, int odd, unsigned blocks, int nee, const Grid &g, const Phys &p, const void *f,
-                      const float4 *M, float *rho, float *u, float *j, hipStream_t s)
+                      const float4 *M, const float *rref, float *rho, float *u, float *j, hipStream_t s)
 {
-#define MK(S, O) moments_kernel<L, S, O><<<blocks, 256, 0, s>>>(g, p, nee, f, M, rho, u, j)
+#define MK(S, O) moments_kernel<L, S, O><<<blocks, 256, 0, s>>>(g, p, nee, f, M, rref, rho, u, j)
     if (st == kMom)
         MK(kMom, 0);
+    else if (st == kH16)
+        odd == kPull ? MK(kH16, kPull) : odd ? MK(kH16, 1) : MK(kH16, 0);
     else if (st == kF16)
         odd == kPull ? MK(kF16, kPull) : odd ? MK(kF16, 1) : MK(kF16, 0);
     else
@@ -251,15 +296,23 @@ void launch_moments_l(int st, int odd, unsigned blocks, int nee, const Grid &g, 
 }  // namespace
 
 hipError_t launch_moments(int dim, int st, int odd, int nee, const Grid &g, const Phys &p,
-                          const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s)
+                          const void *f, const float4 *M, const float *rref, float *rho, float *u, float *j,
+                          hipStream_t s)
 {
     const unsigned blocks = (unsigned)((g.n_f + 255) / 256);
     if (blocks == 0) return hipSuccess;
-    if (st < kF32 || st > kMom) return hipErrorInvalidValue;
+    if (st < kF32 || st > kH16) return hipErrorInvalidValue;
     if (dim == 2)
-        launch_moments_l<D2Q9>(st, odd, blocks, nee, g, p, f, M, rho, u, j, s);
+        launch_moments_l<D2Q9>(st, odd, blocks, nee, g, p, f, M, rref, rho, u, j, s);
     else
-        launch_moments_l<D3Q19>(st, odd, blocks, nee, g, p, f, M, rho, u, j, s);
+        launch_moments_l<D3Q19>(st, odd, blocks, nee, g, p, f, M, rref, rho, u, j, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_means(const Grid &g, const float *drho, float *rref, hipStream_t s)
+{
+    if (g.nx <= 0) return hipSuccess;
+    plane_means_kernel<<<g.nx, 256, 0, s>>>(g, drho, rref);
     return hipGetLastError();
 }
 
@@ -281,11 +334,11 @@ hipError_t launch_reduce_tiles(const double *in, int ntiles, int stride, int wid
     return hipGetLastError();
 }
 
-hipError_t launch_mass(const Grid &g, const float *C, double *part, double *out, hipStream_t s)
+hipError_t launch_mass(const Grid &g, const float *C, const __half2 *Clo, double *part, double *out, hipStream_t s)
 {
     const int tiles = g.P / kTile;
     if (tiles == 0) return hipSuccess;
-    mass_kernel<<<tiles, kTile, 0, s>>>(g, C, part);
+    mass_kernel<<<tiles, kTile, 0, s>>>(g, C, Clo, part);
     reduce_tiles_kernel<<<1, 1024, 0, s>>>(part, tiles, 2, 2, out);
     return hipGetLastError();
 }

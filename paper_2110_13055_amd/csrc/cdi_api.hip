@@ -110,7 +110,8 @@ int check_params(const cdi_params *p)
         return fail(CDI_E_INVALID, "bad equilibrium");
     if (p->np_x_bc < 0 || p->np_x_bc > 3) return fail(CDI_E_INVALID, "bad np_x_bc");
     if (p->np_substeps < 1) return fail(CDI_E_INVALID, "np_substeps must be >= 1");
-    if (p->precision != CDI_FP32 && p->precision != CDI_FP16_DEV && p->precision != CDI_MOMENTS)
+    if (p->precision != CDI_FP32 && p->precision != CDI_FP16_DEV && p->precision != CDI_MOMENTS &&
+        p->precision != CDI_FP16)
         return fail(CDI_E_INVALID, "bad precision");
     if (p->streaming != CDI_STREAM_AA && p->streaming != CDI_STREAM_PULL)
         return fail(CDI_E_INVALID, "bad streaming");
@@ -233,9 +234,11 @@ struct NodeLayout {
     float *j[2];
     float *ubuf;
     float *C[2];
+    __half2 *Clo[2];  // the concentrations' FP16 remainders (both species per node)
     float *tmp;
     float *xfer;  // lexicographic staging for host copies (4 planes of N_f)
     float *psi;   // prescribed potential in internal node order
+    float *rref[2];  // FP32 storage: plane reference tables (nx values each; see PlaneRef)
     double *acc, *resid, *part, *red;
     int *sched;
     int *nbr;    // neighbour list (Q-1 planes of P), built once
@@ -245,7 +248,11 @@ struct NodeLayout {
 };
 
 // Bytes per stored population of a storage kind.
-static int pop_bytes(int st) { return st == kF32 ? 4 : st == kF16 ? 2 : 0; }
+static int pop_bytes(int st) { return st == kF32 ? 4 : (st == kF16 || st == kH16) ? 2 : 0; }
+// the storages with FP32 moment buffers (their fused steps carry j there)
+static bool moment_buffers(int st) { return st == kF16 || st == kMom; }
+// the storages relative to plane references
+static bool plain_pops(int st) { return st == kF32 || st == kH16; }
 
 // Doubles of the diagnostics scratch: per-tile sums (3 per tile) or the
 // vertical-profile partials (3 per x plane and z chunk) plus its result (3 nx).
@@ -258,11 +265,11 @@ static uint64_t diag_doubles(const cdi_geometry *g, int64_t P)
 }
 
 static NodeLayout node_layout(void *ws, int dim, int st, int pull, int64_t P, int64_t plane,
-                              uint64_t ndiag)
+                              uint64_t ndiag, int64_t nx)
 {
     const int Q = dim == 2 ? 9 : 19;
     const int64_t ntiles = P / kTile;
-    const bool mb = st != kF32;  // moment buffers
+    const bool mb = moment_buffers(st);
     Carver c(ws);
     NodeLayout L;
     L.base = ws;
@@ -275,12 +282,17 @@ static NodeLayout node_layout(void *ws, int dim, int st, int pull, int64_t P, in
     if (st == kMom) L.f = nullptr;
     L.j[0] = c.take<float>(4ull * dim * P);
     L.j[1] = c.take<float>(4ull * dim * P);
-    L.ubuf = c.take<float>(4ull * dim * P);
+    L.ubuf = c.take<float>(4ull * (dim + 1) * P);
     L.C[0] = c.take<float>(8ull * P);
     L.C[1] = c.take<float>(8ull * P);
+    L.Clo[0] = c.take<__half2>(4ull * P);
+    L.Clo[1] = c.take<__half2>(4ull * P);
     L.tmp = c.take<float>(4ull * (1 + dim) * P);
     L.xfer = c.take<float>(16ull * P);
     L.psi = c.take<float>(4ull * P);
+    L.rref[0] = c.take<float>(plain_pops(st) ? 4ull * nx : 0);
+    L.rref[1] = c.take<float>(plain_pops(st) ? 4ull * nx : 0);
+    if (!plain_pops(st)) L.rref[0] = L.rref[1] = nullptr;
     L.acc = c.take<double>(64ull * ntiles);
     L.resid = c.take<double>(16ull * ntiles);
     L.part = c.take<double>(16ull * ntiles);
@@ -299,7 +311,7 @@ struct cdi_solver {
     cdi_geometry geom;
     cdi_params params;
     int dim, Q, inout;
-    int st;    // storage: kF32, kF16 or kMom
+    int st;    // storage: kF32, kF16, kMom or kH16
     int pull;  // pull streaming (two population arrays; fcur holds the state)
     int mb;  // moment buffers in use (kF16, kMom): j of a fused step lives in them
     int64_t nvox, nf;
@@ -308,6 +320,9 @@ struct cdi_solver {
     VoxLayout vox;
     NodeLayout node;
     int parity = 0, fcur = 0, mcur = 0, jcur = 0, ccur = 0, jstate = J_INVALID;
+    int rcur = 0;   // FP32: the plane reference table of the stored state
+    int rpend = 0;  // the next flow step renews it (reads with rref[rcur], writes with the other)
+    int rlive = 0;  // the references have been renewed at least once (before, all are zero)
     int64_t flow_steps = 0, np_steps = 0;
     double ka, keff[2], porosity;
     cdi_tuning tuning{0, 0, 0, 0};
@@ -320,13 +335,17 @@ namespace {
 struct SnapHeader {
     uint64_t magic, bytes;
     int32_t parity, mcur, jcur, ccur, jstate, fcur;
-    int32_t psi_on, pad;  // the potential in use is the field in the state (else the ramp)
+    int32_t psi_on;  // the potential in use is the field in the state (else the ramp)
+    int32_t rstate;  // rcur | rpend << 1 | rlive << 2
     int64_t flow_steps, np_steps, nf;
 };
 constexpr uint64_t kSnapMagic = 0x43444931534e4150ull;
 
 // Population array holding the state, and the kernels' parity argument.
 void *cur_pops(const cdi_solver *s) { return s->pull && s->fcur ? s->node.f2 : s->node.f; }
+// FP32 / FP16 populations: the plane reference table of the stored state
+// (nullptr while every reference is still zero, so the steps skip it).
+const float *cur_rref(const cdi_solver *s) { return s->rlive ? s->node.rref[s->rcur] : nullptr; }
 int stream_arg(const cdi_solver *s) { return s->pull ? kPull : s->parity; }
 
 // Buffers of the next step of s (current double-buffer halves).
@@ -343,7 +362,12 @@ Bufs make_bufs(const cdi_solver *s, int flags)
     b.jout = s->node.j[s->jcur ^ 1];
     b.Cin = s->node.C[s->ccur];
     b.Cout = s->node.C[s->ccur ^ 1];
+    b.Clin = s->node.Clo[s->ccur];
+    b.Clout = s->node.Clo[s->ccur ^ 1];
     b.ubuf = s->node.ubuf;
+    b.rin = cur_rref(s);
+    b.rout = s->rpend ? s->node.rref[s->rcur ^ 1] : b.rin;
+    if (s->rpend && !b.rin) b.rin = s->node.rref[s->rcur];  // the first renewal reads the zero table
     b.acc = s->node.acc;
     b.resid = s->node.resid;
     b.flags = flags | (s->flow_steps > 0 ? kNee : 0);
@@ -354,6 +378,10 @@ Bufs make_bufs(const cdi_solver *s, int flags)
 void advance_state(cdi_solver *s, int lbm, int np)
 {
     if (lbm) {
+        if (s->rpend) {
+            s->rcur ^= 1;
+            s->rpend = 0;
+        }
         s->parity ^= 1;
         if (s->pull) s->fcur ^= 1;
         if (s->mb) s->mcur ^= 1;
@@ -378,7 +406,7 @@ int ensure_j(cdi_solver *s)
         HIPCHK(launch_j_from_m(s->dim, s->g, s->node.M[s->mcur], s->node.j[s->jcur], s->stream));
     } else {
         HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
-                              s->mb ? s->node.M[s->mcur] : nullptr, nullptr, nullptr,
+                              s->mb ? s->node.M[s->mcur] : nullptr, cur_rref(s), nullptr, nullptr,
                               s->node.j[s->jcur], s->stream));
     }
     s->jstate = J_VALID;
@@ -604,8 +632,8 @@ int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *
     const int st = params ? params->precision : CDI_FP32;
     const int pull = params ? params->streaming == CDI_STREAM_PULL : 0;
     const int Q = dim == 2 ? 9 : 19;
-    out->node_bytes_per_fluid = (uint64_t)Q * pop_bytes(st) * (pull ? 2 : 1) + (st != kF32 ? 32 : 0) +
-                                12ull * dim + 16 + 4ull * (1 + dim) + 4ull * (Q - 1) + 1;
+    out->node_bytes_per_fluid = (uint64_t)Q * pop_bytes(st) * (pull ? 2 : 1) + (moment_buffers(st) ? 32 : 0) +
+                                12ull * dim + 4 + 16 + 8 + 4ull * (1 + dim) + 4ull * (Q - 1) + 1;
     g_err[0] = 0;
     return CDI_OK;
 }
@@ -669,7 +697,7 @@ int cdi_node_bytes(const cdi_geometry *geom, const cdi_params *params, int64_t n
     if (!bytes || n_fluid <= 0) return fail(CDI_E_INVALID, "bad n_fluid or bytes pointer");
     const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
     *bytes = node_layout(nullptr, geom->dim, params->precision, params->streaming == CDI_STREAM_PULL, P,
-                         (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz), diag_doubles(geom, P)).bytes;
+                         (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz), diag_doubles(geom, P), geom->nx).bytes;
     return CDI_OK;
 }
 
@@ -703,10 +731,13 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     const int st_kind = params->precision;
     const int64_t P = (n_fluid + kTile - 1) / kTile * kTile;
     // per-node arrays are addressed with 32-bit byte offsets (16-byte moments)
-    if (P * (st_kind == kF32 ? 4 : 16) > 4294967295LL)
-        return fail(CDI_E_INVALID, "too many fluid nodes for one instance (limit 2^30, 2^28 with moment buffers)");
+    // (the two planes of a direction and its opposite from one base: 2P elements)
+    if (P * (st_kind == kF32 ? 8 : moment_buffers(st_kind) ? 16 : 4) > 4294967295LL)
+        return fail(CDI_E_INVALID,
+                    "too many fluid nodes for one instance (limit 2^29 FP32, 2^30 FP16, 2^28 with moment buffers)");
     NodeLayout N = node_layout(node_ws, geom->dim, st_kind, params->streaming == CDI_STREAM_PULL, P,
-                               (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz), diag_doubles(geom, P));
+                               (int64_t)geom->ny * (geom->dim == 2 ? 1 : geom->nz), diag_doubles(geom, P),
+                               geom->nx);
     if (node_ws_bytes < N.bytes) return fail(CDI_E_BUFFER, "node_ws too small: %llu < %llu",
                                              (unsigned long long)node_ws_bytes, (unsigned long long)N.bytes);
     if (params->np_x_bc != CDI_NPX_PERIODIC && params->np_x_bc != CDI_NPX_CLOSED && geom->nx < 2)
@@ -720,7 +751,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     s->dim = geom->dim;
     s->Q = geom->dim == 2 ? 9 : 19;
     s->st = st_kind;
-    s->mb = st_kind != kF32;
+    s->mb = moment_buffers(st_kind);
     s->pull = params->streaming == CDI_STREAM_PULL && st_kind != kMom;
     s->inout = params->drive == CDI_INLET_OUTLET;
     s->nvox = nvox;
@@ -784,17 +815,26 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
         if (s->st == kF16 && s->pull) chk(launch_fill_u32((uint32_t *)N.f2, 0u, (int64_t)s->Q * P / 2, st));
         chk(launch_fill_f32((float *)N.M[0], 0.f, 4 * P, st));
         chk(launch_fill_f32((float *)N.M[1], 0.f, 4 * P, st));
+    } else if (s->st == kH16) {
+        chk(launch_fill_u32((uint32_t *)N.f, 0u, (int64_t)s->Q * P / 2, st));
+        if (s->pull) chk(launch_fill_u32((uint32_t *)N.f2, 0u, (int64_t)s->Q * P / 2, st));
     } else {
         chk(launch_fill_f32((float *)N.f, 0.f, (int64_t)s->Q * P, st));
         if (s->pull) chk(launch_fill_f32((float *)N.f2, 0.f, (int64_t)s->Q * P, st));
     }
     chk(launch_fill_f32(N.j[0], 0.f, (int64_t)s->dim * P, st));
     chk(launch_fill_f32(N.j[1], 0.f, (int64_t)s->dim * P, st));
-    chk(launch_fill_f32(N.ubuf, 0.f, (int64_t)s->dim * P, st));
+    chk(launch_fill_f32(N.ubuf, 0.f, (int64_t)(s->dim + 1) * P, st));
+    if (N.rref[0]) {  // rest state: no reference deviation yet
+        chk(launch_fill_f32(N.rref[0], 0.f, geom->nx, st));
+        chk(launch_fill_f32(N.rref[1], 0.f, geom->nx, st));
+    }
     if (params->psi_field)
         chk(launch_permute(params->psi_field, N.psi, V.lex2int, (int)n_fluid, (int)P, 1, 0, st));
     chk(launch_fill_f32(N.C[0], (float)params->c0, 2 * P, st));
     chk(launch_fill_f32(N.C[1], (float)params->c0, 2 * P, st));
+    chk(launch_fill_u32((uint32_t *)N.Clo[0], 0u, P, st));
+    chk(launch_fill_u32((uint32_t *)N.Clo[1], 0u, P, st));
     chk(launch_fill_f64(N.acc, 0.0, 8ll * s->ntiles, st));
     chk(launch_fill_f64(N.resid, 0.0, 2ll * s->ntiles, st));
     chk(launch_build_nbr(s->dim, g, N.nbr, st));
@@ -864,6 +904,14 @@ int cdi_flow_step_to_steady(cdi_solver *s, double tol, int64_t max_steps, int32_
         if (check) flags |= kResid;
         int rc = step_once(s, 1, 0, flags);
         if (rc) return rc;
+        if ((flags & kStoreU) && s->node.rref[0]) {
+            // FP32: renew the plane references from this state's rho - 1 (stored
+            // with u); the next step reads with the old table and writes with the new
+            HIPCHK(launch_plane_means(s->g, s->node.ubuf + (size_t)s->dim * s->P, s->node.rref[s->rcur ^ 1],
+                                      s->stream));
+            s->rpend = 1;
+            s->rlive = 1;
+        }
         if (check) {
             HIPCHK(launch_reduce_tiles(s->node.resid, s->ntiles, 2, 2, s->node.red, s->stream));
             double h[2];
@@ -931,7 +979,7 @@ int cdi_mass_balance(cdi_solver *s, double out[8])
 {
     if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
     HIPCHK(launch_reduce_tiles(s->node.acc, s->ntiles, 8, 6, s->node.red, s->stream));
-    HIPCHK(launch_mass(s->g, s->node.C[s->ccur], s->node.part, s->node.red + 8, s->stream));
+    HIPCHK(launch_mass(s->g, s->node.C[s->ccur], s->node.Clo[s->ccur], s->node.part, s->node.red + 8, s->stream));
     double h[10];
     int rc = d2h(s, h, s->node.red, 80);
     if (rc) return rc;
@@ -963,7 +1011,7 @@ int cdi_copy_velocity(cdi_solver *s, float *u)
 {
     if (!s || !u) return fail(CDI_E_INVALID, "NULL argument");
     HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
-                          s->mb ? s->node.M[s->mcur] : nullptr, nullptr, s->node.tmp, nullptr, s->stream));
+                          s->mb ? s->node.M[s->mcur] : nullptr, cur_rref(s), nullptr, s->node.tmp, nullptr, s->stream));
     return planes_d2h(s, u, s->node.tmp, s->dim);
 }
 
@@ -971,7 +1019,7 @@ int cdi_copy_density(cdi_solver *s, float *rho)
 {
     if (!s || !rho) return fail(CDI_E_INVALID, "NULL argument");
     HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
-                          s->mb ? s->node.M[s->mcur] : nullptr, s->node.tmp, nullptr, nullptr, s->stream));
+                          s->mb ? s->node.M[s->mcur] : nullptr, cur_rref(s), s->node.tmp, nullptr, nullptr, s->stream));
     return planes_d2h(s, rho, s->node.tmp, 1);
 }
 
@@ -1001,7 +1049,10 @@ int cdi_copy_concentration(cdi_solver *s, float *c)
 int cdi_set_concentration(cdi_solver *s, const float *c)
 {
     if (!s || !c) return fail(CDI_E_INVALID, "NULL argument");
-    return planes_h2d(s, s->node.C[s->ccur], c, 2);
+    int rc = planes_h2d(s, s->node.C[s->ccur], c, 2);
+    if (rc) return rc;
+    HIPCHK(launch_fill_u32((uint32_t *)s->node.Clo[s->ccur], 0u, s->P, s->stream));  // no remainders
+    return CDI_OK;
 }
 
 // ------------------------------------------------------------ electric potential
@@ -1278,7 +1329,7 @@ int np_solve(cdi_solver *s, double idt, double tol, int32_t max_iter, void *ws, 
     }
     *iters = (int)std::max(st[kNsIters], st[kNsIters + 1]);
     if (st[kNsDone] == 2.0) return fail(CDI_E_DIVERGED, "ion solve diverged or broke down after %d iterations", k);
-    HIPCHK(launch_nps_store(a, s->node.C[s->ccur], s->stream));
+    HIPCHK(launch_nps_store(a, s->node.C[s->ccur], s->node.Clo[s->ccur], s->stream));
     if (st[kNsDone] == 0)
         return fail(CDI_E_NOT_CONVERGED, "ion solve: %d iterations, relative residuals %g, %g", k,
                     std::sqrt(st[kNsRr] / std::max(st[kNsBb], 1e-300)),
@@ -1347,7 +1398,7 @@ int cdi_diagnostics(cdi_solver *s, cdi_diag *out)
     if (!s || !out) return fail(CDI_E_INVALID, "NULL argument");
     // u of the current populations into tmp (d planes), then the tile sums
     HIPCHK(launch_moments(s->dim, s->st, stream_arg(s), s->flow_steps > 0, s->g, s->p, cur_pops(s),
-                          s->mb ? s->node.M[s->mcur] : nullptr, nullptr, s->node.tmp, nullptr, s->stream));
+                          s->mb ? s->node.M[s->mcur] : nullptr, cur_rref(s), nullptr, s->node.tmp, nullptr, s->stream));
     HIPCHK(launch_diag(s->dim, s->g, s->node.tmp, s->node.nbr, s->node.diag, s->node.red, s->stream));
     double h[3];
     int rc = d2h(s, h, s->node.red, sizeof h);
@@ -1403,7 +1454,8 @@ int cdi_snapshot(cdi_solver *s, void *host, uint64_t bytes)
     if (!s || !host) return fail(CDI_E_INVALID, "NULL argument");
     if (bytes < sizeof(SnapHeader) + s->node.state_bytes) return fail(CDI_E_BUFFER, "snapshot buffer too small");
     SnapHeader h{kSnapMagic, s->node.state_bytes, s->parity, s->mcur, s->jcur, s->ccur, s->jstate, s->fcur,
-                 s->p.psi != nullptr, 0, s->flow_steps, s->np_steps, s->nf};
+                 s->p.psi != nullptr, s->rcur | (s->rpend << 1) | (s->rlive << 2), s->flow_steps, s->np_steps,
+                 s->nf};
     std::memcpy(host, &h, sizeof h);
     return d2h(s, (uint8_t *)host + sizeof h, s->node.base, s->node.state_bytes);
 }
@@ -1425,6 +1477,9 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
     s->jcur = h.jcur;
     s->ccur = h.ccur;
     s->jstate = h.jstate;
+    s->rcur = h.rstate & 1;
+    s->rpend = (h.rstate >> 1) & 1;
+    s->rlive = (h.rstate >> 2) & 1;
     s->flow_steps = h.flow_steps;
     s->np_steps = h.np_steps;
     s->p.psi = h.psi_on ? s->node.psi : nullptr;
@@ -1817,6 +1872,8 @@ int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
         if (md == kModeFlow) any_flow = true;
         if ((md == kModeFlow || md == kModeFused) && s->flow_steps == 0) need_first = true;
         if (md == kModeFused && s->mb) need_first = true;
+        // a pending renewal of the plane references applies to one step only
+        if ((md == kModeFlow || md == kModeFused) && s->rpend) need_first = true;
     }
     // order after the members' own streams
     for (int k = 0; k < bt->n; ++k) HIPCHK(hipStreamSynchronize(bt->m[k]->stream));

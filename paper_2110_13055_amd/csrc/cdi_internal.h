@@ -137,14 +137,27 @@ struct Bufs {
     float *jout;
     const float *Cin;
     float *Cout;
+    const __half2 *Clin;  // the concentrations' FP16 remainders (see lo_encode), per node
+    __half2 *Clout;
     double *acc;
     double *resid;
-    float *ubuf;
+    float *ubuf;    // FP32 storage: u (d planes) and rho - 1 (plane d) of the state, on kStoreU
+    // FP32 storage: reference density deviation per x plane of the values read
+    // and of the values written (see PlaneRef); nullptr: zero
+    const float *rin;
+    const float *rout;
     int flags;
 };
 
-// Storage of the lattice state (values of cdi_params.precision).
-constexpr int kF32 = 0, kF16 = 1, kMom = 2;
+// Storage of the lattice state (values of cdi_params.precision): FP32
+// populations and FP16 populations (both relative to the plane references,
+// the FP16 ones scaled; the ions' flux in its own buffer), FP16 deviations
+// from the emitter's equilibrium with FP32 moment buffers, moments only.
+constexpr int kF32 = 0, kF16 = 1, kMom = 2, kH16 = 3;
+template <int ST>
+constexpr bool kPlain = ST == kF32 || ST == kH16;  // populations relative to the plane references
+template <int ST>
+constexpr bool kHalfPop = ST == kF16 || ST == kH16;  // populations stored in FP16
 
 // One instance of a batched launch.
 constexpr int kModeIdle = 0, kModeFlow = 1, kModeIons = 2, kModeFused = 3;
@@ -204,9 +217,15 @@ hipError_t launch_step(int dim, int st, int odd, int lbm, int np, const Grid &g,
 hipError_t launch_batch(int dim, int st, int cls, const BatchInst *inst, const int2 *tiles, int ntiles,
                         int workgroups, int lds_pad, hipStream_t s);
 // Moments of the stored state: rho (nullable), u (nullable, d planes),
-// j (nullable, d planes).
+// j (nullable, d planes); rref: the FP32 plane references of the state
+// (nullptr: zero).
 hipError_t launch_moments(int dim, int st, int odd, int nee, const Grid &g, const Phys &p,
-                          const void *f, const float4 *M, float *rho, float *u, float *j, hipStream_t s);
+                          const void *f, const float4 *M, const float *rref, float *rho, float *u, float *j,
+                          hipStream_t s);
+// Plane references: rref[x] = mean of drho (rho - 1 of the fluid nodes, one
+// plane of P values in node order) over the fluid voxels of plane x, 0 where
+// the plane holds none; FP64 sums in a fixed order (one workgroup per plane).
+hipError_t launch_plane_means(const Grid &g, const float *drho, float *rref, hipStream_t s);
 // Packed coordinates of the first node of every tile (host-side tile schedule).
 hipError_t launch_tile_heads(const Grid &g, uint32_t *heads, hipStream_t s);
 // Neighbour list of every fluid node (see Grid::nbr), Q-1 planes of P.
@@ -216,8 +235,8 @@ hipError_t launch_j_from_m(int dim, const Grid &g, const float4 *M, float *j, hi
 // Deterministic single-block sums: out[k] = sum_t in[t*stride + k], k < width.
 hipError_t launch_reduce_tiles(const double *in, int ntiles, int stride, int width, double *out,
                                hipStream_t s);
-// FP64 sum of each concentration field (solute mass): out[0..1].
-hipError_t launch_mass(const Grid &g, const float *C, double *part, double *out, hipStream_t s);
+// FP64 sum of each concentration field with its remainders (solute mass): out[0..1].
+hipError_t launch_mass(const Grid &g, const float *C, const __half2 *Clo, double *part, double *out, hipStream_t s);
 // max over nodes/species of dt * (sum of outflow coefficients); out[0].
 hipError_t launch_stability(int dim, const Grid &g, const Phys &p, const float *j, double *part,
                             double *out, hipStream_t s);

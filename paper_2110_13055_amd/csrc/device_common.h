@@ -145,14 +145,25 @@ __device__ inline int nb_get(const Grid &g, const NbCtx &c, int i)
     return (L::ex[i] != 0 && c.xo[dx]) ? kOutside : m;
 }
 
-// BGK equilibrium minus w_i for a direction of weight w, from rho - 1, u and
-// e.u: quadratic in u, or its linear (Stokes) part.
+// 1 / rho from rho - 1: the hardware reciprocal (within 1 ulp), one
+// instruction where an IEEE division takes ten. Every kernel that forms u =
+// j / rho uses it, so they all form the same u.
+__device__ __forceinline__ float inv_rho(float drho) { return __builtin_amdgcn_rcpf(1.f + drho); }
+
+// BGK equilibrium less w_i (1 + R) for a direction of weight w, where R is a
+// reference density deviation: from dr = rho - 1 - R, rho and e.u. Quadratic
+// in u, or its linear (Stokes) part.
+__device__ inline float feq_rel_eu(float w, float dr, float rho, float eu, float ux, float uy, float uz, int linear)
+{
+    if (linear) return w * (dr + 3.f * rho * eu);
+    const float uu = ux * ux + uy * uy + uz * uz;
+    return w * (dr + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+}
+
+// The same with R = 0 (equilibrium minus w_i, from rho - 1).
 __device__ inline float feq_bar_eu(float w, float drho, float eu, float ux, float uy, float uz, int linear)
 {
-    const float rho = 1.f + drho;
-    if (linear) return w * (drho + 3.f * rho * eu);
-    const float uu = ux * ux + uy * uy + uz * uz;
-    return w * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+    return feq_rel_eu(w, drho, 1.f + drho, eu, ux, uy, uz, linear);
 }
 
 // The same for lattice direction i.
@@ -163,23 +174,103 @@ __device__ inline float feq_bar(int i, float drho, float ux, float uy, float uz,
     return feq_bar_eu(L::w[i], drho, eu, ux, uy, uz, linear);
 }
 
-// Population plane i of node n (planes P apart).
-template <int FP16>
-__device__ inline float ld(const void *F, int P, int i, int n)
+template <class L>
+__device__ inline float feq_rel(int i, float dr, float rho, float ux, float uy, float uz, int linear)
 {
-    const size_t o = (size_t)i * P + n;
-    if (FP16) return __half2float(reinterpret_cast<const __half *>(F)[o]);
-    return reinterpret_cast<const float *>(F)[o];
+    const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+    return feq_rel_eu(L::w[i], dr, rho, eu, ux, uy, uz, linear);
+}
+
+// FP32 population storage holds f_i - w_i (1 + R[x_s]), where x_s is the x
+// plane of the node whose slot holds the value (pull streaming: the emitter,
+// the node that collided it; AA: the node written to) and R[x] is a reference
+// density deviation per x plane (the plane mean of rho - 1, renewed now and
+// then: the stored values then carry only the local fluctuations, which FP32
+// rounds far more finely than f - w_i near a pressure drop). A step reads
+// with table Rin and writes with table Rout (equal except on the step that
+// renews R) and works with g_i = f_i - w_i (1 + Rout[x]) = stored +
+// w_i (Rin[x_s] - Rout[x]). A value written into the slot of the neighbour
+// x + e_i (AA, odd parity) is stored as g + w_i (Rout[x] - Rout[x + e_x]).
+struct PlaneRef {
+    float rout;   // Rout[x]
+    float dIn[3]; // Rin[x - ex] - Rout[x], ex = -1, 0, 1
+    float dOut[3];// Rout[x] - Rout[x + ex]
+};
+
+// (dOut only for the odd AA parity, which writes into neighbours' slots)
+template <int ODD>
+__device__ inline PlaneRef plane_ref(const Grid &g, const float *rin, const float *rout, int x)
+{
+    PlaneRef r{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    if (!rin) return r;
+    const int xm = x > 0 ? x - 1 : (g.periodic_x ? g.nx - 1 : 0);
+    const int xp = x < g.nx - 1 ? x + 1 : (g.periodic_x ? 0 : g.nx - 1);
+    r.rout = ldu(rout, (uint32_t)x);
+    r.dIn[0] = ldu(rin, (uint32_t)xp) - r.rout;  // ex = -1: the slot's node is at x + 1
+    r.dIn[1] = ldu(rin, (uint32_t)x) - r.rout;
+    r.dIn[2] = ldu(rin, (uint32_t)xm) - r.rout;  // ex = +1: at x - 1
+    if (ODD == 1) {
+        r.dOut[0] = r.rout - ldu(rout, (uint32_t)xm);
+        r.dOut[2] = r.rout - ldu(rout, (uint32_t)xp);
+    }
+    return r;
+}
+
+// g_i from the stored value read for direction i (ODD: the kernels' parity
+// argument) of a node whose neighbours are nb.
+template <class L, int ODD>
+__device__ __forceinline__ float rel_pop(float raw, int i, const int *nb, const PlaneRef &r)
+{
+    const bool fl = (i != 0) && nb[L::opp[i]] >= 0;
+    const bool there = ODD != 0 && fl;  // pull or odd parity: read in the emitter's slot
+    return raw + L::w[i] * (there ? r.dIn[L::ex[i] + 1] : r.dIn[1]);
+}
+
+// The value to store for outgoing g_i (relative to Rout[x]).
+template <class L, int ODD>
+__device__ __forceinline__ float stored_pop(float g, int i, const int *nb, const PlaneRef &r)
+{
+    if (ODD != 1 || i == 0) return g;  // written into the node's own slot
+    return nb[i] >= 0 ? g + L::w[i] * r.dOut[L::ex[i] + 1] : g;
+}
+
+// Plane i of a structure-of-arrays field (planes P apart). The plane's base
+// is the same for the whole wave, so an access is that base plus a 32-bit
+// byte offset of the node: no 64-bit address arithmetic per lane.
+template <class T>
+__device__ __forceinline__ T *plane_of(void *F, int P, int i)
+{
+    return reinterpret_cast<T *>(F) + (size_t)i * (size_t)P;
+}
+template <class T>
+__device__ __forceinline__ const T *plane_of(const void *F, int P, int i)
+{
+    return reinterpret_cast<const T *>(F) + (size_t)i * (size_t)P;
+}
+
+// Value of plane a at node na, or of plane b at node nb (one of the two per
+// lane), where a and b are the same plane or two adjacent ones (a direction
+// and its opposite are numbered as neighbours): both are addressed from the
+// lower plane's base, so a single load with a 32-bit offset of at most 2P
+// elements serves either case.
+template <int FP16>
+__device__ __forceinline__ float ld_pair(const void *F, int P, int a, int na, int b, int nb, bool first)
+{
+    const int lo = a < b ? a : b;
+    const uint32_t idx = first ? (uint32_t)na + (a > lo ? (uint32_t)P : 0u) : (uint32_t)nb + (b > lo ? (uint32_t)P : 0u);
+    if (FP16) return __half2float(ldu(plane_of<__half>(F, P, lo), idx));
+    return ldu(plane_of<float>(F, P, lo), idx);
 }
 
 template <int FP16>
-__device__ inline void st(void *F, int P, int i, int n, float v)
+__device__ __forceinline__ void st_pair(void *F, int P, int a, int na, int b, int nb, bool first, float v)
 {
-    const size_t o = (size_t)i * P + n;
+    const int lo = a < b ? a : b;
+    const uint32_t idx = first ? (uint32_t)na + (a > lo ? (uint32_t)P : 0u) : (uint32_t)nb + (b > lo ? (uint32_t)P : 0u);
     if (FP16)
-        reinterpret_cast<__half *>(F)[o] = __float2half_rn(v);
+        stu(plane_of<__half>(F, P, lo), idx, __float2half_rn(v));
     else
-        reinterpret_cast<float *>(F)[o] = v;
+        stu(plane_of<float>(F, P, lo), idx, v);
 }
 
 // Stored value behind the incoming population i of node n (FP32 f - w_i or
@@ -188,11 +279,13 @@ template <class L, int ST, int ODD>
 __device__ inline float gather_raw(const void *F, int P, const int *nb, int n, int i)
 {
     if (ST == kMom) return 0.f;
+    constexpr bool H = kHalfPop<ST>;
     const int j = L::opp[i];
     const bool fl = (i != 0) && nb[j] >= 0;
-    if (ODD == kPull) return fl ? ld<ST == kF16>(F, P, i, nb[j]) : ld<ST == kF16>(F, P, j, n);
-    if (!ODD || i == 0 || !fl) return ld<ST == kF16>(F, P, i, n);
-    return ld<ST == kF16>(F, P, j, nb[j]);
+    // pull: plane i of the emitter x - e_i, or the node's own reflected plane j
+    if (ODD == kPull) return ld_pair<H>(F, P, i, nb[j], j, n, fl);
+    // AA: plane i of the node itself, or (odd parity, fluid emitter) plane j of the emitter
+    return ld_pair<H>(F, P, i, n, j, nb[j], !ODD || i == 0 || !fl);
 }
 
 // FP16 and moment storage: f_i - w_i from the stored value and the emitter's
@@ -215,6 +308,7 @@ __device__ inline float gather(const void *F, int P, const int *nb, int n, int i
 {
     const float raw = gather_raw<L, ST, ODD>(F, P, nb, n, i);
     if (ST == kF32) return raw;
+    if (ST == kH16) return raw * p.hs_inv;
     const int j = L::opp[i];
     const bool fl = (i != 0) && nb[j] >= 0;
     return from_emitter<L, ST>(raw, i, fl, ldu(M, (uint32_t)(fl ? nb[j] : n)), p);
@@ -226,24 +320,25 @@ template <class L, int ST, int ODD>
 __device__ inline void scatter(void *F, int P, const int *nb, int n, int i, float v)
 {
     if (ST == kMom) return;
-    constexpr bool H = ST == kF16;
+    constexpr bool H = kHalfPop<ST>;
+    const int j = L::opp[i];
     if (ODD == kPull)
-        st<H>(F, P, i, n, v);
-    else if (!ODD || i == 0)
-        st<H>(F, P, L::opp[i], n, v);
-    else if (nb[i] >= 0)
-        st<H>(F, P, i, nb[i], v);
+        st_pair<H>(F, P, i, n, i, n, true, v);  // the node's own plane i
     else
-        st<H>(F, P, L::opp[i], n, v);
+        // even parity (or the rest direction): the node's own plane opp(i); odd
+        // parity: plane i of the fluid neighbour x + e_i, else (reflected) plane opp(i)
+        st_pair<H>(F, P, j, n, i, nb[i], !ODD || i == 0 || nb[i] < 0, v);
 }
 
 // Non-equilibrium extrapolation (Guo, Zheng & Shi 2002) for the inlet
 // (velocity u_in) or outlet (density rho_out) node next to the interior node
 // whose post-streaming populations are fc: the boundary takes the target
-// equilibrium plus the interior node's non-equilibrium part.
+// equilibrium plus the interior node's non-equilibrium part. fc is relative to
+// the interior node's reference rc (fc_i = f_i - w_i (1 + rc)), fb is returned
+// relative to the boundary node's rb (0 and 0 for f - w_i storage).
 template <class L>
-__device__ inline void nee_populations(const Phys &p, bool inlet, const float (&fc)[L::Q],
-                                       float (&fb)[L::Q])
+__device__ inline void nee_populations(const Phys &p, bool inlet, const float (&fc)[L::Q], float (&fb)[L::Q],
+                                       float rc = 0.f, float rb = 0.f)
 {
     float dr = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -253,14 +348,40 @@ __device__ inline void nee_populations(const Phys &p, bool inlet, const float (&
         jy += L::ey[i] * fc[i];
         jz += L::ez[i] * fc[i];
     }
-    const float ri = 1.f / (1.f + dr);
+    const float rho = 1.f + rc + dr;
+    const float ri = __builtin_amdgcn_rcpf(rho);
     const float ux = jx * ri, uy = jy * ri, uz = jz * ri;
-    const float tdr = inlet ? dr : p.rho_out - 1.f;
+    // target: inlet (rho of the interior node, u_in), outlet (rho_out, u of the interior node)
+    const float trho = inlet ? rho : p.rho_out;
     const float tx = inlet ? p.u_in : ux, ty = inlet ? 0.f : uy, tz = inlet ? 0.f : uz;
+    const float tdr = inlet ? (rc + dr) - rb : (p.rho_out - 1.f) - rb;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        fb[i] = feq_bar<L>(i, tdr, tx, ty, tz, p.linear_eq) +
-                (fc[i] - feq_bar<L>(i, dr, ux, uy, uz, p.linear_eq));
+        fb[i] = feq_rel<L>(i, tdr, trho, tx, ty, tz, p.linear_eq) +
+                (fc[i] - feq_rel<L>(i, dr, rho, ux, uy, uz, p.linear_eq));
+}
+
+// Concentrations are stored as an FP32 value and an FP16 remainder per
+// species (times 2^24): value + remainder carry the explicit update's sum to
+// about 2^-35 of C, so increments far below half an FP32 ulp accumulate in the
+// remainder instead of being dropped. (Rounded to FP32 alone, the update
+// stalls wherever a cell's change per step falls below half an ulp, which
+// near a steady state left C up to 1e-3 off after 20000 steps.) A remainder
+// too large for FP16 (|C| beyond 2^15) is dropped.
+__device__ __forceinline__ float lo_decode(__half h) { return __half2float(h) * (1.f / 16777216.f); }
+__device__ __forceinline__ __half lo_encode(float lo)
+{
+    const float t = lo * 16777216.f;
+    return __float2half_rn(fabsf(t) < 65000.f ? t : 0.f);
+}
+
+// a + b = s + e exactly, s = fl(a + b) (Knuth's TwoSum).
+__device__ __forceinline__ float two_sum(float a, float b, float &e)
+{
+    const float s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+    return s;
 }
 
 // Scharfetter-Gummel flux from P to N with normal drift w, Pe = w / D:
@@ -287,6 +408,55 @@ __device__ inline float sg_flux(float D, float invD2, float hw, float cp, float 
         bs = 0.5f * a * (e + 1.f) * __builtin_amdgcn_rcpf(e - 1.f);
     }
     return fmaf(D * bs, cp - cn, hw * (cp + cn));
+}
+
+// Sum of v over the wave in a fixed order, the same value in every lane:
+// neighbouring pairs, then quads, then eights and rows of 16 by DPP lane
+// permutations within each row of 16 lanes (VALU only, no LDS), then the four
+// rows' sums, each read from the row's first lane, in row order. Every lane
+// of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_plus(float v)
+{
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = dpp_plus<0xB1>(v);   // quad_perm [1,0,3,2]: pairs
+    v = dpp_plus<0x4E>(v);   // quad_perm [2,3,0,1]: quads
+    v = dpp_plus<0x124>(v);  // row_ror:4: two quads
+    v = dpp_plus<0x128>(v);  // row_ror:8: the row of 16
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return ((r0 + r1) + r2) + r3;
+}
+
+// Per-tile FP64 accumulation of N per-lane FP32 amounts: each wave sums its
+// lanes (wave_sum; a wave whose lanes all hold 0 skips it), thread 0 adds the
+// waves' sums in wave order in FP64 and adds the nonzero totals to acc[0..N).
+// Called by every thread of the block; sm holds (blockDim/64) * N doubles.
+template <int N>
+__device__ inline void tile_accumulate(const float (&v)[N], double *sm, double *acc)
+{
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float w = __ballot(v[k] != 0.f) ? wave_sum(v[k]) : 0.f;
+        if ((threadIdx.x & 63) == 0) sm[wave * N + k] = (double)w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double t = 0;
+            for (int w = 0; w < nw; ++w) t += sm[w * N + k];
+            if (t != 0.0) acc[k] += t;
+        }
+    }
+    __syncthreads();
 }
 
 // Sum over the block in a fixed order (wave shuffles, then the waves in

@@ -445,12 +445,15 @@ __global__ __launch_bounds__(kTile) void nps_check_kernel(NpsArgs a, int k, int 
     if (threadIdx.x == 0 && a.state[kNsDone] == 0.0 && !act[0] && !act[1]) a.state[kNsDone] = 1.0;
 }
 
-__global__ __launch_bounds__(kTile) void nps_store_kernel(const double *x, float *C, int P, int n_f)
+// The FP64 solution as FP32 concentrations with their remainders.
+__global__ __launch_bounds__(kTile) void nps_store_kernel(const double *x, float *C, __half2 *Clo, int P, int n_f)
 {
     const int n = blockIdx.x * kTile + threadIdx.x;
     if (n >= n_f) return;
-    C[n] = (float)x[n];
-    C[P + n] = (float)x[P + n];
+    const float c0 = (float)x[n], c1 = (float)x[P + n];
+    C[n] = c0;
+    C[P + n] = c1;
+    Clo[n] = __halves2half2(lo_encode((float)(x[n] - c0)), lo_encode((float)(x[P + n] - c1)));
 }
 
 // Rates of adsorption, inflow and outflow of C (per tile, FP64).
@@ -551,10 +554,10 @@ hipError_t launch_nps_check(const NpsArgs &a, int G, int k, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_nps_store(const NpsArgs &a, float *Cout, hipStream_t s)
+hipError_t launch_nps_store(const NpsArgs &a, float *Cout, __half2 *Clo, hipStream_t s)
 {
     const int tiles = a.g.P / kTile;
-    if (tiles > 0) nps_store_kernel<<<tiles, kTile, 0, s>>>(a.x, Cout, a.g.P, a.g.n_f);
+    if (tiles > 0) nps_store_kernel<<<tiles, kTile, 0, s>>>(a.x, Cout, Clo, a.g.P, a.g.n_f);
     return hipGetLastError();
 }
 

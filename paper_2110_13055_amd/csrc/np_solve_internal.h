@@ -46,7 +46,7 @@ hipError_t launch_nps_iter(int dim, const NpsArgs &a, int G, int k, hipStream_t 
 // The stop test before iteration k (one workgroup).
 hipError_t launch_nps_check(const NpsArgs &a, int G, int k, hipStream_t s);
 // C_out = (float) x for the fluid nodes.
-hipError_t launch_nps_store(const NpsArgs &a, float *Cout, hipStream_t s);
+hipError_t launch_nps_store(const NpsArgs &a, float *Cout, __half2 *Clo, hipStream_t s);
 // Rates of adsorption, inflow and outflow of the concentrations C (FP64 per
 // tile), times scale, added to acc (scale = dt of an implicit step) or
 // written to part and reduced into out[0..5] (out != nullptr).

@@ -9,8 +9,9 @@
 // node and its face neighbours, while the LBM part writes the flux of this
 // step. Face fluxes are Scharfetter-Gummel; the two sides of a face compute
 // exactly opposite values, so solute is conserved to the rounding of the
-// update. Per tile, the adsorbed / inflow / outflow amounts are reduced in
-// FP64 in a fixed order and added to that tile's own accumulator slot.
+// update. Per tile, the adsorbed / inflow / outflow amounts of the step are
+// summed over each wave's 64 nodes in FP32, then over the tile's waves in
+// FP64, in a fixed order, and added to that tile's own FP64 accumulator slot.
 //
 // Inlet/outlet planes (x = 0 and x = nx - 1): the node one plane inside owns
 // the post-streaming populations the extrapolation needs, so its thread also
@@ -24,12 +25,14 @@ namespace {
 // Moments, residual terms, collision and the AA store of one node whose
 // incoming populations (minus w_i) are f; NP: also store the mass flux j for
 // the ions of the next step (FP32; the other storages carry it in Mout).
+// FP32 storage: f_i - w_i (1 + pr.rout) on entry, and values stored relative
+// to the plane references of pr (see PlaneRef); the other storages pass zeros.
 template <class L, int ST, int ODD, int NP>
 __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, const Bufs &b, int P, int n, const int *nb,
-                                const float (&f)[L::Q], double (&res)[2])
+                                const float (&f)[L::Q], const PlaneRef &pr, double (&res)[2])
 {
     constexpr int Q = L::Q, D = L::D;
-    float drho = 0, jx = 0, jy = 0, jz = 0;
+    float drho = 0, jx = 0, jy = 0, jz = 0;  // drho: rho - 1 - pr.rout
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         drho += f[i];
@@ -42,40 +45,52 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
         jy += 0.5f * p.F[1];
         jz += 0.5f * p.F[2];
     }
-    const float rinv = 1.f / (1.f + drho);
+    const float rho = 1.f + pr.rout + drho;
+    const float rinv = __builtin_amdgcn_rcpf(rho);
     const float ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
     if (b.flags & kResid) {
         float px, py, pz;
-        if (ST != kF32) {
+        if (!kPlain<ST>) {
             const float4 m = ldu(b.Min, (uint32_t)n);
             px = m.y;
             py = m.z;
             pz = m.w;
         } else {
-            px = b.ubuf[n];
-            py = b.ubuf[P + n];
-            pz = D == 3 ? b.ubuf[2 * P + n] : 0.f;
+            px = ldu(b.ubuf, (uint32_t)n);
+            py = ldu(b.ubuf + P, (uint32_t)n);
+            pz = D == 3 ? ldu(b.ubuf + 2 * (size_t)P, (uint32_t)n) : 0.f;
         }
         const double dx = (double)ux - px, dy = (double)uy - py, dz = (double)uz - pz;
         res[0] += dx * dx + dy * dy + dz * dz;
         res[1] += (double)ux * ux + (double)uy * uy + (double)uz * uz;
     }
-    if (ST == kF32 && (b.flags & kStoreU)) {
-        b.ubuf[n] = ux;
-        b.ubuf[P + n] = uy;
-        if (D == 3) b.ubuf[2 * P + n] = uz;
+    if (kPlain<ST> && (b.flags & kStoreU)) {
+        stu(b.ubuf, (uint32_t)n, ux);
+        stu(b.ubuf + P, (uint32_t)n, uy);
+        if (D == 3) stu(b.ubuf + 2 * (size_t)P, (uint32_t)n, uz);
+        stu(b.ubuf + (size_t)D * P, (uint32_t)n, pr.rout + drho);  // rho - 1, for the plane references
     }
-    if (ST != kF32) stu(b.Mout, (uint32_t)n, make_float4(drho, ux, uy, uz));
-    if (NP && ST == kF32) {
-        b.jout[n] = jx;
-        b.jout[P + n] = jy;
-        if (D == 3) b.jout[2 * P + n] = jz;
+    if (!kPlain<ST>) stu(b.Mout, (uint32_t)n, make_float4(drho, ux, uy, uz));
+    if (NP && kPlain<ST>) {
+        stu(b.jout, (uint32_t)n, jx);
+        stu(b.jout + P, (uint32_t)n, jy);
+        if (D == 3) stu(b.jout + 2 * (size_t)P, (uint32_t)n, jz);
     }
     if (ST == kMom) return;  // the post-collision state is the equilibrium of Mout
     const float om = p.omega;
+    // FP16 populations are stored times hs
+    const float sc = ST == kH16 ? p.hs : 1.f;
+    if (kPlain<ST> && om == 1.f && !p.forced) {
+        // tau = 1: BGK (Eq. 8) relaxes every population to the equilibrium
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            scatter<L, ST, ODD>(ODD == kPull ? b.f2 : b.f, P, nb, n, i,
+                                sc * stored_pop<L, ODD>(feq_rel<L>(i, drho, rho, ux, uy, uz, p.linear_eq), i, nb, pr));
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const float fe = feq_bar<L>(i, drho, ux, uy, uz, p.linear_eq);
+        const float fe = feq_rel<L>(i, drho, rho, ux, uy, uz, p.linear_eq);
         float src = 0.f;
         if (p.forced) {  // Guo, Zheng & Shi (2002) source term
             const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
@@ -88,7 +103,7 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
         if (ST == kF16)
             out = ((1.f - om) * (f[i] - fe) + src) * p.hs;
         else
-            out = f[i] - om * (f[i] - fe) + src;
+            out = sc * stored_pop<L, ODD>(f[i] - om * (f[i] - fe) + src, i, nb, pr);
         scatter<L, ST, ODD>(ODD == kPull ? b.f2 : b.f, P, nb, n, i, out);
     }
 }
@@ -102,7 +117,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     const int n = tile * kTile + threadIdx.x;
     const bool active = n < g.n_f;
     const int P = g.P;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     double res[2] = {0, 0};
 
     // coordinates and neighbour map values of the node
@@ -111,7 +126,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     bool edge = false;
     if (active) {
         unpack_xyz(g, ldu(g.fluid, (uint32_t)n), x, y, z);
-        constexpr bool need_all = LBM && (ODD || ST != kF32);
+        constexpr bool need_all = LBM && (ODD || !kPlain<ST>);
         edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
         nb[0] = n;
         // the list, when the instance has one, for the steps that carry the ions
@@ -120,7 +135,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         // without it, and flow-only steps stream their populations at the copy
         // rate already and only pay for the list's bytes (+10 %): those two
         // look their neighbours up
-        constexpr bool kList = NP && !(LBM && ST == kF32);
+        constexpr bool kList = NP && !(LBM && kPlain<ST>);
         if (kList && g.nbr) {  // precomputed: independent of the coordinates
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
@@ -152,7 +167,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     // a divergent branch would wait for its data before the next face starts
     // (its flux is always the stored one): -27 % per ion-only step.
     constexpr bool kEarly = NP;
-    constexpr bool kEarlyJ = kEarly && (ST == kF32 || !LBM);
+    constexpr bool kEarlyJ = kEarly && (kPlain<ST> || !LBM);
     // with a potential field, the neighbours' potential too, where the flux
     // is loaded early (ion-only step 1.18 -> 0.96 ms, FP32 fused 3.50 ->
     // 3.27 ms on the 512^3 electrode, same waves per SIMD); not in the
@@ -161,22 +176,24 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     // SIMD, which costs the served requests, all in the ramp, 10 %)
     constexpr bool kEarlyPsi = kEarlyJ && !BATCH;
     float ec[2] = {0.f, 0.f}, ej[3] = {0.f, 0.f, 0.f};
+    __half2 elo = __floats2half2_rn(0.f, 0.f);
     float ecn[2 * D][2], ejn[2 * D], epsi[2 * D];
     if (kEarly && active) {
-        ec[0] = b.Cin[n];
-        ec[1] = b.Cin[P + n];
+        ec[0] = ldu(b.Cin, (uint32_t)n);
+        ec[1] = ldu(b.Cin + P, (uint32_t)n);
+        elo = ldu(b.Clin, (uint32_t)n);
         if (kEarlyJ) {
-            ej[0] = b.jin[n];
-            ej[1] = b.jin[P + n];
-            ej[2] = D == 3 ? b.jin[2 * P + n] : 0.f;
+            ej[0] = ldu(b.jin, (uint32_t)n);
+            ej[1] = ldu(b.jin + P, (uint32_t)n);
+            ej[2] = D == 3 ? ldu(b.jin + 2 * (size_t)P, (uint32_t)n) : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < 2 * D; ++k) {
             const int m = nb[k + 1];
             const bool fl = m >= 0;
-            ecn[k][0] = fl ? b.Cin[m] : 0.f;
-            ecn[k][1] = fl ? b.Cin[P + m] : 0.f;
-            ejn[k] = (fl && kEarlyJ) ? b.jin[(k >> 1) * P + m] : 0.f;
+            ecn[k][0] = fl ? ldu(b.Cin, (uint32_t)m) : 0.f;
+            ecn[k][1] = fl ? ldu(b.Cin + P, (uint32_t)m) : 0.f;
+            ejn[k] = (fl && kEarlyJ) ? ldu(b.jin + (size_t)(k >> 1) * P, (uint32_t)m) : 0.f;
             epsi[k] = (kEarlyPsi && p.psi) ? ldu(p.psi, (uint32_t)(fl ? m : n)) : 0.f;
         }
     }
@@ -187,13 +204,14 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     // the flow's incoming populations (the collision follows the ions)
     float f[Q];
     bool do_flow = false;
+    PlaneRef pr{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // FP32: the node's plane references
     {
         if (LBM && active) {
             // a boundary node with a fluid interior neighbour is advanced by that neighbour
             const bool by_partner = edge && ((x == 0 && nb[1] >= 0) || (x == g.nx - 1 && nb[2] >= 0));
             if (!by_partner) {
                 do_flow = true;
-                if (ST != kF32 && NP) {
+                if (!kPlain<ST> && NP) {
 #pragma unroll
                     for (int k = 0; k < 2 * D; ++k)
                         mface[k] = nb[k + 1] >= 0 ? ldu(b.Min, (uint32_t)nb[k + 1]) : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -233,7 +251,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                             f[i] = from_emitter<L, ST>(gather_raw<L, ST, ODD>(b.f, P, nb, n, i), i, fl, mg[u], p);
                         }
                     }
-                } else if (ST != kF32) {
+                } else if (!kPlain<ST>) {
                     // flow only: all emitters' moments loaded first, then used
                     // (moments 1.73 -> 1.27 ms, FP16 3.08 -> 2.53 ms per flow
                     // step; groups of 6: 1.34 / 2.64)
@@ -259,8 +277,9 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                         }
                     }
                 } else {
+                    pr = plane_ref<ODD>(g, b.rin, b.rout, x);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) f[i] = gather<L, ST, ODD>(b.f, P, nb, n, i, b.Min, p);
+                    for (int i = 0; i < Q; ++i) f[i] = rel_pop<L, ODD>(gather<L, ST, ODD>(b.f, P, nb, n, i, b.Min, p), i, nb, pr);
                 }
             }
         }
@@ -269,9 +288,9 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     // the ions: face fluxes of the explicit finite-volume update
     {
         if (NP && active) {
-            const float cP[2] = {kEarly ? ec[0] : b.Cin[n], kEarly ? ec[1] : b.Cin[P + n]};
+            const float cP[2] = {ec[0], ec[1]};
             float jP[3];
-            const bool jm = ST != kF32 && (b.flags & kJFromM);
+            const bool jm = !kPlain<ST> && (b.flags & kJFromM);
             if (jm) {
                 const float4 m = have_m ? mown : ldu(b.Min, (uint32_t)n);
                 const float r = 1.f + m.x;
@@ -283,9 +302,9 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 jP[1] = ej[1];
                 jP[2] = ej[2];
             } else {
-                jP[0] = b.jin[n];
-                jP[1] = b.jin[P + n];
-                jP[2] = D == 3 ? b.jin[2 * P + n] : 0.f;
+                jP[0] = ldu(b.jin, (uint32_t)n);
+                jP[1] = ldu(b.jin + P, (uint32_t)n);
+                jP[2] = D == 3 ? ldu(b.jin + 2 * (size_t)P, (uint32_t)n) : 0.f;
             }
             const float psiP = p.psi ? ldu(p.psi, (uint32_t)n) : 0.f;
             // per species: 2/D, and (z D)/2 so that half the drift is hw = u/2 - (z D/2) dpsi
@@ -343,7 +362,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                         const float4 mm = (have_m && !xb) ? mface[k] : ldu(b.Min, (uint32_t)m);
                         jN = (1.f + mm.x) * (axis == 0 ? mm.y : (axis == 1 ? mm.z : mm.w));
                     } else {
-                        jN = (early && kEarlyJ) ? ejn[k] : b.jin[axis * P + m];
+                        jN = (early && kEarlyJ) ? ejn[k] : ldu(b.jin + (size_t)axis * P, (uint32_t)m);
                     }
                     // half the face-normal drift: advection by the mean flux of the
                     // two cells, migration down the potential difference
@@ -354,25 +373,29 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
                         const float hw = mig ? hun - hzD[s] * dpsi : hun;
-                        out[s] += sg_flux(p.D[s], invD2[s], hw, cP[s], early ? ecn[k][s] : b.Cin[s * P + m]);
+                        out[s] += sg_flux(p.D[s], invD2[s], hw, cP[s],
+                                          early ? ecn[k][s] : ldu(b.Cin + (size_t)s * P, (uint32_t)m));
                     }
                 }
                 // inert wall: no flux
             }
-            b.Cout[n] = cP[0] - p.dt * out[0];
-            b.Cout[P + n] = cP[1] - p.dt * out[1];
-            acc[0] = (double)p.dt * fa[0];
-            acc[1] = (double)p.dt * fa[1];
-            acc[2] = (double)p.dt * fi[0];
-            acc[3] = (double)p.dt * fi[1];
-            acc[4] = (double)p.dt * fo[0];
-            acc[5] = (double)p.dt * fo[1];
+            // forward Euler into value + remainder (see lo_encode)
+            float e0, e1;
+            stu(b.Cout, (uint32_t)n, two_sum(cP[0], lo_decode(__low2half(elo)) - p.dt * out[0], e0));
+            stu(b.Cout + P, (uint32_t)n, two_sum(cP[1], lo_decode(__high2half(elo)) - p.dt * out[1], e1));
+            stu(b.Clout, (uint32_t)n, __halves2half2(lo_encode(e0), lo_encode(e1)));
+            acc[0] = p.dt * fa[0];
+            acc[1] = p.dt * fa[1];
+            acc[2] = p.dt * fi[0];
+            acc[3] = p.dt * fi[1];
+            acc[4] = p.dt * fo[0];
+            acc[5] = p.dt * fo[1];
         }
     }
 
     // the flow: collide and stream (and the residual terms on request)
     if (LBM && do_flow) {
-        lbm_node<L, ST, ODD, NP>(p, b, P, n, nb, f, res);
+        lbm_node<L, ST, ODD, NP>(p, b, P, n, nb, f, pr, res);
         const bool inl = edge && x == 1 && nb[2] >= 0;
         const bool outl = edge && x == g.nx - 2 && nb[1] >= 0;
         if (inl || outl) {
@@ -383,8 +406,10 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
 #pragma unroll
             for (int i = 1; i < Q; ++i) nbb[i] = nb_map<L>(g, xb, y, z, i, false);  // rare path
             float fb[Q];
-            nee_populations<L>(p, inl, f, fb);
-            lbm_node<L, ST, ODD, NP>(p, b, P, bn, nbb, fb, res);
+            PlaneRef pb{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+            if (kPlain<ST>) pb = plane_ref<ODD>(g, b.rin, b.rout, xb);
+            nee_populations<L>(p, inl, f, fb, pr.rout, pb.rout);
+            lbm_node<L, ST, ODD, NP>(p, b, P, bn, nbb, fb, pb, res);
         }
     }
     if (LBM && (b.flags & kResid)) {
@@ -397,16 +422,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         __syncthreads();
     }
 
-    if (NP) {
-        double s[6];
-        block_sum<6>(acc, sm, s);
-        if (threadIdx.x == 0) {
-            double *a = b.acc + (size_t)tile * 8;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) a[k] += s[k];
-        }
-        __syncthreads();
-    }
+    if (NP) tile_accumulate<6>(acc, sm, b.acc + (size_t)tile * 8);
 }
 
 template <class L, int ST, int ODD, int LBM, int NP>
@@ -493,6 +509,13 @@ void launch_prec(int st, int odd, int lbm, int np, const Grid &g, const Phys &p,
 {
     if (st == kMom) {
         launch_mode<L, kMom, 0>(lbm, np, g, p, b, s);
+    } else if (st == kH16) {
+        if (odd == kPull)
+            launch_mode<L, kH16, kPull>(lbm, np, g, p, b, s);
+        else if (odd)
+            launch_mode<L, kH16, 1>(lbm, np, g, p, b, s);
+        else
+            launch_mode<L, kH16, 0>(lbm, np, g, p, b, s);
     } else if (st == kF16) {
         if (odd == kPull)
             launch_mode<L, kF16, kPull>(lbm, np, g, p, b, s);
@@ -516,6 +539,8 @@ void launch_batch_l(int st, int cls, const BatchInst *inst, const int2 *tiles, i
 {
     if (st == kMom)
         launch_batch_t<L, kMom>(cls, inst, tiles, ntiles, wg, pad, s);
+    else if (st == kH16)
+        launch_batch_t<L, kH16>(cls, inst, tiles, ntiles, wg, pad, s);
     else if (st == kF16)
         launch_batch_t<L, kF16>(cls, inst, tiles, ntiles, wg, pad, s);
     else
@@ -528,7 +553,7 @@ hipError_t launch_batch(int dim, int st, int cls, const BatchInst *inst, const i
                         int workgroups, int lds_pad, hipStream_t s)
 {
     if (ntiles <= 0 || workgroups <= 0) return hipSuccess;
-    if (cls < 0 || cls >= kClasses || st < kF32 || st > kMom) return hipErrorInvalidValue;
+    if (cls < 0 || cls >= kClasses || st < kF32 || st > kH16) return hipErrorInvalidValue;
     if (dim == 2)
         launch_batch_l<D2Q9>(st, cls, inst, tiles, ntiles, workgroups, lds_pad, s);
     else
@@ -540,7 +565,7 @@ hipError_t launch_step(int dim, int st, int odd, int lbm, int np, const Grid &g,
                        const Bufs &b, hipStream_t s)
 {
     if (g.P <= 0) return hipSuccess;
-    if (st < kF32 || st > kMom) return hipErrorInvalidValue;
+    if (st < kF32 || st > kH16) return hipErrorInvalidValue;
     if (dim == 2)
         launch_prec<D2Q9>(st, odd, lbm, np, g, p, b, s);
     else

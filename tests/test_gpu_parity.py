@@ -118,28 +118,50 @@ def test_flow_to_steady_residual_sequence_matches_oracle():
         assert abs(r - ro) <= 1e-3 * ro
 
 
-def test_flow_to_steady_fp32_steady_state_then_5k_ion_steps():
+_CFG0 = {}
+
+
+def _cfg0_oracle():
+    """The FP64 oracle's steady flow of the 2D channel (residual <= 1e-8), then
+    its 5000 ion steps on the frozen flow; computed once per session."""
+    if not _CFG0:
+        g, p, _ = preset("channel2d_128x64")
+        o = oracle_solver(g, p)
+        rco, stepso, ro = o.flow_to_steady(tol=1e-8, max_steps=400000, check_every=100)
+        assert rco == 0
+        _CFG0["u"] = o.velocity()
+        o.freeze_velocity()
+        assert o.np_steps(5000) == 0
+        _CFG0["c"] = o.conc()
+        _CFG0["a"] = o.adsorbed_total()
+        _CFG0["steps"], _CFG0["r"] = stepso, ro
+    return _CFG0
+
+
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL])
+def test_flow_to_steady_fp32_steady_state_then_5k_ion_steps(streaming):
     # The 2D channel's whole protocol: flow to a residual of 1e-8, then 5000
-    # ion steps on the frozen flow. FP32 storage of f - w_i resolves velocity
-    # changes down to about ulp(w_i * |rho - 1|) / |u|; below that the
-    # residual stops falling and the call reports STAGNATED with the reached
-    # residual. The state it reaches is compared with the FP64 steady state at
-    # r <= 1e-8, and the ions after 5000 steps on each with the parity bars.
-    g, p, _ = preset("channel2d_128x64")
+    # ion steps on the frozen flow, against the FP64 oracle at the north-star
+    # bars (velocity 1e-5, C 1e-4, adsorbed 1e-4). FP32 storage keeps the
+    # populations relative to a per-plane reference density renewed at every
+    # residual check, so the residual falls far below the floor of plain
+    # f - w_i storage (near 3e-6 on this channel, whose density drops by 0.028
+    # from inlet to outlet); if it stops falling first the call reports
+    # STAGNATED with the reached residual.
+    ref = _cfg0_oracle()
+    g, p, _ = preset("channel2d_128x64", streaming=streaming)
     s = Solver(g, p)
     rc, steps, r = s.flow_to_steady(tol=1e-8, max_steps=400000, check_every=100)
-    o = oracle_solver(g, p)
-    rco, stepso, ro = o.flow_to_steady(tol=1e-8, max_steps=400000, check_every=100)
-    err = rel_l2(s.velocity(), o.velocity())
-    print(f"GPU rc={rc} steps={steps} r={r:.3e}; oracle steps={stepso} r={ro:.3e}; u relL2={err:.3e}")
-    assert rco == 0
+    err = rel_l2(s.velocity(), ref["u"])
+    print(f"GPU rc={rc} steps={steps} r={r:.3e}; oracle steps={ref['steps']} r={ref['r']:.3e}; u relL2={err:.3e}")
     assert rc in (L.OK, L.STAGNATED)
-    assert err <= 1e-4
-    o.freeze_velocity()
+    assert err <= 1e-5
     s.np_step(5000)
-    assert o.np_steps(5000) == 0
-    assert np.abs(o.conc() - 1.0).max() > 0.1
-    _check_np(s, o)
+    c = s.concentration()
+    assert np.abs(ref["c"] - 1.0).max() > 0.1
+    assert np.abs(c - ref["c"]).max() <= 1e-4
+    a = s.adsorbed_total()
+    assert np.all(np.abs(a - ref["a"]) <= 1e-4 * np.abs(ref["a"]))
 
 
 # ------------------------------------------------------------------ Nernst-Planck
