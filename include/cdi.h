@@ -397,6 +397,17 @@ int cdi_potential_bytes(const cdi_solver *s, uint64_t *bytes);
 int cdi_solve_potential(cdi_solver *s, const cdi_potential *pot, void *ws, uint64_t ws_bytes,
                         cdi_potential_result *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture aside, tight serving loops, harnesses that forbid hipMalloc):
+ * cdi_solve_potential with the library's own scratch instead of a caller
+ * workspace: a 64 MiB device array per GPU, held until the process ends, so
+ * lattices whose cdi_potential_bytes exceeds 64 MiB (about a million fluid
+ * nodes) are refused with CDI_E_BUFFER. The call allocates nothing. Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (two
+ * host threads, or solvers on different streams) race; serialise them.
+ * Same results as cdi_solve_potential, statuses as there. */
+int cdi_solve_potential_noalloc(cdi_solver *s, const cdi_potential *pot, cdi_potential_result *out);
+
 /* Coupled Poisson-Nernst-Planck: nsteps ion steps (fused_flow as in
  * cdi_np_step), with the potential solved afresh from the concentrations
  * before every `every`-th step (explicit, lagged coupling; the positivity

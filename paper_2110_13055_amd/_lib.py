@@ -126,6 +126,7 @@ SIGNATURES = {
     "cdi_batch_autotune": (C.c_int, [P, I32, P, P, P]),
     "cdi_potential_bytes": (C.c_int, [P, P]),
     "cdi_solve_potential": (C.c_int, [P, P, P, U64, P]),
+    "cdi_solve_potential_noalloc": (C.c_int, [P, P, P]),
     "cdi_np_step_coupled": (C.c_int, [P, I64, I32, P, I32, P, U64]),
     "cdi_copy_potential": (C.c_int, [P, P]),
     "cdi_np_solve_bytes": (C.c_int, [P, P]),

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 using namespace cdi;
@@ -316,6 +317,7 @@ struct cdi_solver {
     int mb;  // moment buffers in use (kF16, kMom): j of a fused step lives in them
     int64_t nvox, nf;
     int P, ntiles;
+    int device;  // the device current at initialisation (its buffers live there)
     hipStream_t stream;
     VoxLayout vox;
     NodeLayout node;
@@ -759,6 +761,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     s->P = (int)P;
     s->ntiles = (int)(P / kTile);
     s->stream = (hipStream_t)stream;
+    if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
     s->vox = V;
     s->node = N;
     s->porosity = (double)n_fluid / (double)nvox;
@@ -1229,6 +1232,63 @@ int cdi_solve_potential(cdi_solver *s, const cdi_potential *pot, void *ws, uint6
 {
     if (!s) return fail(CDI_E_INVALID, "NULL solver");
     return solve_potential(s, pot, ws, ws_bytes, out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- a solve without a caller workspace
+
+// The workspace of cdi_solve_potential_noalloc: a file-scope device array,
+// one copy per GPU the library runs on, held until the process ends. Host
+// code never passes the array's name to a kernel or a copy (on the host it
+// is a stand-in, not a device address): it looks up each device's address
+// once, with that device current, and uses that.
+static constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (looked up on first use).
+int scratch_on(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(CDI_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess || !ptr)
+            return fail(CDI_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdi_solve_potential_noalloc(cdi_solver *s, const cdi_potential *pot, cdi_potential_result *out)
+{
+    if (!s) return fail(CDI_E_INVALID, "NULL solver");
+    const uint64_t need = pot_layout(nullptr, s->P).bytes;
+    if (need > kNoAllocScratchBytes)
+        return fail(CDI_E_BUFFER, "potential solve needs %llu bytes of scratch, the library's holds %llu "
+                                  "(use cdi_solve_potential with a workspace)",
+                    (unsigned long long)need, (unsigned long long)kNoAllocScratchBytes);
+    void *ws = nullptr;
+    int rc = scratch_on(s->device, &ws);
+    if (rc) return rc;
+    // the solve initialises every workspace value it reads (setup kernel)
+    return solve_potential(s, pot, ws, kNoAllocScratchBytes, out);
 }
 
 int cdi_np_step_coupled(cdi_solver *s, int64_t nsteps, int32_t fused_flow, const cdi_potential *pot,

@@ -284,6 +284,16 @@ class Solver:
         L.check(rc, "cdi_solve_potential", (L.OK, L.E_NOT_CONVERGED) if allow_not_converged else (L.OK,))
         return out.iterations, out.residual
 
+    def solve_potential_noalloc(self, pot: "Potential", allow_not_converged: bool = False):
+        """solve_potential without a workspace: the library's own scratch
+        (cdi_solve_potential_noalloc; lattices up to its 64 MiB)."""
+        c, out = pot.to_c(), L.CPotentialResult()
+        rc = self.lib.cdi_solve_potential_noalloc(self.h, C.byref(c), C.byref(out))
+        self.potential_stats = dict(iterations=out.iterations, residual=out.residual,
+                                    fp32_rounds=out.fp32_rounds, fp64_iterations=out.fp64_iterations)
+        L.check(rc, "cdi_solve_potential_noalloc", (L.OK, L.E_NOT_CONVERGED) if allow_not_converged else (L.OK,))
+        return out.iterations, out.residual
+
     def np_step_coupled(self, n: int, pot: "Potential", every: int = 1, fused: bool = False):
         """n ion steps with the potential re-solved every `every` steps."""
         ws = self._pot_ws()
