@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -45,6 +46,14 @@ BYTES_FUSED = {"fp32": 19 * 4 * 2 + BYTES_C + 24, "fp16": 19 * 2 * 2 + BYTES_C +
                "fp16_dev": 19 * 2 * 2 + BYTES_C + 32, "moments": BYTES_C + 32}
 BYTES_LBM = {"fp32": 19 * 4 * 2, "fp16": 19 * 2 * 2, "fp16_dev": 19 * 2 * 2 + 32, "moments": 32}
 BYTES_NP = BYTES_C + 12  # C and remainders read + write, frozen j read
+
+
+_T0 = time.perf_counter()
+
+
+def log(msg: str) -> None:
+    """Progress on stderr (stdout carries only the JSON record)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(kind: str):
@@ -235,26 +244,104 @@ def batched_rates(steps: int, streaming: int, n: int = 64):
     return out
 
 
-def serving_run(n_requests: int, precision: int, slots: int, streaming: int):
+def small_batch_rates(steps: int, streaming: int, n: int = 64, flow_steps: int = 2000, ion_steps: int = 1000):
+    """Batching where one instance leaves the GPU idle: n small electrodes
+    (cubes of edge 48-64, the cfg3 parameter ranges otherwise), FP32. Fused
+    step rate batched vs each instance stepped alone; and whole solves of a
+    fixed protocol (flow_steps flow steps, then ion_steps ion steps on the
+    frozen flow) batched vs the n solves one after the other."""
+    import torch
+    import paper_2110_13055_amd as P
+    specs = P.batch_instances(n, precision=P.FP32, streaming=streaming, edge_range=(48, 64))
+    out = {"instances": n, "edge_range": [48, 64]}
+    solvers = [P.Solver(g, p) for g, p in specs]
+    nf = sum(s.n_fluid for s in solvers)
+    out["n_fluid_total"] = nf
+    for s in solvers:
+        s.flow_steps(2)
+    b = P.Batch(solvers)
+    b.advance(2, [P.MODE_FUSED] * n)
+    t = time_region(lambda: b.advance(steps, [P.MODE_FUSED] * n), b.stream)
+    out["fused_batched_mlups"] = round(nf * steps / t / 1e6, 1)
+
+    def seq():
+        for s in solvers:
+            s.np_step(steps, fused=True)
+    t = time_region(seq, solvers[0].stream)
+    out["fused_sequential_mlups"] = round(nf * steps / t / 1e6, 1)
+    out["fused_batched_vs_sequential"] = round(out["fused_batched_mlups"] / out["fused_sequential_mlups"], 3)
+    b.close()
+    del solvers
+    torch.cuda.empty_cache()
+    # whole solves: fresh instances each way
+    solvers = [P.Solver(g, p) for g, p in specs]
+    b = P.Batch(solvers)
+
+    def batched_solves():
+        b.advance(flow_steps, [P.MODE_FLOW] * n)
+        b.advance(ion_steps, [P.MODE_IONS] * n)
+    tb = time_region(batched_solves, b.stream)
+    b.close()
+    del solvers
+    solvers = [P.Solver(g, p) for g, p in specs]
+
+    def sequential_solves():
+        for s in solvers:
+            s.flow_steps(flow_steps)
+            s.np_step(ion_steps, fused=False)
+    ts = time_region(sequential_solves, solvers[0].stream)
+    out["solve_protocol"] = f"{flow_steps} flow + {ion_steps} ion steps per instance"
+    out["solves_batched_s"] = round(tb, 3)
+    out["solves_sequential_s"] = round(ts, 3)
+    out["solves_batched_vs_sequential"] = round(ts / tb, 3)
+    del solvers
+    torch.cuda.empty_cache()
+    return out
+
+
+# Slots of the continuous-batching server: enough concurrent requests to fill
+# the GPU with the small ones (a 2D 256^2 request or a 64^3 cube alone leaves
+# most compute units idle) without sharing it among so many that none finish
+# (with 64 slots every admitted request advanced at 1/64 of the rate).
+SERVE_SLOTS = 16
+# Fluid nodes stepped together at most. One 3D request of 2-4 million fluid
+# nodes already keeps the FP32 step at its full node rate; admitting more
+# beyond that only time-slices the GPU among them and delays every one.
+SERVE_ACTIVE_NODES = 4_000_000
+
+
+def serving_run(n_requests: int, precision: int, slots: int, streaming: int, horizon_s: float,
+                max_active_nodes: float = math.inf):
     """Serve a fixed Poisson trace (2 requests/s, half 2D 256^2, half 3D
-    64^3-192^3) with a 200 GB admission budget and the given slot count."""
+    64^3-192^3) with a 200 GB admission budget and the given slot count, up to
+    horizon_s seconds; what is left then is the backlog."""
     import torch
     import paper_2110_13055_amd as P
     from paper_2110_13055_amd.serving import GpuExecutor, Server, latency_stats
     reqs = P.serving_requests(n_requests, precision=precision, streaming=streaming)
     ex = GpuExecutor()
-    srv = Server(ex, budget_bytes=200e9, max_slots=slots, round_steps=500)
+    srv = Server(ex, budget_bytes=200e9, max_slots=slots, round_steps=250,
+                 max_active_nodes=max_active_nodes)
+    node_steps = [0]
+    advance = ex.advance
+
+    def counted(groups, modes, nsteps):
+        node_steps[0] += nsteps * sum(h.n_fluid for hs in groups.values() for h in hs)
+        return advance(groups, modes, nsteps)
+    ex.advance = counted
     t0 = time.perf_counter()
-    res = srv.run(reqs)
+    res = srv.run(reqs, horizon_s=horizon_s, progress=lambda m: log(f"serving: {m}"))
     wall = time.perf_counter() - t0
     ex.close()
     torch.cuda.empty_cache()
     st = latency_stats(res, wall)
     st = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
-    st.update(failures=[f"{r.rid}: {r.status}" for r in res if r.status != "ok"])
+    st.update(failures=[f"{r.rid}: {r.status[:60]}" for r in res if r.status.startswith("failed")],
+              rejected_ids=[r.rid for r in res if r.status.startswith("rejected")])
     st.update(wall_s=round(wall, 2), backlog=srv.backlog, peak_slots=srv.peak_slots,
               peak_gb=round(srv.peak_bytes / 1e9, 2), rounds=srv.rounds,
-              flow_steps=sum(r.flow_steps for r in res), np_steps=sum(r.np_steps for r in res))
+              flow_steps=sum(r.flow_steps for r in res), np_steps=sum(r.np_steps for r in res),
+              node_steps_g=round(node_steps[0] / 1e9, 2), mlups=round(node_steps[0] / wall / 1e6, 1))
     return st
 
 
@@ -305,8 +392,10 @@ def main():
     ap.add_argument("--no-potential", action="store_true", help="skip the potential-solve leg")
     ap.add_argument("--potential-only", action="store_true",
                     help="run only the potential-solve leg and print its record (for profiling)")
-    ap.add_argument("--serve-requests", type=int, default=12,
+    ap.add_argument("--serve-requests", type=int, default=120,
                     help="requests in the serving trace (0 skips the serving leg)")
+    ap.add_argument("--serve-horizon", type=float, default=50.0,
+                    help="seconds each serving run lasts (the rest is reported as backlog)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the probe's copy kernel over this size (a kernel of known "
                          "traffic, to calibrate HBM byte counters under a profiler)")
@@ -332,9 +421,13 @@ def main():
         print(json.dumps({"workload": WORKLOAD, "potential": potential_rates()}), flush=True)
         return
     strm = P.STREAM_PULL if args.streaming == "pull" else P.STREAM_AA
+    log("fused / flow / ion steps, FP32")
     r32 = gpu_rates(P.FP32, args.steps, args.warmup, strm)
+    log("FP16 populations")
     rh16 = gpu_rates(P.FP16, args.steps, args.warmup, strm)
+    log("FP16 deviations")
     r16 = gpu_rates(P.FP16_DEV, args.steps, args.warmup, strm)
+    log("moments")
     rmo = gpu_rates(P.MOMENTS, args.steps, args.warmup, strm)
     nf = r32["n_fluid"]
     K = args.steps
@@ -381,19 +474,33 @@ def main():
         "device": torch.cuda.get_device_name(0),
     }
     if not args.no_probe:
+        log("bandwidth probe")
         out["hbm_probe"] = hbm_probe()
     if not args.no_potential:
+        log("potential")
         out["potential"] = potential_rates()
     if not args.no_batch:
+        log("batched, 64 cubes of edge 48-160")
         out["batched"] = batched_rates(K, strm)
+        log("batched, 64 cubes of edge 48-64")
+        out["batched_small"] = small_batch_rates(K, strm)
     if args.serve_requests > 0:
-        sv = {"requests": args.serve_requests, "rate_hz": 2.0, "budget_gb": 200}
-        sv["continuous_batching_moments"] = serving_run(args.serve_requests, P.MOMENTS, 64, strm)
-        sv["continuous_batching_fp32"] = serving_run(args.serve_requests, P.FP32, 64, strm)
-        sv["plain_fp32_one_at_a_time"] = serving_run(args.serve_requests, P.FP32, 1, strm)
+        H = args.serve_horizon
+        sv = {"requests": args.serve_requests, "rate_hz": 2.0, "budget_gb": 200, "horizon_s": H,
+              "slots": SERVE_SLOTS, "max_active_nodes": SERVE_ACTIVE_NODES}
+        log("serving: continuous batching, moments")
+        sv["continuous_batching_moments"] = serving_run(args.serve_requests, P.MOMENTS, SERVE_SLOTS, strm, H,
+                                                         SERVE_ACTIVE_NODES)
+        log("serving: continuous batching, FP32")
+        sv["continuous_batching_fp32"] = serving_run(args.serve_requests, P.FP32, SERVE_SLOTS, strm, H,
+                                                      SERVE_ACTIVE_NODES)
+        log("serving: FP32 one at a time")
+        sv["plain_fp32_one_at_a_time"] = serving_run(args.serve_requests, P.FP32, 1, strm, H)
         out["serving"] = sv
     if not args.no_cpu:
+        log("CPU baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline()
+    log("done")
     print(json.dumps(out), flush=True)
 
 

@@ -188,6 +188,18 @@ typedef struct {
  * disk generator jams. */
 int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *out);
 
+/* Host only, no device work: admission check of an inlet/outlet flow. The
+ * lattice Boltzmann method is weakly compressible: the pressure drop that
+ * drives the flow through the electrode is carried by density differences,
+ * which must stay well below the rest density. Estimates the steady density
+ * drop by Darcy's law over the electrode's length (nx - 2 buffer_x) with
+ * the Kozeny-Carman permeability phi^3 / (5 s^2), s the fluid-solid surface
+ * per volume (from the primitives' statistics, or counted on user labels),
+ * drho = 3 nu u_in L / k; zero for the body-force drive. *drho_estimate
+ * (nullable) receives it. Returns UNSTABLE when it exceeds max_drho (<= 0:
+ * 0.5), else OK. */
+int cdi_flow_check(const cdi_geometry *geom, const cdi_params *params, double max_drho, double *drho_estimate);
+
 /* Voxelise the primitives and number the fluid voxels on the device (labels,
  * fluid index map, compacted fluid list), into vox_ws (device, >= vox_bytes,
  * 256-byte aligned). Synchronises once to return *n_fluid. Bit-identical to
@@ -232,8 +244,10 @@ int cdi_flow_step_to_steady(cdi_solver *s, double tol, int64_t max_steps, int32_
  * velocity is frozen at the mass flux j = rho u of the current populations
  * (or the field set by cdi_set_np_velocity). fused_flow = 1: every step also
  * advances the flow, and the ions see the mass flux of the previous step.
- * Checks the positivity bound dt * sum(outflow coefficients) <= 1 once
- * (synchronising) and returns UNSTABLE without stepping if it fails. */
+ * Checks the positivity bound dt * sum(outflow coefficients) <= 1 before the
+ * first step (synchronising) and returns UNSTABLE without stepping if it
+ * fails; with fused_flow, whose flow keeps changing, again every 256 steps
+ * (UNSTABLE then after the steps already taken, state valid). */
 int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow);
 
 /* Total adsorbed amount per species [Na, Cl] (lattice units: concentration x
@@ -311,6 +325,29 @@ int cdi_batch_bytes(cdi_solver *const *members, int32_t n, uint64_t *bytes);
 int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t ws_bytes, void *stream,
                      cdi_batch **out);
 int cdi_batch_destroy(cdi_batch *b);
+
+/* Batches whose membership changes while they run (continuous batching):
+ * an empty batch with room for up to max_members members holding up to
+ * max_fluid fluid nodes together; cdi_batch_capacity_bytes sizes its device
+ * workspace ws (256-byte aligned, kept by the caller until destroy). Members
+ * must still share the device, the dimension and the storage precision (set
+ * by the first admitted). */
+int cdi_batch_capacity_bytes(int32_t max_members, int64_t max_fluid, uint64_t *bytes);
+int cdi_batch_create_empty(int32_t max_members, int64_t max_fluid, void *ws, uint64_t ws_bytes, void *stream,
+                           cdi_batch **out);
+
+/* Admit a solver as the last member (index cdi_batch_members - 1), with no new
+ * workspace: BUFFER when the batch is full (members or fluid nodes beyond its
+ * capacity), INVALID for a duplicate or a mismatched solver. Retire a member:
+ * waits for the batch's queued work, then removes it (later members move up
+ * one index; the solver itself is untouched and usable alone). The modes of
+ * the next cdi_batch_advance follow the new member order. A membership
+ * change keeps the captured step graph when the launch shape is unchanged
+ * (it re-captures otherwise). Results stay bitwise those of each member
+ * stepped alone. */
+int cdi_batch_admit(cdi_batch *b, cdi_solver *member);
+int cdi_batch_retire(cdi_batch *b, cdi_solver *member);
+int cdi_batch_members(const cdi_batch *b, int32_t *n);
 
 /* Advance every member by nsteps in its mode (host array modes[n]):
  *   FLOW  = cdi_flow_steps, IONS = cdi_np_step(fused 0), FUSED = cdi_np_step(fused 1),

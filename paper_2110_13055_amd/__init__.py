@@ -13,5 +13,5 @@ from ._lib import (  # noqa: F401
     MODE_FLOW, MODE_FUSED, MODE_IDLE, MODE_IONS, STREAM_AA, STREAM_PULL, PSIX_DIRICHLET, PSIX_NEUMANN,
     PSIX_PERIODIC, PROBE_COPY, PROBE_READ, PROBE_FILL,
 )
-from .solver import Batch, Geometry, Params, Potential, Solver, bandwidth_probe, plan  # noqa: F401
+from .solver import Batch, Geometry, Params, Potential, Solver, bandwidth_probe, flow_check, plan  # noqa: F401
 from .presets import PRESETS, batch_instances, fibre_case, fibre_sweep, preset, serving_requests  # noqa: F401

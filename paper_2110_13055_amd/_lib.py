@@ -95,6 +95,7 @@ P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
 # name -> (restype, argtypes); the list of symbols include/cdi.h declares
 SIGNATURES = {
     "cdi_plan": (C.c_int, [P, P, P]),
+    "cdi_flow_check": (C.c_int, [P, P, D, P]),
     "cdi_build_geometry": (C.c_int, [P, P, U64, P, P]),
     "cdi_node_bytes": (C.c_int, [P, P, I64, P]),
     "cdi_flow_init": (C.c_int, [P, P, P, U64, P, U64, I64, P, P]),
@@ -119,6 +120,11 @@ SIGNATURES = {
     "cdi_batch_bytes": (C.c_int, [P, I32, P]),
     "cdi_batch_create": (C.c_int, [P, I32, P, U64, P, P]),
     "cdi_batch_destroy": (C.c_int, [P]),
+    "cdi_batch_capacity_bytes": (C.c_int, [I32, I64, P]),
+    "cdi_batch_create_empty": (C.c_int, [I32, I64, P, U64, P, P]),
+    "cdi_batch_admit": (C.c_int, [P, P]),
+    "cdi_batch_retire": (C.c_int, [P, P]),
+    "cdi_batch_members": (C.c_int, [P, P]),
     "cdi_batch_advance": (C.c_int, [P, I64, P]),
     "cdi_batch_residuals": (C.c_int, [P, P]),
     "cdi_batch_set_launch": (C.c_int, [P, I32, I32]),

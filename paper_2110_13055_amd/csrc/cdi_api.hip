@@ -600,6 +600,64 @@ int cdi_struct_size(const char *name, uint64_t *bytes)
     return fail(CDI_E_INVALID, "unknown struct %s", name);
 }
 
+int cdi_flow_check(const cdi_geometry *geom, const cdi_params *params, double max_drho, double *drho_estimate)
+{
+    int rc = check_geometry(geom);
+    if (rc) return rc;
+    if ((rc = check_params(params)) != CDI_OK) return rc;
+    if (!(max_drho >= 0)) return fail(CDI_E_INVALID, "bad max_drho");
+    const double limit = max_drho > 0 ? max_drho : 0.5;
+    double est = 0.0;
+    if (params->drive == CDI_INLET_OUTLET) {
+        // porosity and fluid-solid surface per volume of the electrode region
+        const double a = geom->r_min, b = geom->r_max, phi_t = geom->porosity;
+        double phi = phi_t, sv = 0.0;
+        if (geom->kind == CDI_USER_LABELS) {
+            const int nx = geom->nx, ny = geom->ny, nz = geom->dim == 2 ? 1 : geom->nz;
+            int64_t fluid = 0, faces = 0, vol = 0;
+            for (int z = 0; z < nz; ++z)
+                for (int y = 0; y < ny; ++y)
+                    for (int x = geom->buffer_x; x < nx - geom->buffer_x; ++x) {
+                        const uint8_t l = geom->user_labels[((int64_t)z * ny + y) * nx + x];
+                        ++vol;
+                        if (l != 0) continue;
+                        ++fluid;
+                        const int d3 = geom->dim == 3;
+                        const int nbs[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, d3}, {0, 0, -d3}};
+                        for (int k = 0; k < (d3 ? 6 : 4); ++k) {
+                            const int xn = x + nbs[k][0], yn = (y + nbs[k][1] + ny) % ny, zn = (z + nbs[k][2] + nz) % nz;
+                            if (geom->user_labels[((int64_t)zn * ny + yn) * nx + xn] != 0) ++faces;
+                        }
+                    }
+            phi = vol ? (double)fluid / vol : 1.0;
+            sv = vol ? (double)faces / vol : 0.0;
+        } else if (geom->kind == CDI_SPHERES || geom->kind == CDI_FIBRES) {
+            // Boolean models: surface per volume phi (-ln phi) times 3 E[r^2]/E[r^3]
+            // (spheres) or 2 / r (cylinders)
+            const double er2 = b > a ? (b * b * b - a * a * a) / (3 * (b - a)) : a * a;
+            const double er3 = b > a ? (b * b * b * b - a * a * a * a) / (4 * (b - a)) : a * a * a;
+            sv = geom->kind == CDI_SPHERES ? 3.0 * phi * -std::log(phi) * er2 / er3 : 2.0 * phi * -std::log(phi) / a;
+        } else {  // non-overlapping disks: perimeter per area (1 - phi) 2 E[r] / E[r^2]
+            const double er2 = b > a ? (b * b * b - a * a * a) / (3 * (b - a)) : a * a;
+            sv = (1.0 - phi) * 2.0 * 0.5 * (a + b) / er2;
+        }
+        if (sv > 0 && phi > 0 && phi < 1) {
+            // Kozeny-Carman permeability and Darcy's law over the electrode's length
+            const double k = phi * phi * phi / (5.0 * sv * sv);
+            const double nu = (params->tau - 0.5) / 3.0;
+            const double len = geom->nx - 2.0 * geom->buffer_x;
+            est = 3.0 * nu * std::fabs(params->u_in) * len / k;  // rho = 3 p in lattice units
+        }
+    }
+    if (drho_estimate) *drho_estimate = est;
+    if (est > limit)
+        return fail(CDI_E_UNSTABLE,
+                    "the steady flow needs a density drop of about %.2g across the electrode (Kozeny-Carman), "
+                    "beyond %.2g: outside the weakly compressible range of the lattice Boltzmann method", est, limit);
+    g_err[0] = 0;
+    return CDI_OK;
+}
+
 int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *out)
 {
     int rc = check_geometry(geom);
@@ -947,6 +1005,9 @@ int cdi_flow_step_to_steady(cdi_solver *s, double tol, int64_t max_steps, int32_
     return status;
 }
 
+// fused steps between two checks of the positivity bound within one call
+constexpr int64_t kFusedRecheck = 256;
+
 int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow)
 {
     if (!s || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
@@ -958,6 +1019,14 @@ int cdi_np_step(cdi_solver *s, int64_t nsteps, int32_t fused_flow)
     if (!(worst <= 1.0))
         return fail(CDI_E_UNSTABLE, "positivity bound violated: dt * sum(outflow coefficients) = %g > 1", worst);
     for (int64_t k = 0; k < nsteps; ++k) {
+        if (fused_flow && k > 0 && k % kFusedRecheck == 0) {
+            // the flow keeps changing under fused steps: the bound is taken again
+            s->jstate = s->mb ? J_IN_M : J_VALID;
+            if ((rc = check_stability(s, &worst)) != CDI_OK) return rc;
+            if (!(worst <= 1.0))
+                return fail(CDI_E_UNSTABLE, "positivity bound violated after %lld fused steps: %g > 1",
+                            (long long)k, worst);
+        }
         if (fused_flow) {
             const int flags = (s->mb && k > 0) ? kJFromM : 0;
             if ((rc = step_once(s, 1, 1, flags)) != CDI_OK) return rc;
@@ -1646,13 +1715,14 @@ struct cdi_batch {
     std::vector<cdi_solver *> m;
     std::vector<int> tile_begin;
     int n = 0, dim = 0, st = 0, total_tiles = 0, cus = 0;
+    int cap_n = 0, cap_tiles = 0;  // capacity of the workspace and staging (members, tiles)
     int workgroups_req = 0, blocks_per_cu = 0, lds_pad = 0;
     hipStream_t stream = nullptr;
-    BatchInst *dinst = nullptr;  // device, kSlots * n
-    int2 *dtiles = nullptr;      // device, kSlots * total_tiles (instance, tile), grouped by step class
-    double *dred = nullptr;      // device, 2 per member
-    BatchInst *hstage = nullptr; // pinned host, kSlots * n
-    int2 *htiles = nullptr;      // pinned host, kSlots * total_tiles
+    BatchInst *dinst = nullptr;  // device, kSlots * cap_n
+    int2 *dtiles = nullptr;      // device, kSlots * cap_tiles (instance, tile), grouped by step class
+    double *dred = nullptr;      // device, 2 per member slot
+    BatchInst *hstage = nullptr; // pinned host, kSlots * cap_n
+    int2 *htiles = nullptr;      // pinned host, kSlots * cap_tiles
     int cls_begin[kSlots][kClasses + 1] = {};
     std::vector<int> resid_valid;
     hipGraphExec_t exec = nullptr;
@@ -1707,7 +1777,7 @@ int batch_flags(const cdi_solver *s, int mode, int64_t idx, int64_t nsteps, bool
 // Descriptors of one step and its (instance, tile) list grouped by step class.
 void fill_slot(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64_t nsteps, bool want_resid)
 {
-    BatchInst *h = bt->hstage + (size_t)slot * bt->n;
+    BatchInst *h = bt->hstage + (size_t)slot * bt->cap_n;
     int count[kClasses] = {};
     for (int k = 0; k < bt->n; ++k) {
         const cdi_solver *s = bt->m[k];
@@ -1723,7 +1793,7 @@ void fill_slot(cdi_batch *bt, int slot, const int32_t *modes, int64_t idx, int64
     for (int c = 0; c < kClasses; ++c) beg[c + 1] = beg[c] + count[c];
     int pos[kClasses];
     for (int c = 0; c < kClasses; ++c) pos[c] = beg[c];
-    int2 *t = bt->htiles + (size_t)slot * bt->total_tiles;
+    int2 *t = bt->htiles + (size_t)slot * bt->cap_tiles;
     for (int k = 0; k < bt->n; ++k) {
         const int c = step_class(modes[k], stream_arg(bt->m[k]));
         if (c < 0) continue;
@@ -1747,12 +1817,12 @@ void advance_members(cdi_batch *bt, const int32_t *modes)
 int upload_slot(cdi_batch *bt, int slot)
 {
     const size_t bytes = sizeof(BatchInst) * (size_t)bt->n;
-    HIPCHK(hipMemcpyAsync(bt->dinst + (size_t)slot * bt->n, bt->hstage + (size_t)slot * bt->n, bytes,
+    HIPCHK(hipMemcpyAsync(bt->dinst + (size_t)slot * bt->cap_n, bt->hstage + (size_t)slot * bt->cap_n, bytes,
                           hipMemcpyHostToDevice, bt->stream));
     const size_t nt = (size_t)bt->cls_begin[slot][kClasses];
     if (nt)
-        HIPCHK(hipMemcpyAsync(bt->dtiles + (size_t)slot * bt->total_tiles,
-                              bt->htiles + (size_t)slot * bt->total_tiles, 8 * nt, hipMemcpyHostToDevice,
+        HIPCHK(hipMemcpyAsync(bt->dtiles + (size_t)slot * bt->cap_tiles,
+                              bt->htiles + (size_t)slot * bt->cap_tiles, 8 * nt, hipMemcpyHostToDevice,
                               bt->stream));
     return CDI_OK;
 }
@@ -1763,8 +1833,8 @@ int launch_slot(cdi_batch *bt, int slot)
     for (int c = 0; c < kClasses; ++c) {
         const int count = beg[c + 1] - beg[c];
         if (count <= 0) continue;
-        HIPCHK(launch_batch(bt->dim, bt->st, c, bt->dinst + (size_t)slot * bt->n,
-                            bt->dtiles + (size_t)slot * bt->total_tiles + beg[c], count,
+        HIPCHK(launch_batch(bt->dim, bt->st, c, bt->dinst + (size_t)slot * bt->cap_n,
+                            bt->dtiles + (size_t)slot * bt->cap_tiles + beg[c], count,
                             batch_workgroups(bt, count), bt->lds_pad, bt->stream));
     }
     return CDI_OK;
@@ -1832,13 +1902,23 @@ int cdi_batch_bytes(cdi_solver *const *members, int32_t n, uint64_t *bytes)
     return CDI_OK;
 }
 
-int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t ws_bytes, void *stream,
-                     cdi_batch **out)
+}  // extern "C"
+
+namespace {
+
+// Tiles a batch of capacity max_fluid fluid nodes over max_members members can hold.
+int64_t capacity_tiles(int32_t max_members, int64_t max_fluid)
 {
-    uint64_t need = 0;
-    int rc = cdi_batch_bytes(members, n, &need);
-    if (rc) return rc;
+    return (max_fluid + kTile - 1) / kTile + max_members;
+}
+
+// A batch with room for cap_n members and cap_tiles tiles in ws, holding members[0..n).
+int batch_new(cdi_solver *const *members, int32_t n, int cap_n, int64_t cap_tiles, void *ws, uint64_t ws_bytes,
+              void *stream, cdi_batch **out)
+{
     if (!out || !ws || ((uintptr_t)ws % kAlign)) return fail(CDI_E_BUFFER, "batch workspace NULL or misaligned");
+    if (cap_n <= 0 || cap_tiles <= 0 || cap_tiles > 0x3fffffff) return fail(CDI_E_INVALID, "bad batch capacity");
+    const uint64_t need = batch_layout(cap_n, (int)cap_tiles, nullptr, nullptr, nullptr, nullptr);
     if (ws_bytes < need) return fail(CDI_E_BUFFER, "batch workspace too small: %llu < %llu",
                                      (unsigned long long)ws_bytes, (unsigned long long)need);
     for (int k = 1; k < n; ++k)
@@ -1848,14 +1928,16 @@ int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t w
     if (!bt) return fail(CDI_E_INVALID, "out of host memory");
     bt->m.assign(members, members + n);
     bt->n = n;
-    bt->dim = members[0]->dim;
-    bt->st = members[0]->st;
+    bt->dim = n > 0 ? members[0]->dim : -1;
+    bt->st = n > 0 ? members[0]->st : -1;
+    bt->cap_n = cap_n;
+    bt->cap_tiles = (int)cap_tiles;
     bt->stream = (hipStream_t)stream;
     for (int k = 0; k < n; ++k) {
         bt->tile_begin.push_back(bt->total_tiles);
         bt->total_tiles += members[k]->ntiles;
     }
-    batch_layout(n, bt->total_tiles, &bt->dinst, &bt->dtiles, &bt->dred, ws);
+    batch_layout(cap_n, bt->cap_tiles, &bt->dinst, &bt->dtiles, &bt->dred, ws);
     bt->resid_valid.assign(n, 0);
     int dev = 0;
     auto cleanup = [&](int code) {
@@ -1868,15 +1950,95 @@ int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t w
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&bt->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "device query failed"));
-    if (hipHostMalloc((void **)&bt->hstage, sizeof(BatchInst) * (size_t)kSlots * n, hipHostMallocDefault) !=
+    if (hipHostMalloc((void **)&bt->hstage, sizeof(BatchInst) * (size_t)kSlots * cap_n, hipHostMallocDefault) !=
         hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
-    if (hipHostMalloc((void **)&bt->htiles, 8ull * kSlots * (size_t)bt->total_tiles, hipHostMallocDefault) !=
+    if (hipHostMalloc((void **)&bt->htiles, 8ull * kSlots * (size_t)bt->cap_tiles, hipHostMallocDefault) !=
         hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
     if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "event creation failed"));
     *out = bt;
+    return CDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdi_batch_create(cdi_solver *const *members, int32_t n, void *ws, uint64_t ws_bytes, void *stream,
+                     cdi_batch **out)
+{
+    uint64_t need = 0;
+    int rc = cdi_batch_bytes(members, n, &need);
+    if (rc) return rc;
+    int64_t tiles = 0;
+    for (int k = 0; k < n; ++k) tiles += members[k]->ntiles;
+    return batch_new(members, n, n, tiles, ws, ws_bytes, stream, out);
+}
+
+int cdi_batch_capacity_bytes(int32_t max_members, int64_t max_fluid, uint64_t *bytes)
+{
+    if (max_members <= 0 || max_fluid <= 0 || !bytes) return fail(CDI_E_INVALID, "bad batch capacity");
+    const int64_t tiles = capacity_tiles(max_members, max_fluid);
+    if (tiles > 0x3fffffff) return fail(CDI_E_INVALID, "batch capacity too large");
+    *bytes = batch_layout(max_members, (int)tiles, nullptr, nullptr, nullptr, nullptr);
+    return CDI_OK;
+}
+
+int cdi_batch_create_empty(int32_t max_members, int64_t max_fluid, void *ws, uint64_t ws_bytes, void *stream,
+                           cdi_batch **out)
+{
+    if (max_members <= 0 || max_fluid <= 0) return fail(CDI_E_INVALID, "bad batch capacity");
+    return batch_new(nullptr, 0, max_members, capacity_tiles(max_members, max_fluid), ws, ws_bytes, stream, out);
+}
+
+int cdi_batch_admit(cdi_batch *bt, cdi_solver *member)
+{
+    if (!bt || !member) return fail(CDI_E_INVALID, "NULL argument");
+    for (const cdi_solver *m : bt->m)
+        if (m == member) return fail(CDI_E_INVALID, "solver is already a member");
+    if (bt->n > 0 && (member->dim != bt->dim || member->st != bt->st))
+        return fail(CDI_E_INVALID, "batch members must share dimension and precision");
+    if (bt->n + 1 > bt->cap_n || (int64_t)bt->total_tiles + member->ntiles > bt->cap_tiles)
+        return fail(CDI_E_BUFFER, "batch full: %d of %d members, %d + %d of %d tiles", bt->n, bt->cap_n,
+                    bt->total_tiles, member->ntiles, bt->cap_tiles);
+    if (bt->n == 0) {
+        bt->dim = member->dim;
+        bt->st = member->st;
+    }
+    bt->m.push_back(member);
+    bt->tile_begin.push_back(bt->total_tiles);
+    bt->total_tiles += member->ntiles;
+    bt->resid_valid.push_back(0);
+    bt->n++;
+    return CDI_OK;
+}
+
+int cdi_batch_retire(cdi_batch *bt, cdi_solver *member)
+{
+    if (!bt || !member) return fail(CDI_E_INVALID, "NULL argument");
+    int k = 0;
+    while (k < bt->n && bt->m[k] != member) ++k;
+    if (k == bt->n) return fail(CDI_E_INVALID, "solver is not a member");
+    // nothing batched may still be reading the member's descriptors or state
+    if (bt->stream) HIPCHK(hipStreamSynchronize(bt->stream));
+    bt->m.erase(bt->m.begin() + k);
+    bt->resid_valid.erase(bt->resid_valid.begin() + k);
+    bt->n--;
+    bt->tile_begin.clear();
+    bt->total_tiles = 0;
+    for (int q = 0; q < bt->n; ++q) {
+        bt->tile_begin.push_back(bt->total_tiles);
+        bt->total_tiles += bt->m[q]->ntiles;
+    }
+    return CDI_OK;
+}
+
+int cdi_batch_members(const cdi_batch *bt, int32_t *n)
+{
+    if (!bt || !n) return fail(CDI_E_INVALID, "NULL argument");
+    *n = bt->n;
     return CDI_OK;
 }
 
@@ -1920,8 +2082,9 @@ int cdi_batch_get_launch(const cdi_batch *bt, int32_t *workgroups, int32_t *bloc
 
 int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
 {
-    if (!bt || !modes || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
-    if (nsteps == 0) return CDI_OK;
+    if (!bt || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
+    if (nsteps == 0 || bt->n == 0) return CDI_OK;
+    if (!modes) return fail(CDI_E_INVALID, "modes is NULL");
     bool any_flow = false, need_first = false;
     for (int k = 0; k < bt->n; ++k) {
         const int md = modes[k];

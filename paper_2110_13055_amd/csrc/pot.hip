@@ -80,7 +80,7 @@ __device__ inline void face_maps(const PotArgs &a, int n, int (&m)[2 * L::D])
 {
     if (NBR) {
 #pragma unroll
-        for (int k = 0; k < 2 * L::D; ++k) m[k] = ldu(a.nbr, (uint32_t)(k * a.g.P + n));
+        for (int k = 0; k < 2 * L::D; ++k) m[k] = ldu(a.nbr + (size_t)k * a.g.P, (uint32_t)n);  // plane k
         return;
     }
     int x, y, z;

@@ -119,7 +119,7 @@ def batch_instances(n: int = 64, base_seed: int = BASE_SEED, precision: int = L.
 
 def serving_requests(n: int, rate_hz: float = 2.0, base_seed: int = BASE_SEED,
                      precision: int = L.FP32, np_steps_2d: int = 5000, np_steps_3d: int = 20000,
-                     flow_tol: float = 1e-8, flow_max_steps: int = 20000,
+                     flow_tol: float = 1e-6, flow_max_steps: int = 20000,
                      streaming: int = L.STREAM_AA):
     """A fixed trace of mixed solve requests with Poisson arrivals: half are
     2D 256x256 D2Q9 channels (disks r in [4, 8], walls top/bottom, porosity

@@ -7,12 +7,22 @@ footprint fits the budget, keeps its state resident on the GPU, and advances
 all admitted requests together in rounds. A round is one batched advance per
 group (requests of one lattice dimension and storage precision form a group;
 each group has its own stream, so the 2D and 3D groups overlap on the device).
-A request runs its flow phase in rounds until its steady-state residual
-reaches the tolerance, stops falling (no new minimum for ``stagnation_rounds``
-rounds: the floor of single-precision storage) or its flow budget is spent,
-then its ion phase on the
-frozen flow for the requested number of steps; it is then retired: results
-read back, slot and memory released. Latency is arrival to result.
+Before a request takes a slot its flow is checked on the host: an inlet
+velocity that would need a density drop beyond the weakly compressible
+range of the lattice Boltzmann method (Kozeny-Carman estimate,
+``cdi_flow_check``) is rejected at once. A request runs its flow phase in
+rounds until its steady-state residual reaches the tolerance, stops falling
+(no new minimum for ``stagnation_rounds`` rounds: the floor of
+single-precision storage) or its flow budget is spent, then its ion phase on
+the frozen flow for the requested number of steps; it is then retired:
+results read back, slot and memory released. A request whose flow stopped
+short of its tolerance retires as ``ok_unconverged`` (its reached residual is
+in the result). Latency is arrival to result.
+
+Members join and leave each group's batch in place (``cdi_batch_admit`` /
+``cdi_batch_retire`` on a batch created with room to spare): no new
+workspace, and the captured step graph is kept while the launch shape
+allows.
 
 A request's step sequence depends only on the request (rounds of
 ``round_steps`` counted from its own admission, the phase switch decided by
@@ -22,7 +32,7 @@ result is the same alone and in any mix.
 The scheduler talks to an executor: ``GpuExecutor`` drives libcdi through the
 binding; the protocol is small enough for test doubles (``start``,
 ``footprint_estimate``, ``footprint``, ``group_key``, ``advance``, ``finish``,
-``release``).
+``release``, and optionally ``check``).
 """
 from __future__ import annotations
 
@@ -79,6 +89,8 @@ class _Active:
     residual: float = math.inf
     best: float = math.inf
     since_best: int = 0
+    converged: bool = False
+    work: int = 0        # fluid nodes it adds to each step of its group
 
 
 _MEMBER = re.compile(r"member (\d+):")
@@ -91,25 +103,39 @@ class GpuExecutor:
     # descriptors, tile lists, allocator rounding)
     OVERHEAD = 4 << 20
 
-    def __init__(self, device: str = "cuda", keep_fields: bool = False):
+    def __init__(self, device: str = "cuda", keep_fields: bool = False, max_members: int = 64,
+                 max_fluid: int = 1 << 26, max_drho: float = 0.0):
         import torch
-        from .solver import Batch, Solver, plan
+        from .solver import Batch, Solver, flow_check, plan
         self.torch = torch
-        self.Solver, self.Batch, self.plan = Solver, Batch, plan
+        self.Solver, self.Batch, self.plan, self.flow_check = Solver, Batch, plan, flow_check
         self.device = torch.device(device)
         self.keep_fields = keep_fields
+        self.max_members, self.max_fluid, self.max_drho = int(max_members), int(max_fluid), float(max_drho)
         self.streams: Dict[tuple, object] = {}
-        self._batches: Dict[tuple, tuple] = {}
+        self._batches: Dict[tuple, object] = {}   # group -> Batch with room to admit
 
     def _stream(self, key):
         if key not in self.streams:
             self.streams[key] = self.torch.cuda.Stream(device=self.device)
         return self.streams[key]
 
+    def check(self, req: Request):
+        """(admissible, message): the host-side flow check."""
+        ok, est, msg = self.flow_check(req.geom, req.params, self.max_drho)
+        return ok, msg
+
     def footprint_estimate(self, req: Request) -> int:
         info = self.plan(req.geom, req.params)
         return int(info.vox_bytes + info.node_bytes_per_fluid * max(info.n_fluid_est, 1) * 1.1
                    + self.OVERHEAD)
+
+    def work_estimate(self, req: Request) -> int:
+        """Fluid nodes the request would add to a step (the plan's estimate)."""
+        return int(self.plan(req.geom, req.params).n_fluid_est)
+
+    def work(self, handle) -> int:
+        return int(handle.n_fluid)
 
     def start(self, req: Request):
         key = (req.geom.dim, req.params.precision)
@@ -121,26 +147,52 @@ class GpuExecutor:
     def group_key(self, handle):
         return (handle.dim, handle.params.precision)
 
+    def _batch_for(self, key, members):
+        """The group's batch holding exactly `members`, in that order: members
+        that left are retired and new ones admitted in place; a batch that is
+        full is replaced by one with twice the room."""
+        b = self._batches.get(key)
+        if b is None:
+            b = self._batches[key] = self.Batch(stream=self._stream(key), capacity=(self.max_members, self.max_fluid),
+                                                device=str(self.device))
+        want = {id(m) for m in members}
+        for m in list(b.members):
+            if id(m) not in want:
+                b.retire(m)
+        have = [id(m) for m in b.members]
+        if have != [id(m) for m in members[:len(have)]]:   # order differs: start over
+            for m in list(b.members):
+                b.retire(m)
+        for m in members[len(b.members):]:
+            try:
+                b.admit(m)
+            except L.CdiError as exc:
+                if exc.code != L.E_BUFFER:
+                    raise
+                cap_n = max(self.max_members, 2 * len(members))
+                self.max_fluid *= 2
+                old = b
+                b = self._batches[key] = self.Batch(list(old.members), stream=self._stream(key),
+                                                    capacity=(cap_n, self.max_fluid), device=str(self.device))
+                old.close()
+                b.admit(m)
+        return b
+
     def advance(self, groups: Dict[tuple, List[object]], modes: Dict[tuple, List[int]], nsteps: int):
         """Every group advances nsteps (groups overlap on their streams).
         Returns (residuals per group, failures {group: (member, message)});
         a failed group was not stepped."""
         failed = {}
         for key, members in groups.items():
-            ids = tuple(id(m) for m in members)
-            cached = self._batches.get(key)
-            if cached is None or cached[0] != ids:
-                if cached is not None:
-                    cached[1].close()
-                self._batches[key] = (ids, self.Batch(members, stream=self._stream(key)))
+            b = self._batch_for(key, members)
             try:
-                self._batches[key][1].advance(nsteps, modes[key])
+                b.advance(nsteps, modes[key])
             except L.CdiError as exc:
                 m = _MEMBER.search(str(exc))
                 if exc.code != L.E_UNSTABLE or m is None:
                     raise
                 failed[key] = (int(m.group(1)), str(exc))
-        res = {key: self._batches[key][1].residuals() for key in groups if key not in failed}
+        res = {key: self._batches[key].residuals() for key in groups if key not in failed}
         return res, failed
 
     def finish(self, handle):
@@ -151,15 +203,14 @@ class GpuExecutor:
         return out
 
     def release(self, handle):
-        for key, (ids, b) in list(self._batches.items()):
-            if id(handle) in ids:
-                b.close()
-                del self._batches[key]
+        for b in self._batches.values():
+            if any(m is handle for m in b.members):
+                b.retire(handle)
         handle.synchronize()
         handle.close()
 
     def close(self):
-        for _, b in self._batches.values():
+        for b in self._batches.values():
             b.close()
         self._batches.clear()
 
@@ -169,6 +220,7 @@ class Server:
 
     def __init__(self, executor, budget_bytes: float = 200e9, max_slots: int = 64,
                  round_steps: int = 200, stagnation_rounds: int = 3,
+                 max_active_nodes: float = math.inf,
                  clock: Optional[Callable[[], float]] = None,
                  sleep: Optional[Callable[[float], None]] = None):
         if round_steps < 2:
@@ -178,6 +230,10 @@ class Server:
         self.max_slots = int(max_slots)
         self.round_steps = int(round_steps)
         self.stagnation_rounds = int(stagnation_rounds)
+        # fluid nodes stepped together at most (the first request is always
+        # admitted): past what fills the GPU, batching more only time-slices it
+        self.max_active_nodes = float(max_active_nodes)
+        self.active_nodes = 0
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
         self.queue: List[Request] = []
@@ -198,8 +254,21 @@ class Server:
     def _admit(self):
         while self.queue and len(self.active) < self.max_slots:
             req = self.queue[0]
-            est = self.ex.footprint_estimate(req)
             now = self._now()
+            check = getattr(self.ex, "check", None)
+            if check is not None:
+                ok, msg = check(req)
+                if not ok:  # refused before it takes a slot
+                    self.queue.pop(0)
+                    self.results.append(Result(req.rid, req.arrival_s, now, now, 0,
+                                               status=f"rejected: unstable flow: {msg}"))
+                    continue
+            try:
+                est = self.ex.footprint_estimate(req)
+            except Exception as exc:  # e.g. its electrode cannot be generated: refused, nothing else affected
+                self.queue.pop(0)
+                self.results.append(Result(req.rid, req.arrival_s, now, now, 0, status=f"rejected: {exc}"))
+                continue
             if est > self.budget:
                 self.queue.pop(0)
                 self.results.append(Result(req.rid, req.arrival_s, now, now, est,
@@ -207,6 +276,10 @@ class Server:
                 continue
             if self.used + est > self.budget:
                 break  # FIFO: wait until retirements free memory
+            work_estimate = getattr(self.ex, "work_estimate", None)
+            if (self.active and work_estimate is not None
+                    and self.active_nodes + work_estimate(req) > self.max_active_nodes):
+                break  # FIFO: wait until the active work drops
             self.queue.pop(0)
             try:
                 h = self.ex.start(req)
@@ -215,20 +288,25 @@ class Server:
                                            status=f"failed: {exc}"))
                 continue
             fp = self.ex.footprint(h)
+            work = self.ex.work(h) if hasattr(self.ex, "work") else 0
             self.used += fp
-            self.active.append(_Active(req, h, now, fp))
+            self.active_nodes += work
+            self.active.append(_Active(req, h, now, fp, work=work))
         self.peak_slots = max(self.peak_slots, len(self.active))
         self.peak_bytes = max(self.peak_bytes, self.used)
 
     def _retire(self, a: _Active, status: str):
         out = {}
-        if status == "ok":
+        if status == "ok" and not a.converged:
+            status = "ok_unconverged"
+        if status in ("ok", "ok_unconverged"):
             try:
                 out = self.ex.finish(a.handle)
             except Exception as exc:
                 status = f"failed: {exc}"
         self.ex.release(a.handle)
         self.used -= a.footprint
+        self.active_nodes -= a.work
         self.active.remove(a)
         ads = tuple(np.asarray(out["adsorbed"], dtype=float).tolist()) if "adsorbed" in out else (math.nan,) * 2
         bal = tuple(np.asarray(out["balance"], dtype=float).reshape(-1).tolist()) if "balance" in out else ()
@@ -239,15 +317,22 @@ class Server:
             self.fields[a.req.rid] = extra
 
     # ------------------------------------------------------------ main loop
-    def run(self, requests: List[Request], horizon_s: float = math.inf) -> List[Result]:
+    def run(self, requests: List[Request], horizon_s: float = math.inf,
+            progress: Optional[Callable[[str], None]] = None, progress_every_s: float = 10.0) -> List[Result]:
         """Serve requests (arrival_s relative to the start of the run). Ends
         when all are done, or at horizon_s; what is left then is the backlog
-        (queued, not yet arrived, or still active)."""
+        (queued, not yet arrived, or still active). progress (optional)
+        receives a status line every progress_every_s seconds."""
         pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
         self.t0 = self.clock()
         i = 0
+        next_report = progress_every_s
         while True:
             now = self._now()
+            if progress is not None and now >= next_report:
+                progress(f"t={now:.0f} s: {len(self.results)} done, {len(self.active)} active, "
+                         f"{len(self.queue)} queued, {len(pending) - i} to arrive")
+                next_report += progress_every_s
             while i < len(pending) and pending[i].arrival_s <= now:
                 self.queue.append(pending[i])
                 i += 1
@@ -297,6 +382,7 @@ class Server:
                         retire.append((a, "failed: flow diverged"))
                     elif (a.residual <= a.req.flow_tol or a.since_best >= self.stagnation_rounds
                           or a.flow_steps >= a.req.flow_max_steps):
+                        a.converged = a.residual <= a.req.flow_tol
                         a.phase = L.MODE_IONS
                         if a.req.np_steps <= 0:
                             retire.append((a, "ok"))
@@ -315,11 +401,15 @@ def poisson_arrivals(n: int, rate_hz: float, seed: int) -> List[float]:
 
 
 def latency_stats(results: List[Result], wall_s: float) -> dict:
-    ok = [r for r in results if r.status == "ok"]
+    """Completed = results delivered ("ok", or "ok_unconverged": flow stopped
+    short of its tolerance, counted apart too); latency over those."""
+    ok = [r for r in results if r.status in ("ok", "ok_unconverged")]
     lat = np.array([r.latency_s for r in ok], dtype=float)
     return {
         "completed": len(ok),
-        "failed": sum(1 for r in results if r.status != "ok"),
+        "unconverged": sum(1 for r in ok if r.status == "ok_unconverged"),
+        "rejected": sum(1 for r in results if r.status.startswith("rejected")),
+        "failed": sum(1 for r in results if r.status.startswith("failed")),
         "solves_per_hour": len(ok) / wall_s * 3600.0 if wall_s > 0 else math.nan,
         "p50_s": float(np.percentile(lat, 50)) if ok else math.nan,
         "p99_s": float(np.percentile(lat, 99)) if ok else math.nan,

@@ -115,6 +115,20 @@ def bandwidth_probe(mode: int, dst, src=None, value: int = 0, stream=None) -> No
                                     value & 0xFFFFFFFF, st.cuda_stream), "cdi_bandwidth_probe")
 
 
+def flow_check(geom: Geometry, params: Params, max_drho: float = 0.0):
+    """Host-only admission check (cdi_flow_check): (ok, estimated steady
+    density drop across the electrode, message)."""
+    lib = L.load()
+    g, keep = geom.to_c()
+    p = params.to_c()
+    est = C.c_double()
+    rc = lib.cdi_flow_check(C.byref(g), C.byref(p), max_drho, C.byref(est))
+    if rc not in (L.OK, L.E_UNSTABLE):
+        L.check(rc, "cdi_flow_check")
+    msg = lib.cdi_last_error().decode(errors="replace") if rc != L.OK else ""
+    return rc == L.OK, est.value, msg
+
+
 @dataclass
 class Potential:
     """Settings of the potential solve (Poisson, Eq. 4-5; see cdi_potential in
@@ -394,25 +408,53 @@ class Batch:
     for all members, step pairs replayed from a captured HIP graph. Each
     member's results equal those of advancing it alone."""
 
-    def __init__(self, members, stream=None):
+    def __init__(self, members=(), stream=None, capacity=None, device="cuda"):
+        """members: the initial solvers. capacity (max_members, max_fluid):
+        room to admit and retire members later without a new workspace
+        (cdi_batch_create_empty + cdi_batch_admit); None: exactly the
+        initial members (cdi_batch_create)."""
         torch = _torch()
         self.lib = L.load()
         self.members = list(members)
         n = len(self.members)
-        if n == 0:
-            raise ValueError("empty batch")
-        dev = self.members[0].device
+        if n == 0 and capacity is None:
+            raise ValueError("empty batch without a capacity")
+        dev = self.members[0].device if n else torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
-        self._arr = (C.c_void_p * n)(*[s.h.value for s in self.members])
         nb = C.c_uint64()
-        L.check(self.lib.cdi_batch_bytes(self._arr, n, C.byref(nb)), "cdi_batch_bytes")
-        self.ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=dev)
         h = C.c_void_p()
-        L.check(self.lib.cdi_batch_create(self._arr, n, C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
-                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)),
-                "cdi_batch_create")
-        self.h = h
-        self.n = n
+        if capacity is None:
+            self._arr = (C.c_void_p * n)(*[s.h.value for s in self.members])
+            L.check(self.lib.cdi_batch_bytes(self._arr, n, C.byref(nb)), "cdi_batch_bytes")
+            self.ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=dev)
+            L.check(self.lib.cdi_batch_create(self._arr, n, C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                              C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                    "cdi_batch_create")
+            self.h = h
+        else:
+            cap_n, cap_fluid = int(capacity[0]), int(capacity[1])
+            L.check(self.lib.cdi_batch_capacity_bytes(cap_n, cap_fluid, C.byref(nb)), "cdi_batch_capacity_bytes")
+            self.ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=dev)
+            L.check(self.lib.cdi_batch_create_empty(cap_n, cap_fluid, C.c_void_p(self.ws.data_ptr()),
+                                                    self.ws.numel(), C.c_void_p(self.stream.cuda_stream),
+                                                    C.byref(h)), "cdi_batch_create_empty")
+            self.h = h
+            members, self.members = self.members, []
+            for s in members:
+                self.admit(s)
+        self.n = len(self.members)
+
+    def admit(self, solver):
+        """Add a member at the end (cdi_batch_admit); raises CdiError(BUFFER) when full."""
+        L.check(self.lib.cdi_batch_admit(self.h, solver.h), "cdi_batch_admit")
+        self.members.append(solver)
+        self.n = len(self.members)
+
+    def retire(self, solver):
+        """Remove a member (cdi_batch_retire); later members move up one index."""
+        L.check(self.lib.cdi_batch_retire(self.h, solver.h), "cdi_batch_retire")
+        self.members = [m for m in self.members if m is not solver]
+        self.n = len(self.members)
 
     def _modes(self, modes):
         if isinstance(modes, int):

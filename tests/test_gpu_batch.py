@@ -232,3 +232,74 @@ def test_batch_members_in_a_solved_potential_equal_members_alone(precision):
     for k, (a, c) in enumerate(zip(alone, batched)):
         for x, y in zip(state(a), state(c)):
             assert np.array_equal(x, y), f"member {k}"
+
+
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16, L.MOMENTS])
+def test_members_admitted_and_retired_mid_run(precision):
+    # a batch created with room to spare: members join while others run and
+    # leave before the end, in place (no new workspace); every member ends
+    # bitwise where the same sequence of steps takes it alone
+    specs = members(precision, n=5)
+    # (member, first stage, last stage) and the per-stage (steps, mode of every member)
+    life = {0: (0, 3), 1: (0, 1), 2: (1, 3), 3: (2, 3), 4: (1, 2)}
+    stages = [(9, FLOW), (8, FUSED), (11, FLOW), (7, FUSED)]
+
+    def mode_at(k, q):
+        a, b = life[k]
+        if not (a <= q <= b):
+            return None
+        return stages[q][1] if (k + q) % 3 else IONS if q > a else FLOW
+
+    alone = []
+    for k, (g, p) in enumerate(specs):
+        s = Solver(g, p)
+        for q, (n, _) in enumerate(stages):
+            m = mode_at(k, q)
+            if m == FLOW:
+                s.flow_steps(n)
+            elif m == IONS:
+                s.np_step(n, fused=False)
+            elif m == FUSED:
+                s.np_step(n, fused=True)
+        alone.append(state(s))
+
+    print(f"admit/retire precision={precision}", flush=True)
+    sol = [Solver(g, p) for g, p in specs]
+    b = Batch(capacity=(4, 10 ** 6))
+    ws = b.ws.data_ptr()
+    for q, (n, _) in enumerate(stages):
+        for k in range(5):
+            if life[k][0] == q:
+                b.admit(sol[k])
+        assert b.n <= 4
+        b.advance(n, [mode_at(sol.index(s), q) for s in b.members])
+        for k in range(5):
+            if life[k][1] == q:
+                b.retire(sol[k])
+    assert b.n == 0 and b.ws.data_ptr() == ws
+    b.close()
+    for k in range(5):
+        got = state(sol[k])
+        for a, c in zip(alone[k], got):
+            assert np.array_equal(a, c), k
+
+
+def test_admit_refuses_a_full_batch_and_a_mismatch():
+    specs = members(L.FP32, n=3)
+    sol = [Solver(g, p) for g, p in specs]
+    b = Batch(capacity=(2, 10 ** 6))
+    b.admit(sol[0])
+    with pytest.raises(L.CdiError) as e:
+        b.admit(sol[0])
+    assert e.value.code == L.E_INVALID
+    b.admit(sol[1])
+    with pytest.raises(L.CdiError) as e:
+        b.admit(sol[2])                       # two members is the room it has
+    assert e.value.code == L.E_BUFFER
+    b.retire(sol[0])
+    b.admit(sol[2])
+    g, p = specs[0]
+    p.precision = L.MOMENTS
+    with pytest.raises(L.CdiError):
+        b.admit(Solver(g, p))                 # another storage precision
+    b.close()

@@ -55,12 +55,13 @@ def serve(reqs):
     return srv, res
 
 
-@pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV, L.MOMENTS])
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16, L.FP16_DEV, L.MOMENTS])
 def test_served_results_alone_equal_mix(precision):
     reqs = trace(precision)
     srv, mix = serve(reqs)
     assert srv.backlog == 0 and srv.peak_slots >= 3 and srv.used == 0
-    assert all(r.status == "ok" for r in mix.values())
+    # a flow that stopped at its step budget short of 1e-5 is delivered as unconverged
+    assert all(r.status in ("ok", "ok_unconverged") for r in mix.values())
     st = latency_stats(list(mix.values()), wall_s=1.0)
     assert st["completed"] == len(reqs)
     for r in reqs:
