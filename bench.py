@@ -396,6 +396,9 @@ def main():
                     help="requests in the serving trace (0 skips the serving leg)")
     ap.add_argument("--serve-horizon", type=float, default=50.0,
                     help="seconds each serving run lasts (the rest is reported as backlog)")
+    ap.add_argument("--serve-whole-limit", type=float, default=240.0,
+                    help="the chosen serving form also serves the whole trace, up to this many "
+                         "seconds (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the probe's copy kernel over this size (a kernel of known "
                          "traffic, to calibrate HBM byte counters under a profiler)")
@@ -496,6 +499,10 @@ def main():
                                                       SERVE_ACTIVE_NODES)
         log("serving: FP32 one at a time")
         sv["plain_fp32_one_at_a_time"] = serving_run(args.serve_requests, P.FP32, 1, strm, H)
+        if args.serve_whole_limit > 0:
+            log("serving: continuous batching, moments, the whole trace")
+            sv["continuous_batching_moments_whole_trace"] = serving_run(
+                args.serve_requests, P.MOMENTS, SERVE_SLOTS, strm, args.serve_whole_limit, SERVE_ACTIVE_NODES)
         out["serving"] = sv
     if not args.no_cpu:
         log("CPU baseline (FP64 oracle)")

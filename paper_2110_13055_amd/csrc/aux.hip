@@ -53,14 +53,8 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = fb[i];
     }
-    float drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        drho += f[i];
-        jx += L::ex[i] * f[i];
-        jy += L::ey[i] * f[i];
-        jz += L::ez[i] * f[i];
-    }
+    float drho, jx, jy, jz;
+    lat_moments<L>(f, drho, jx, jy, jz);
     if (p.forced) {
         jx += 0.5f * p.F[0];
         jy += 0.5f * p.F[1];

@@ -123,11 +123,15 @@ __device__ inline void nb_ctx(const Grid &g, int x, int y, int z, bool periodic_
         c.X[d] = ((uint32_t)(xn >> k.bsx) << V) | (uint32_t)(xn & ((1 << k.bsx) - 1));
         int yn = y + d - 1;
         yn = yn < 0 ? yn + g.ny : (yn >= g.ny ? yn - g.ny : yn);
-        c.Y[d] = ((uint32_t)((yn >> k.bsy) * k.nbx) << V) | ((uint32_t)(yn & ((1 << k.bsy) - 1)) << k.bsx);
+        // brick-row products as 24-bit multiplies (full rate; the 32-bit
+        // multiply issues at a quarter): below 2^30 voxels, no brick count or
+        // brick index reaches 2^24
+        c.Y[d] = (__umul24((uint32_t)(yn >> k.bsy), (uint32_t)k.nbx) << V) |
+                 ((uint32_t)(yn & ((1 << k.bsy) - 1)) << k.bsx);
         if (L::D == 3) {
             int zn = z + d - 1;
             zn = zn < 0 ? zn + g.nz : (zn >= g.nz ? zn - g.nz : zn);
-            c.Z[d] = ((uint32_t)((zn >> k.bsz) * k.nbx * k.nby) << V) |
+            c.Z[d] = (__umul24((uint32_t)(zn >> k.bsz), (uint32_t)(k.nbx * k.nby)) << V) |
                      ((uint32_t)(zn & ((1 << k.bsz) - 1)) << (k.bsx + k.bsy));
         } else {
             c.Z[d] = 0;
@@ -145,14 +149,73 @@ __device__ inline int nb_get(const Grid &g, const NbCtx &c, int i)
     return (L::ex[i] != 0 && c.xo[dx]) ? kOutside : m;
 }
 
+// acc + c v for a lattice vector component c (-1, 0 or 1 on D2Q9 and D3Q19;
+// a constant once a direction loop is unrolled): the product with 0 is
+// dropped and the others become an add or a subtraction. The compiler may not
+// drop 0 * v by itself (under IEEE rules it is NaN for an infinite v); the
+// value is the same, up to the sign of a zero.
+__device__ __forceinline__ float lat_add(float acc, int c, float v)
+{
+    return c == 0 ? acc : (c > 0 ? acc + v : acc - v);
+}
+
+// e_i . u, from -0 (the exact additive identity: -0 + v is v for every v).
+template <class L>
+__device__ __forceinline__ float lat_dot(int i, float ux, float uy, float uz)
+{
+    return lat_add(lat_add(lat_add(-0.f, L::ex[i], ux), L::ey[i], uy), L::ez[i], uz);
+}
+
+// Zeroth and first moments of f: d = sum_i f_i, j = sum_i e_i f_i.
+template <class L>
+__device__ __forceinline__ void lat_moments(const float (&f)[L::Q], float &d, float &jx, float &jy, float &jz)
+{
+    d = jx = jy = jz = -0.f;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        d += f[i];
+        jx = lat_add(jx, L::ex[i], f[i]);
+        jy = lat_add(jy, L::ey[i], f[i]);
+        jz = lat_add(jz, L::ez[i], f[i]);
+    }
+}
+
 // 1 / rho from rho - 1: the hardware reciprocal (within 1 ulp), one
 // instruction where an IEEE division takes ten. Every kernel that forms u =
 // j / rho uses it, so they all form the same u.
 __device__ __forceinline__ float inv_rho(float drho) { return __builtin_amdgcn_rcpf(1.f + drho); }
 
-// BGK equilibrium less w_i (1 + R) for a direction of weight w, where R is a
-// reference density deviation: from dr = rho - 1 - R, rho and e.u. Quadratic
-// in u, or its linear (Stokes) part.
+// BGK equilibrium less w_i (1 + R), R a reference density deviation, split
+// into per-node terms so that a direction costs two fused multiply-adds and
+// a product: with dr = rho - 1 - R it is w_i (a + e.u (b + c e.u)), where
+// a = dr - (3/2) rho u.u, b = 3 rho and c = (9/2) rho; the linear (Stokes)
+// part has a = dr and c = 0.
+struct EqTerms {
+    float a, b, c;
+};
+
+__device__ inline EqTerms eq_terms(float dr, float rho, float ux, float uy, float uz, int linear)
+{
+    if (linear) return EqTerms{dr, 3.f * rho, 0.f};
+    const float uu = ux * ux + uy * uy + uz * uz;
+    return EqTerms{fmaf(-1.5f * rho, uu, dr), 3.f * rho, 4.5f * rho};
+}
+
+__device__ __forceinline__ float feq_eu(float w, const EqTerms &t, float eu)
+{
+    return w * fmaf(eu, fmaf(t.c, eu, t.b), t.a);
+}
+
+// direction i of the node whose terms are t
+template <class L>
+__device__ __forceinline__ float feq_dir(int i, const EqTerms &t, float ux, float uy, float uz)
+{
+    return feq_eu(L::w[i], t, lat_dot<L>(i, ux, uy, uz));
+}
+
+// one direction of weight w, from dr = rho - 1 - R, rho and e.u, where each
+// direction has its own moments (the emitters' equilibria of the FP16 and
+// moment storages): the same polynomial, evaluated directly
 __device__ inline float feq_rel_eu(float w, float dr, float rho, float eu, float ux, float uy, float uz, int linear)
 {
     if (linear) return w * (dr + 3.f * rho * eu);
@@ -164,21 +227,6 @@ __device__ inline float feq_rel_eu(float w, float dr, float rho, float eu, float
 __device__ inline float feq_bar_eu(float w, float drho, float eu, float ux, float uy, float uz, int linear)
 {
     return feq_rel_eu(w, drho, 1.f + drho, eu, ux, uy, uz, linear);
-}
-
-// The same for lattice direction i.
-template <class L>
-__device__ inline float feq_bar(int i, float drho, float ux, float uy, float uz, int linear)
-{
-    const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
-    return feq_bar_eu(L::w[i], drho, eu, ux, uy, uz, linear);
-}
-
-template <class L>
-__device__ inline float feq_rel(int i, float dr, float rho, float ux, float uy, float uz, int linear)
-{
-    const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
-    return feq_rel_eu(L::w[i], dr, rho, eu, ux, uy, uz, linear);
 }
 
 // FP32 population storage holds f_i - w_i (1 + R[x_s]), where x_s is the x
@@ -295,7 +343,7 @@ __device__ inline float gather_raw(const void *F, int P, const int *nb, int n, i
 template <class L, int ST>
 __device__ inline float from_emitter(float raw, int i, bool fl, float4 m, const Phys &p)
 {
-    const float eu = L::ex[i] * m.y + L::ey[i] * m.z + L::ez[i] * m.w;
+    const float eu = lat_dot<L>(i, m.y, m.z, m.w);
     const float fe = feq_bar_eu(L::w[i], m.x, fl ? eu : -eu, m.y, m.z, m.w, p.linear_eq);
     return ST == kMom ? fe : fe + raw * p.hs_inv;
 }
@@ -340,14 +388,8 @@ template <class L>
 __device__ inline void nee_populations(const Phys &p, bool inlet, const float (&fc)[L::Q], float (&fb)[L::Q],
                                        float rc = 0.f, float rb = 0.f)
 {
-    float dr = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        dr += fc[i];
-        jx += L::ex[i] * fc[i];
-        jy += L::ey[i] * fc[i];
-        jz += L::ez[i] * fc[i];
-    }
+    float dr, jx, jy, jz;
+    lat_moments<L>(fc, dr, jx, jy, jz);
     const float rho = 1.f + rc + dr;
     const float ri = __builtin_amdgcn_rcpf(rho);
     const float ux = jx * ri, uy = jy * ri, uz = jz * ri;
@@ -355,10 +397,10 @@ __device__ inline void nee_populations(const Phys &p, bool inlet, const float (&
     const float trho = inlet ? rho : p.rho_out;
     const float tx = inlet ? p.u_in : ux, ty = inlet ? 0.f : uy, tz = inlet ? 0.f : uz;
     const float tdr = inlet ? (rc + dr) - rb : (p.rho_out - 1.f) - rb;
+    const EqTerms te = eq_terms(tdr, trho, tx, ty, tz, p.linear_eq), ce = eq_terms(dr, rho, ux, uy, uz, p.linear_eq);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        fb[i] = feq_rel<L>(i, tdr, trho, tx, ty, tz, p.linear_eq) +
-                (fc[i] - feq_rel<L>(i, dr, rho, ux, uy, uz, p.linear_eq));
+        fb[i] = feq_dir<L>(i, te, tx, ty, tz) + (fc[i] - feq_dir<L>(i, ce, ux, uy, uz));
 }
 
 // Concentrations are stored as an FP32 value and an FP16 remainder per

@@ -32,14 +32,8 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
                                 const float (&f)[L::Q], const PlaneRef &pr, double (&res)[2])
 {
     constexpr int Q = L::Q, D = L::D;
-    float drho = 0, jx = 0, jy = 0, jz = 0;  // drho: rho - 1 - pr.rout
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        drho += f[i];
-        jx += L::ex[i] * f[i];
-        jy += L::ey[i] * f[i];
-        jz += L::ez[i] * f[i];
-    }
+    float drho, jx, jy, jz;  // drho: rho - 1 - pr.rout
+    lat_moments<L>(f, drho, jx, jy, jz);
     if (p.forced) {  // Guo forcing: u = (sum e f + F/2) / rho
         jx += 0.5f * p.F[0];
         jy += 0.5f * p.F[1];
@@ -77,6 +71,7 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
         if (D == 3) stu(b.jout + 2 * (size_t)P, (uint32_t)n, jz);
     }
     if (ST == kMom) return;  // the post-collision state is the equilibrium of Mout
+    const EqTerms eq = eq_terms(drho, rho, ux, uy, uz, p.linear_eq);
     const float om = p.omega;
     // FP16 populations are stored times hs
     const float sc = ST == kH16 ? p.hs : 1.f;
@@ -85,15 +80,15 @@ __device__ __attribute__((always_inline)) inline void lbm_node(const Phys &p, co
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             scatter<L, ST, ODD>(ODD == kPull ? b.f2 : b.f, P, nb, n, i,
-                                sc * stored_pop<L, ODD>(feq_rel<L>(i, drho, rho, ux, uy, uz, p.linear_eq), i, nb, pr));
+                                sc * stored_pop<L, ODD>(feq_dir<L>(i, eq, ux, uy, uz), i, nb, pr));
         return;
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const float fe = feq_rel<L>(i, drho, rho, ux, uy, uz, p.linear_eq);
+        const float fe = feq_dir<L>(i, eq, ux, uy, uz);
         float src = 0.f;
         if (p.forced) {  // Guo, Zheng & Shi (2002) source term
-            const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+            const float eu = lat_dot<L>(i, ux, uy, uz);
             src = p.fcoef * L::w[i] *
                   ((3.f * (L::ex[i] - ux) + 9.f * eu * L::ex[i]) * p.F[0] +
                    (3.f * (L::ey[i] - uy) + 9.f * eu * L::ey[i]) * p.F[1] +

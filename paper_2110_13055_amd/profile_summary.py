@@ -8,9 +8,9 @@ Inputs are the CSV directories of three rocprofv3 runs of the same bench
 command (``--kernel-trace --stats``, ``--pmc FETCH_SIZE``, ``--pmc
 WRITE_SIZE``, all with ``--output-format csv``) and the bench's own stdout
 (for the fluid-node count). The bench command must include
-``--copy-probe-mib N``: one device-to-device copy of N MiB, whose counter
-readings give the scale from each counter to bytes (a copy reads and writes
-exactly N MiB).
+``--copy-probe-mib N``: one pass of the bandwidth probe's streaming copy
+kernel over N MiB, whose counter readings give the scale from each counter
+to bytes (the copy reads and writes exactly N MiB, in 16-byte accesses).
 
 Output: a Markdown table per step-kernel variant (average duration, HBM
 bytes per launch and per fluid node from the counters, achieved GB/s) and a
@@ -30,7 +30,7 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("step.hip", "device_common.h", "cdi_internal.h")
-STORAGE = {"0": "fp32", "1": "fp16_dev", "2": "moments"}
+STORAGE = {"0": "fp32", "1": "fp16_dev", "2": "moments", "3": "fp16"}
 
 
 def kernel_source_hash() -> str:
@@ -78,9 +78,9 @@ def _counters(d, counter):
         if r["Counter_Name"] != counter:
             continue
         v = float(r["Counter_Value"])
-        if "copyBuffer" in r["Kernel_Name"]:
+        if "copy_kernel(" in r["Kernel_Name"]:
             if copy is None or v > copy:
-                copy = v  # the probe is the largest copy of the run
+                copy = v  # the bandwidth probe's streaming copy (the largest of the run)
             continue
         k = _variant(r["Kernel_Name"])
         if k:
@@ -131,7 +131,7 @@ def summarise(trace, fetch, write, bench_log, copy_mib, commands=()):
                   kernels=rows, commands=list(commands))
     md = [f"# Step kernels on the 512^3 electrode ({n_fluid} fluid nodes)", "",
           f"Kernel source hash: `{record['kernel_source_hash']}`.", "",
-          "Counter scale from the copy probe (one device-to-device copy of "
+          "Counter scale from the bandwidth probe's streaming copy kernel (one pass over "
           f"{copy_mib} MiB, which reads and writes exactly that much): FETCH_SIZE x {fscale:.1f} B, "
           f"WRITE_SIZE x {wscale:.1f} B per unit.", "",
           "| kernel | calls | avg ms | HBM read B/node | HBM write B/node | achieved GB/s |",
@@ -289,7 +289,7 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"])
-            if "copyBuffer" in r["Kernel_Name"]:
+            if "copy_kernel(" in r["Kernel_Name"]:
                 copy = v if copy is None or v > copy else copy
                 continue
             k = _solver_kernel(r["Kernel_Name"])
@@ -324,7 +324,7 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
     record = dict(n_fluid=n_fluid, counter_scale={"FETCH_SIZE": fscale, "WRITE_SIZE": wscale},
                   commands=list(commands))
     md = [f"# Iterative solvers on the 512^3 electrode ({n_fluid} fluid nodes)", "",
-          "Counter scale from the copy probe: FETCH_SIZE x "
+          "Counter scale from the bandwidth probe's streaming copy kernel: FETCH_SIZE x "
           f"{fscale:.1f} B, WRITE_SIZE x {wscale:.1f} B per unit. Algorithmic bytes: what each kernel must move "
           "per fluid node; measured: the HBM counters.", ""]
     for key, title, kernels in (("cg", "Potential, Eq. 4-5: Jacobi-PCG iterations of the mixed-precision refinement",

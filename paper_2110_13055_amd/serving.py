@@ -71,6 +71,7 @@ class Result:
     adsorbed: tuple = (math.nan, math.nan)
     balance: tuple = ()
     status: str = "ok"
+    flow_stop: str = ""     # why the flow phase ended: tol, stagnated or step_limit
 
     @property
     def latency_s(self) -> float:
@@ -90,6 +91,7 @@ class _Active:
     best: float = math.inf
     since_best: int = 0
     converged: bool = False
+    stop: str = ""
     work: int = 0        # fluid nodes it adds to each step of its group
 
 
@@ -311,7 +313,7 @@ class Server:
         ads = tuple(np.asarray(out["adsorbed"], dtype=float).tolist()) if "adsorbed" in out else (math.nan,) * 2
         bal = tuple(np.asarray(out["balance"], dtype=float).reshape(-1).tolist()) if "balance" in out else ()
         self.results.append(Result(a.req.rid, a.req.arrival_s, a.admitted_s, self._now(), a.footprint,
-                                   a.flow_steps, a.residual, a.np_done, ads, bal, status))
+                                   a.flow_steps, a.residual, a.np_done, ads, bal, status, a.stop))
         extra = {k: v for k, v in out.items() if k not in ("adsorbed", "balance")}
         if extra:
             self.fields[a.req.rid] = extra
@@ -383,6 +385,8 @@ class Server:
                     elif (a.residual <= a.req.flow_tol or a.since_best >= self.stagnation_rounds
                           or a.flow_steps >= a.req.flow_max_steps):
                         a.converged = a.residual <= a.req.flow_tol
+                        a.stop = ("tol" if a.converged else
+                                  "step_limit" if a.flow_steps >= a.req.flow_max_steps else "stagnated")
                         a.phase = L.MODE_IONS
                         if a.req.np_steps <= 0:
                             retire.append((a, "ok"))
@@ -405,6 +409,7 @@ def latency_stats(results: List[Result], wall_s: float) -> dict:
     short of its tolerance, counted apart too); latency over those."""
     ok = [r for r in results if r.status in ("ok", "ok_unconverged")]
     lat = np.array([r.latency_s for r in ok], dtype=float)
+    unc = np.array([r.residual for r in ok if r.status == "ok_unconverged"], dtype=float)
     return {
         "completed": len(ok),
         "unconverged": sum(1 for r in ok if r.status == "ok_unconverged"),
@@ -414,4 +419,8 @@ def latency_stats(results: List[Result], wall_s: float) -> dict:
         "p50_s": float(np.percentile(lat, 50)) if ok else math.nan,
         "p99_s": float(np.percentile(lat, 99)) if ok else math.nan,
         "mean_s": float(lat.mean()) if ok else math.nan,
+        # how the delivered requests' flow phases ended, and how far the
+        # unconverged ones were from their tolerance
+        "flow_stops": {k: sum(1 for r in ok if r.flow_stop == k) for k in ("tol", "stagnated", "step_limit")},
+        "unconverged_residual_median": float(np.median(unc)) if len(unc) else math.nan,
     }

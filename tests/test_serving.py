@@ -121,7 +121,7 @@ def test_all_served_with_phase_switch_and_step_counts():
     for k, r in out.items():
         decay = 500.0 + 100 * k
         want_flow = 100 * math.ceil(decay * math.log(1e3) / 100)   # first round with exp(-t/decay) <= 1e-3
-        assert r.status == "ok" and r.flow_steps == want_flow
+        assert r.status == "ok" and r.flow_steps == want_flow and r.flow_stop == "tol"
         assert r.residual <= 1e-3
         assert r.np_steps == 1000 and r.adsorbed == (want_flow, 2000.0)
         assert r.finished_s >= r.admitted_s >= r.arrival_s
@@ -136,8 +136,25 @@ def test_flow_budget_caps_the_flow_phase():
     srv, _, _ = serve(reqs, round_steps=100)
     (r,) = srv.run(reqs)
     assert r.status == "ok_unconverged" and r.flow_steps == 300 and r.residual > 1e-3
+    assert r.flow_stop == "step_limit"
     st = latency_stats([r], 1.0)
     assert st["completed"] == 1 and st["unconverged"] == 1 and st["failed"] == 0
+    assert st["flow_stops"] == {"tol": 0, "stagnated": 0, "step_limit": 1}
+    assert st["unconverged_residual_median"] == pytest.approx(r.residual)
+
+
+def test_flow_that_stops_improving_is_marked_stagnated():
+    class Flat(FakeExecutor):
+        def advance(self, groups, modes, n):
+            res, failed = super().advance(groups, modes, n)
+            return {k: np.where(np.isnan(v), v, 0.5) for k, v in res.items()}, failed
+
+    reqs = [req(0, 0.0)]
+    clock = Clock()
+    srv = Server(Flat(clock), clock=clock, sleep=clock.sleep, round_steps=100, stagnation_rounds=3)
+    (r,) = srv.run(reqs)
+    # the first round sets the best residual; three rounds without improvement end the phase
+    assert r.status == "ok_unconverged" and r.flow_stop == "stagnated" and r.flow_steps == 400
 
 
 def test_request_whose_electrode_cannot_be_planned_fails_alone():
