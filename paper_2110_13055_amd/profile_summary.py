@@ -4,9 +4,10 @@
         --trace DIR --fetch DIR --write DIR --bench-log FILE --copy-mib 1024 \\
         --md OUT.md --json OUT.json [--command TEXT ...]
 
-Inputs are the CSV directories of three rocprofv3 runs of the same bench
-command (``--kernel-trace --stats``, ``--pmc FETCH_SIZE``, ``--pmc
-WRITE_SIZE``, all with ``--output-format csv``) and the bench's own stdout
+Inputs are the CSV directories of rocprofv3 runs of the same bench command
+(``--kernel-trace --stats``, ``--pmc FETCH_SIZE``, ``--pmc WRITE_SIZE`` and,
+optionally, ``--pmc TCC_EA0_RDREQ_32B TCC_EA0_RDREQ_64B TCC_EA0_RDREQ_128B``,
+all with ``--output-format csv``) and the bench's own stdout
 (for the fluid-node count). The bench command must include
 ``--copy-probe-mib N``: one pass of the bandwidth probe's streaming copy
 kernel over N MiB, whose counter readings give the scale from each counter
@@ -88,7 +89,24 @@ def _counters(d, counter):
     return {k: sum(v) / len(v) for k, v in per.items()}, copy
 
 
-def summarise(trace, fetch, write, bench_log, copy_mib, commands=()):
+RDREQ = {"TCC_EA0_RDREQ_32B": 32.0, "TCC_EA0_RDREQ_64B": 64.0, "TCC_EA0_RDREQ_128B": 128.0}
+
+
+def _read_requests(d):
+    """Per-variant mean HBM read bytes per dispatch from the L2's memory read
+    requests by size (32, 64 and 128 bytes; exact for the probe's copy, where
+    FETCH_SIZE counts each 128-byte request as 64 bytes)."""
+    per = defaultdict(lambda: defaultdict(list))
+    for r in _csv(_find(d, "counter_collection.csv")):
+        size = RDREQ.get(r["Counter_Name"])
+        k = _variant(r["Kernel_Name"])
+        if size is None or not k:
+            continue
+        per[k][r["Counter_Name"]].append(float(r["Counter_Value"]) * size)
+    return {k: sum(sum(v) / len(v) for v in byname.values()) for k, byname in per.items()}
+
+
+def summarise(trace, fetch, write, bench_log, copy_mib, commands=(), rdreq=None):
     stats = {}
     for r in _csv(_find(trace, "kernel_stats.csv")):
         k = _variant(r["Name"])
@@ -107,14 +125,16 @@ def summarise(trace, fetch, write, bench_log, copy_mib, commands=()):
     copy_bytes = copy_mib * 1024.0 * 1024.0
     fscale = copy_bytes / fcopy  # bytes per counter unit
     wscale = copy_bytes / wcopy
+    rq = _read_requests(rdreq) if rdreq else {}
     rows = []
     for k in sorted(stats):
         calls, dur = stats[k]
-        fb = fr.get(k, float("nan")) * fscale
+        fetch_b = fr.get(k, float("nan")) * fscale
+        fb = rq.get(k, fetch_b)  # the request counts where taken: exact at every request size
         wb = wr.get(k, float("nan")) * wscale
         rows.append(dict(kernel=k, calls=calls, avg_ms=dur * 1e3, read_bytes=fb, write_bytes=wb,
                          read_per_node=fb / n_fluid, write_per_node=wb / n_fluid,
-                         gbs=(fb + wb) / dur / 1e9))
+                         fetch_scaled_per_node=fetch_b / n_fluid, gbs=(fb + wb) / dur / 1e9))
     # bytes per launch of a whole step (the mean of the kernels one step can
     # be: AA even and odd alternate; pull and moment storage use one)
     per_launch = {}
@@ -134,12 +154,15 @@ def summarise(trace, fetch, write, bench_log, copy_mib, commands=()):
           "Counter scale from the bandwidth probe's streaming copy kernel (one pass over "
           f"{copy_mib} MiB, which reads and writes exactly that much): FETCH_SIZE x {fscale:.1f} B, "
           f"WRITE_SIZE x {wscale:.1f} B per unit.", "",
-          "| kernel | calls | avg ms | HBM read B/node | HBM write B/node | achieved GB/s |",
-          "|---|---:|---:|---:|---:|---:|"]
+          ("HBM read bytes: the L2's memory read requests by size (32, 64, 128 B), which are exact for the "
+           "copy; the FETCH_SIZE column is that counter times the copy's scale, which overstates reads made "
+           "of 32- or 64-byte requests." if rq else "HBM read bytes: FETCH_SIZE times the copy's scale."), "",
+          "| kernel | calls | avg ms | HBM read B/node | (FETCH_SIZE scaled) | HBM write B/node | achieved GB/s |",
+          "|---|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
         md.append(f"| {r['kernel']} | {r['calls']} | {r['avg_ms']:.3f} | {r['read_per_node']:.1f} | "
-                  f"{r['write_per_node']:.1f} | {r['gbs']:.0f} |")
-    md += ["", "Commands (repository root; the three runs of the same bench command):", ""]
+                  f"{r['fetch_scaled_per_node']:.1f} | {r['write_per_node']:.1f} | {r['gbs']:.0f} |")
+    md += ["", "Commands (repository root; runs of the same bench command):", ""]
     md += [f"    {c}" for c in commands]
     return record, "\n".join(md) + "\n"
 
@@ -218,11 +241,16 @@ def main():
     ap.add_argument("--md", required=True)
     ap.add_argument("--json", required=True)
     ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--rdreq", default=None,
+                    help="a rocprofv3 --pmc TCC_EA0_RDREQ_32B TCC_EA0_RDREQ_64B TCC_EA0_RDREQ_128B run "
+                         "of the same command (exact read bytes)")
     ap.add_argument("--potential", action="store_true",
                     help="summarise the potential-solve kernels (bench.py --potential-only)")
     a = ap.parse_args()
-    fn = summarise_potential if a.potential else summarise
-    rec, md = fn(a.trace, a.fetch, a.write, a.bench_log, a.copy_mib, a.command)
+    if a.potential:
+        rec, md = summarise_potential(a.trace, a.fetch, a.write, a.bench_log, a.copy_mib, a.command, a.rdreq)
+    else:
+        rec, md = summarise(a.trace, a.fetch, a.write, a.bench_log, a.copy_mib, a.command, a.rdreq)
     with open(a.json, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
@@ -263,7 +291,7 @@ def _solver_kernel(name: str):
     return None
 
 
-def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
+def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=(), rdreq=None):
     """Per-iteration kernels of the potential solve (Jacobi-PCG) and of the
     implicit ion solve (BiCGSTAB): mean duration, HBM bytes per fluid node and
     GB/s over the dispatches that did work (launches after the device-side
@@ -302,10 +330,28 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
             out[k] = sum(work) / len(work)
         return out, copy
 
+    def read_requests(d):
+        per = defaultdict(float)
+        for r in _csv(_find(d, "counter_collection.csv")):
+            size = RDREQ.get(r["Counter_Name"])
+            k = _solver_kernel(r["Kernel_Name"])
+            if size is not None and k:
+                per[(k, r["Dispatch_Id"])] += float(r["Counter_Value"]) * size
+        byk = defaultdict(list)
+        for (k, _), v in per.items():
+            byk[k].append(v)
+        out = {}
+        for k, v in byk.items():
+            top = max(v)
+            work = [x for x in v if x >= 0.05 * top]
+            out[k] = sum(work) / len(work)
+        return out
+
     fr, fcopy = counters(fetch, "FETCH_SIZE")
     wr, wcopy = counters(write, "WRITE_SIZE")
     copy_bytes = copy_mib * 1024.0 * 1024.0
     fscale, wscale = copy_bytes / fcopy, copy_bytes / wcopy
+    rq = read_requests(rdreq) if rdreq else {}
 
     def group(kernels):
         rows = []
@@ -315,7 +361,7 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
             top = max(durs[k])
             work = [x for x in durs[k] if x >= 0.05 * top]
             dur = sum(work) / len(work)
-            fb, wb = fr.get(k, float("nan")) * fscale, wr.get(k, float("nan")) * wscale
+            fb, wb = rq.get(k, fr.get(k, float("nan")) * fscale), wr.get(k, float("nan")) * wscale
             rows.append(dict(kernel=k, role=role, dispatches=len(work), avg_ms=dur * 1e3, alg_per_node=alg,
                              read_per_node=fb / n_fluid, write_per_node=wb / n_fluid, gbs=(fb + wb) / dur / 1e9,
                              alg_gbs=alg * n_fluid / dur / 1e9))
@@ -326,7 +372,9 @@ def summarise_potential(trace, fetch, write, bench_log, copy_mib, commands=()):
     md = [f"# Iterative solvers on the 512^3 electrode ({n_fluid} fluid nodes)", "",
           "Counter scale from the bandwidth probe's streaming copy kernel: FETCH_SIZE x "
           f"{fscale:.1f} B, WRITE_SIZE x {wscale:.1f} B per unit. Algorithmic bytes: what each kernel must move "
-          "per fluid node; measured: the HBM counters.", ""]
+          "per fluid node; measured: the HBM counters"
+          + (" (reads: the L2's memory read requests by size, exact at every size)." if rq else
+             " (reads: FETCH_SIZE times the copy's scale)."), ""]
     for key, title, kernels in (("cg", "Potential, Eq. 4-5: Jacobi-PCG iterations of the mixed-precision refinement",
                                  POT_KERNELS),
                                 ("cg64", "Potential: the same CG on FP64 vectors alone (fp64 = 1)", POT64_KERNELS),
