@@ -352,8 +352,10 @@ int cdi_batch_members(const cdi_batch *b, int32_t *n);
 /* Advance every member by nsteps in its mode (host array modes[n]):
  *   FLOW  = cdi_flow_steps, IONS = cdi_np_step(fused 0), FUSED = cdi_np_step(fused 1),
  *   IDLE  = untouched.
- * Like cdi_np_step, IONS/FUSED members are checked once for positivity
- * (UNSTABLE names the first failing member and nothing is stepped). Runs of
+ * Like cdi_np_step, IONS/FUSED members are checked for positivity first
+ * (UNSTABLE names the first failing member and nothing is stepped) and, when
+ * a member is FUSED, again at least every 256 steps (UNSTABLE then after the
+ * steps already taken, state valid). Runs of
  * identical steps are replayed from a captured HIP graph. FLOW members also get
  * the residual of their last step (see cdi_batch_residuals) when nsteps >= 2.
  * Asynchronous except for the positivity check. */

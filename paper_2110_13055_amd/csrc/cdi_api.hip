@@ -2085,11 +2085,12 @@ int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
     if (!bt || nsteps < 0) return fail(CDI_E_INVALID, "bad arguments");
     if (nsteps == 0 || bt->n == 0) return CDI_OK;
     if (!modes) return fail(CDI_E_INVALID, "modes is NULL");
-    bool any_flow = false, need_first = false;
+    bool any_flow = false, any_fused = false, need_first = false;
     for (int k = 0; k < bt->n; ++k) {
         const int md = modes[k];
         cdi_solver *s = bt->m[k];
         if (md < kModeIdle || md > kModeFused) return fail(CDI_E_INVALID, "bad mode for member %d", k);
+        if (md == kModeFused) any_fused = true;
         if ((md == kModeIons || md == kModeFused) && s->params.np_substeps != 1)
             return fail(CDI_E_INVALID, "member %d: batched ion steps need np_substeps = 1", k);
         if (md == kModeFlow) any_flow = true;
@@ -2097,6 +2098,22 @@ int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
         if (md == kModeFused && s->mb) need_first = true;
         // a pending renewal of the plane references applies to one step only
         if ((md == kModeFlow || md == kModeFused) && s->rpend) need_first = true;
+    }
+    if (any_fused && nsteps > kFusedRecheck) {
+        // the flow keeps changing under fused steps: as cdi_np_step, the
+        // positivity bound is taken again every kFusedRecheck steps (each
+        // chunk checks it first). The last chunk keeps at least two steps, so
+        // flow members end with their residual as from one call; the steps
+        // themselves do not depend on the chunking.
+        int64_t left = nsteps;
+        while (left > 0) {
+            int64_t c = left > kFusedRecheck ? kFusedRecheck : left;
+            if (left - c == 1) --c;
+            const int rc = cdi_batch_advance(bt, c, modes);
+            if (rc != CDI_OK) return rc;
+            left -= c;
+        }
+        return CDI_OK;
     }
     // order after the members' own streams
     for (int k = 0; k < bt->n; ++k) HIPCHK(hipStreamSynchronize(bt->m[k]->stream));

@@ -74,6 +74,36 @@ def test_batch_equals_members_stepped_alone(precision):
             assert np.array_equal(a, c), f"member {k}"
 
 
+@pytest.mark.parametrize("precision", [L.FP32, L.MOMENTS])
+def test_long_fused_advance_rechecked_in_chunks_equals_alone(precision):
+    # more than 256 fused steps in one call: the batch takes the positivity
+    # bound again every 256 steps (chunks of 256 and 44, then 255 and 2); the
+    # steps, and so the results, are those of each member stepped alone
+    specs = members(precision, n=3)
+    sched = [(3, [FLOW, FLOW, FLOW]), (300, [FUSED, FLOW, FUSED]), (257, [FUSED, IONS, FLOW])]
+    alone = []
+    for k, (g, p) in enumerate(specs):
+        s = Solver(g, p)
+        for n, modes in sched:
+            m = modes[k]
+            if m == FLOW:
+                s.flow_steps(n)
+            elif m == IONS:
+                s.np_step(n, fused=False)
+            else:
+                s.np_step(n, fused=True)
+        alone.append(state(s))
+    solvers = [Solver(g, p) for g, p in specs]
+    b = Batch(solvers)
+    for n, modes in sched:
+        b.advance(n, modes)
+    b.synchronize()
+    for k, s in enumerate(solvers):
+        for a, c in zip(alone[k], state(s)):
+            assert np.array_equal(a, c), f"member {k}"
+    assert np.isfinite(b.residuals()[2])   # the flow member's residual of the chunked call
+
+
 @pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV])
 def test_batch_mixing_aa_and_pull_members(precision):
     specs = members(precision)
