@@ -385,8 +385,9 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
-    ap.add_argument("--streaming", choices=("pull", "aa"), default="pull",
-                    help="population streaming of the FP32 / FP16 forms")
+    ap.add_argument("--streaming", choices=("aa", "pull"), default="aa",
+                    help="population streaming of the FP32 / FP16 forms: AA (one array, in place) "
+                         "or pull (two arrays)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--no-probe", action="store_true", help="skip the streaming bandwidth probe")
     ap.add_argument("--no-potential", action="store_true", help="skip the potential-solve leg")

@@ -198,13 +198,14 @@ def test_unstable_member_is_reported():
     assert e.value.code == L.E_UNSTABLE and "member 1" in str(e.value)
 
 
-def test_full_size_batch_of_64_instances():
+@pytest.mark.parametrize("streaming", [L.STREAM_AA, L.STREAM_PULL], ids=["aa", "pull"])
+def test_full_size_batch_of_64_instances(streaming):
     # the bench's batched workload at its full size (64 cubes of edge 48-160,
-    # 49.5M fluid nodes) in its launch configuration: FP32, pull streaming,
-    # autotuned grid, graph-replayed fused step pairs. Every member equals the
-    # same instance stepped alone, bit for bit; the smallest one also matches
-    # the oracle.
-    specs = P.batch_instances(64, precision=L.FP32, streaming=L.STREAM_PULL)
+    # 49.5M fluid nodes) in its launch configuration: FP32, AA streaming (the
+    # bench's default; pull too), autotuned grid, graph-replayed fused step
+    # pairs. Every member equals the same instance stepped alone, bit for bit;
+    # the smallest one also matches the oracle.
+    specs = P.batch_instances(64, precision=L.FP32, streaming=streaming)
     n = len(specs)
     solvers = [Solver(g, p) for g, p in specs]
     for s in solvers:

@@ -1,6 +1,7 @@
-"""Parity at the full 512^3 size, in the configuration the bench times (pull
+"""Parity at the full 512^3 size, in the configuration the bench times (AA
 streaming, fused LBM + ion steps, default tuning; FP32, FP16 deviation and
-moment storage, which at tau = 1 meet the FP32 bars).
+moment storage, which at tau = 1 meet the FP32 bars; FP32 also with pull
+streaming).
 
 The oracle cannot step 134M voxels, but one step of the method reads only a
 node's neighbours: after T steps from the rest state, a node's values depend on
@@ -36,7 +37,7 @@ REACH = T + 2                # cells a boundary's influence can travel, with a m
 
 
 def _setup():
-    g, p, _ = P.preset("spheres3d_512", precision=L.FP32, streaming=L.STREAM_PULL)
+    g, p, _ = P.preset("spheres3d_512", precision=L.FP32, streaming=L.STREAM_AA)
     lab = oracle_labels(g)
     _, fl = oracle.compact(lab)
     # the default K_a depends on the porosity of the whole electrode; both
@@ -76,11 +77,15 @@ def reference():
     return dict(g=g, p=p, lab=lab, fl=fl, x=x, slabs=out)
 
 
-@pytest.fixture(scope="module", params=[L.FP32, L.FP16_DEV, L.MOMENTS], ids=["fp32", "fp16_dev", "moments"])
+@pytest.fixture(scope="module",
+                params=[(L.FP32, L.STREAM_AA), (L.FP32, L.STREAM_PULL), (L.FP16_DEV, L.STREAM_AA),
+                        (L.MOMENTS, L.STREAM_AA)],
+                ids=["fp32_aa", "fp32_pull", "fp16_dev_aa", "moments"])
 def gpu_run(request, reference):
-    g, p = reference["g"], dataclasses.replace(reference["p"], precision=request.param)
+    prec, strm = request.param
+    g, p = reference["g"], dataclasses.replace(reference["p"], precision=prec, streaming=strm)
     s = P.Solver(g, p)
-    if request.param == L.FP32:
+    if prec == L.FP32:
         assert np.array_equal(s.labels(), reference["lab"])
         m, f = s.fluid_index()
         del m
