@@ -480,6 +480,10 @@ def main():
     if not args.no_probe:
         log("bandwidth probe")
         out["hbm_probe"] = hbm_probe()
+        # the same achieved rate against what a plain copy attains on this GPU
+        cp = out["hbm_probe"]["copy_gbs"]
+        out["roofline"]["attainable_copy_gbs"] = cp
+        out["roofline"]["frac_of_copy"] = round(achieved / cp, 4)
     if not args.no_potential:
         log("potential")
         out["potential"] = potential_rates()

@@ -125,12 +125,13 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
         nb[0] = n;
         // the list, when the instance has one, for the steps that carry the ions
-        // (measured: ion-only -4 %, fused moments -5 %, FP16 -3 %); the fused
-        // FP32 step runs equally fast either way and moves 59 B/node less
+        // (measured on the 512^3 electrode: ion-only -6 %, fused moments -5 %,
+        // FP16 deviations -3 %, FP16 populations -1.5 % AA / -5.5 % pull); the
+        // fused FP32 step runs equally fast either way and moves 59 B/node less
         // without it, and flow-only steps stream their populations at the copy
         // rate already and only pay for the list's bytes (+10 %): those two
         // look their neighbours up
-        constexpr bool kList = NP && !(LBM && kPlain<ST>);
+        constexpr bool kList = NP && !(LBM && ST == kF32);
         if (kList && g.nbr) {  // precomputed: independent of the coordinates
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
