@@ -692,8 +692,13 @@ int cdi_plan(const cdi_geometry *geom, const cdi_params *params, cdi_plan_info *
     const int st = params ? params->precision : CDI_FP32;
     const int pull = params ? params->streaming == CDI_STREAM_PULL : 0;
     const int Q = dim == 2 ? 9 : 19;
+    // the per-node arrays of node_layout: populations, moments, flux (two
+    // sets), previous velocity and density, concentrations and remainders,
+    // scratch, host staging, potential and the neighbour list; plus about
+    // 1 B for the per-tile sums and the schedule
     out->node_bytes_per_fluid = (uint64_t)Q * pop_bytes(st) * (pull ? 2 : 1) + (moment_buffers(st) ? 32 : 0) +
-                                12ull * dim + 4 + 16 + 8 + 4ull * (1 + dim) + 4ull * (Q - 1) + 1;
+                                8ull * dim + 4ull * (dim + 1) + 16 + 8 + 4ull * (1 + dim) + 16 + 4 +
+                                4ull * (Q - 1) + 1;
     g_err[0] = 0;
     return CDI_OK;
 }

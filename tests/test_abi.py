@@ -98,3 +98,26 @@ def test_struct_layouts_match_the_binding():
     n = C.c_uint64()
     assert lib.cdi_struct_size(b"cdi_nothing", C.byref(n)) == L.E_INVALID
     assert lib.cdi_struct_size(None, C.byref(n)) == L.E_INVALID
+
+
+@pytest.mark.parametrize("preset", ["channel2d_128x64", "spheres3d_64"])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+@pytest.mark.parametrize("streaming", [0, 1])
+def test_plan_node_bytes_match_the_workspace_it_sizes(preset, precision, streaming):
+    # the plan's per-node estimate (serving admission sizes requests with it)
+    # against the exact node workspace for the planned node count (host only)
+    import paper_2110_13055_amd as P
+    from paper_2110_13055_amd import _lib as L
+    g, p, _ = P.preset(preset, precision=precision, streaming=streaming)
+    if precision == L.MOMENTS and streaming:
+        pytest.skip("moment storage has no population arrays to stream")
+    info = P.plan(g, p)
+    nb = C.c_uint64()
+    gc, _keep = g.to_c()
+    pc = p.to_c()
+    L.check(L.load().cdi_node_bytes(C.byref(gc), C.byref(pc), C.c_int64(info.n_fluid_est), C.byref(nb)),
+            "cdi_node_bytes")
+    bpf = info.node_bytes_per_fluid
+    est = bpf * info.n_fluid_est
+    # within 3 %, up to one 256-node tile of rounding and the per-instance scratch
+    assert 0.97 * nb.value - 256 * bpf - 16384 <= est <= 1.05 * nb.value + 65536, (est, nb.value)
