@@ -209,11 +209,14 @@ def potential_rates(coupled_steps: int = 10):
     return out
 
 
-def batched_rates(steps: int, streaming: int, n: int = 64):
+def batched_rates(steps: int, streaming: int, n: int = 64, flow_steps: int = 1000, ion_steps: int = 500):
     """Batched stepping of n uneven instances (cubes of edge 48-160, own seed,
     porosity, potential and inlet velocity): the fused step of all instances
     in one persistent launch per step (graph-replayed, grid size autotuned),
-    against the same steps run instance by instance with the plain solver."""
+    against the same steps run instance by instance with the plain solver;
+    and whole solves of a fixed protocol (flow_steps flow steps, then
+    ion_steps ion steps on the frozen flow), batched in FP32 and with moment
+    storage, against the n plain FP32 solves one after the other."""
     import torch
     import paper_2110_13055_amd as P
     out = {"instances": n}
@@ -241,6 +244,30 @@ def batched_rates(steps: int, streaming: int, n: int = 64):
         torch.cuda.empty_cache()
     for name in ("fp32", "fp16_dev", "moments"):
         out[f"{name}_batched_vs_fp32_sequential"] = round(out[f"{name}_batched_mlups"] / out["fp32_sequential_mlups"], 3)
+    out["solve_protocol"] = f"{flow_steps} flow + {ion_steps} ion steps per instance, from rest"
+    for prec, name in ((P.FP32, "fp32"), (P.MOMENTS, "moments")):
+        solvers = [P.Solver(g, p) for g, p in P.batch_instances(n, precision=prec, streaming=streaming)]
+        b = P.Batch(solvers)
+
+        def batched_solves():
+            b.advance(flow_steps, [P.MODE_FLOW] * n)
+            b.advance(ion_steps, [P.MODE_IONS] * n)
+        out[f"solves_{name}_batched_s"] = round(time_region(batched_solves, b.stream), 3)
+        b.close()
+        del b, solvers
+        torch.cuda.empty_cache()
+    solvers = [P.Solver(g, p) for g, p in P.batch_instances(n, precision=P.FP32, streaming=streaming)]
+
+    def sequential_solves():
+        for s in solvers:
+            s.flow_steps(flow_steps)
+            s.np_step(ion_steps, fused=False)
+    ts = time_region(sequential_solves, solvers[0].stream)
+    out["solves_fp32_sequential_s"] = round(ts, 3)
+    for name in ("fp32", "moments"):
+        out[f"solves_{name}_batched_vs_fp32_sequential"] = round(ts / out[f"solves_{name}_batched_s"], 3)
+    del solvers
+    torch.cuda.empty_cache()
     return out
 
 

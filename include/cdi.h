@@ -365,7 +365,9 @@ int cdi_batch_advance(cdi_batch *b, int64_t nsteps, const int32_t *modes);
  * for FLOW members, NaN for the others. Synchronises. */
 int cdi_batch_residuals(cdi_batch *b, double *r);
 
-/* Persistent grid size (0 = 4 workgroups per compute unit) and occupancy cap. */
+/* Grid size of the batched launches (0, the default: one workgroup per tile
+ * of each step class; fewer make the workgroups persistent, each taking
+ * every G-th tile of its XCD's share) and occupancy cap. */
 int cdi_batch_set_launch(cdi_batch *b, int32_t workgroups, int32_t blocks_per_cu);
 int cdi_batch_get_launch(const cdi_batch *b, int32_t *workgroups, int32_t *blocks_per_cu);
 
