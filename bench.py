@@ -18,7 +18,7 @@ record holds for the current kernel sources); ``cpu_baseline`` is the FP64
 reference on this host's cores, on a bounded sample (the seeded 64^3
 sub-case). Beside them: ``potential`` (the Poisson solve of Eq. 4-5, a
 coupled PNP step, and the steady ion state by the implicit solver, on the
-same electrode), ``batched`` (64 uneven electrodes in one persistent launch
+same electrode), ``batched`` (64 uneven electrodes in one launch
 per step) and ``serving`` (a Poisson arrival trace through the continuous-
 batching server). --potential-only runs the solver leg alone.
 """
@@ -212,7 +212,7 @@ def potential_rates(coupled_steps: int = 10):
 def batched_rates(steps: int, streaming: int, n: int = 64, flow_steps: int = 1000, ion_steps: int = 500):
     """Batched stepping of n uneven instances (cubes of edge 48-160, own seed,
     porosity, potential and inlet velocity): the fused step of all instances
-    in one persistent launch per step (graph-replayed, grid size autotuned),
+    in one launch per step class (graph-replayed, grid size autotuned),
     against the same steps run instance by instance with the plain solver;
     and whole solves of a fixed protocol (flow_steps flow steps, then
     ion_steps ion steps on the frozen flow), batched in FP32 and with moment

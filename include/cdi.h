@@ -305,7 +305,7 @@ int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *c
 
 /* ------------------------------------------------------------ batches
  * Many independent electrodes (uneven sizes, own parameters) advanced by one
- * persistent launch per step. Members must share the device, the stream, the
+ * launch per step class. Members must share the device, the stream, the
  * dimension and the storage precision. Each member's results are bitwise
  * identical to advancing that member alone with the same sequence of calls
  * (tile results do not depend on which workgroup computes them). */
@@ -371,7 +371,7 @@ int cdi_batch_residuals(cdi_batch *b, double *r);
 int cdi_batch_set_launch(cdi_batch *b, int32_t workgroups, int32_t blocks_per_cu);
 int cdi_batch_get_launch(const cdi_batch *b, int32_t *workgroups, int32_t *blocks_per_cu);
 
-/* Autotuner for the persistent launch: snapshots all members, times candidate
+/* Autotuner for the batched launches' grid size: snapshots all members, times candidate
  * grid sizes over `steps` steps of the given modes, restores every member and
  * keeps the fastest. Synchronises. */
 int cdi_batch_autotune(cdi_batch *b, int32_t steps, const int32_t *modes, int32_t *workgroups,
