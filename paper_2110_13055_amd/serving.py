@@ -116,6 +116,7 @@ class GpuExecutor:
         self.max_members, self.max_fluid, self.max_drho = int(max_members), int(max_fluid), float(max_drho)
         self.streams: Dict[tuple, object] = {}
         self._batches: Dict[tuple, object] = {}   # group -> Batch with room to admit
+        self._planned = (None, None)               # the last request planned and its plan
 
     def _stream(self, key):
         if key not in self.streams:
@@ -127,14 +128,19 @@ class GpuExecutor:
         ok, est, msg = self.flow_check(req.geom, req.params, self.max_drho)
         return ok, msg
 
+    def _plan(self, req: Request):
+        if self._planned[0] != req.rid:
+            self._planned = (req.rid, self.plan(req.geom, req.params))
+        return self._planned[1]
+
     def footprint_estimate(self, req: Request) -> int:
-        info = self.plan(req.geom, req.params)
+        info = self._plan(req)
         return int(info.vox_bytes + info.node_bytes_per_fluid * max(info.n_fluid_est, 1) * 1.1
                    + self.OVERHEAD)
 
     def work_estimate(self, req: Request) -> int:
         """Fluid nodes the request would add to a step (the plan's estimate)."""
-        return int(self.plan(req.geom, req.params).n_fluid_est)
+        return int(self._plan(req).n_fluid_est)
 
     def work(self, handle) -> int:
         return int(handle.n_fluid)
@@ -236,6 +242,7 @@ class Server:
         # admitted): past what fills the GPU, batching more only time-slices it
         self.max_active_nodes = float(max_active_nodes)
         self.active_nodes = 0
+        self._est: Dict[int, object] = {}   # queued request -> (footprint, work) or a rejection
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
         self.queue: List[Request] = []
@@ -253,36 +260,51 @@ class Server:
         return self.clock() - self.t0
 
     # ------------------------------------------------------------ admission
+    def _estimates(self, req: Request):
+        """(footprint, work) of a queued request, or a rejection message. The
+        host-side check and plan run once per request; a head of the queue
+        that waits for room is not planned again every round."""
+        if req.rid in self._est:
+            return self._est[req.rid]
+        check = getattr(self.ex, "check", None)
+        out = None
+        if check is not None:
+            ok, msg = check(req)
+            if not ok:  # refused before it takes a slot
+                out = f"rejected: unstable flow: {msg}"
+        if out is None:
+            try:
+                est = self.ex.footprint_estimate(req)
+                work_estimate = getattr(self.ex, "work_estimate", None)
+                out = (est, work_estimate(req) if work_estimate is not None else 0)
+            except Exception as exc:  # e.g. its electrode cannot be generated: refused, nothing else affected
+                out = f"rejected: {exc}"
+        self._est[req.rid] = out
+        return out
+
     def _admit(self):
         while self.queue and len(self.active) < self.max_slots:
             req = self.queue[0]
             now = self._now()
-            check = getattr(self.ex, "check", None)
-            if check is not None:
-                ok, msg = check(req)
-                if not ok:  # refused before it takes a slot
-                    self.queue.pop(0)
-                    self.results.append(Result(req.rid, req.arrival_s, now, now, 0,
-                                               status=f"rejected: unstable flow: {msg}"))
-                    continue
-            try:
-                est = self.ex.footprint_estimate(req)
-            except Exception as exc:  # e.g. its electrode cannot be generated: refused, nothing else affected
+            est = self._estimates(req)
+            if isinstance(est, str):
                 self.queue.pop(0)
-                self.results.append(Result(req.rid, req.arrival_s, now, now, 0, status=f"rejected: {exc}"))
+                self._est.pop(req.rid, None)
+                self.results.append(Result(req.rid, req.arrival_s, now, now, 0, status=est))
                 continue
+            est, work_est = est
             if est > self.budget:
                 self.queue.pop(0)
+                self._est.pop(req.rid, None)
                 self.results.append(Result(req.rid, req.arrival_s, now, now, est,
                                            status="rejected: footprint exceeds the budget"))
                 continue
             if self.used + est > self.budget:
                 break  # FIFO: wait until retirements free memory
-            work_estimate = getattr(self.ex, "work_estimate", None)
-            if (self.active and work_estimate is not None
-                    and self.active_nodes + work_estimate(req) > self.max_active_nodes):
+            if self.active and self.active_nodes + work_est > self.max_active_nodes:
                 break  # FIFO: wait until the active work drops
             self.queue.pop(0)
+            self._est.pop(req.rid, None)
             try:
                 h = self.ex.start(req)
             except Exception as exc:  # a failed request retires only itself

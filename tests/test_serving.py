@@ -254,6 +254,28 @@ def test_active_node_cap_binds_fifo_and_admits_an_oversize_first():
     assert srv.active_nodes == 0 and all(r.status == "ok" for r in srv.results)
 
 
+def test_a_waiting_head_is_planned_once():
+    # the head of the queue waits for memory over many rounds; its host-side
+    # check and plan run once, not every round
+    class Counting(FakeExecutor):
+        def __init__(self, clock):
+            super().__init__(clock)
+            self.calls = {}
+
+        def footprint_estimate(self, r):
+            self.calls[r.rid] = self.calls.get(r.rid, 0) + 1
+            return super().footprint_estimate(r)
+
+    reqs = [req(0, 0.0, nbytes=8e9, decay=3000.0), req(1, 0.0, nbytes=8e9), req(2, 0.0, nbytes=1e9)]
+    clock = Clock()
+    ex = Counting(clock)
+    srv = Server(ex, budget_bytes=10e9, round_steps=100, clock=clock, sleep=clock.sleep)
+    srv.run(reqs)
+    assert srv.rounds > 20 and ex.started == [0, 1, 2]
+    assert ex.calls == {0: 1, 1: 1, 2: 1}
+    assert not srv._est
+
+
 def test_continuous_batching_refills_freed_slots():
     # short and long requests: a short one's slot is reused before the long one ends
     reqs = [req(0, 0.0, decay=5000.0), req(1, 0.0, decay=100.0), req(2, 0.0, decay=100.0)]
