@@ -1728,6 +1728,7 @@ struct cdi_batch {
     double *dred = nullptr;      // device, 2 per member slot
     BatchInst *hstage = nullptr; // pinned host, kSlots * cap_n
     int2 *htiles = nullptr;      // pinned host, kSlots * cap_tiles
+    double *hworst = nullptr;    // pinned host, cap_n: the members' positivity bounds
     int cls_begin[kSlots][kClasses + 1] = {};
     std::vector<int> resid_valid;
     hipGraphExec_t exec = nullptr;
@@ -1952,6 +1953,7 @@ int batch_new(cdi_solver *const *members, int32_t n, int cap_n, int64_t cap_tile
     auto cleanup = [&](int code) {
         if (bt->hstage) (void)hipHostFree(bt->hstage);
         if (bt->htiles) (void)hipHostFree(bt->htiles);
+        if (bt->hworst) (void)hipHostFree(bt->hworst);
         if (bt->done) (void)hipEventDestroy(bt->done);
         delete bt;
         return code;
@@ -1964,6 +1966,8 @@ int batch_new(cdi_solver *const *members, int32_t n, int cap_n, int64_t cap_tile
         return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
     if (hipHostMalloc((void **)&bt->htiles, 8ull * kSlots * (size_t)bt->cap_tiles, hipHostMallocDefault) !=
         hipSuccess)
+        return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
+    if (hipHostMalloc((void **)&bt->hworst, 8ull * cap_n, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "pinned staging allocation failed"));
     if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
         return cleanup(fail(CDI_E_DEVICE, "event creation failed"));
@@ -2058,6 +2062,7 @@ int cdi_batch_destroy(cdi_batch *bt)
     if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
     if (bt->hstage) (void)hipHostFree(bt->hstage);
     if (bt->htiles) (void)hipHostFree(bt->htiles);
+    if (bt->hworst) (void)hipHostFree(bt->hworst);
     if (bt->done) (void)hipEventDestroy(bt->done);
     delete bt;
     return CDI_OK;
@@ -2127,14 +2132,26 @@ int cdi_batch_advance(cdi_batch *bt, int64_t nsteps, const int32_t *modes)
     // order after the members' own streams
     for (int k = 0; k < bt->n; ++k) HIPCHK(hipStreamSynchronize(bt->m[k]->stream));
     HIPCHK(hipStreamSynchronize(bt->stream));
-    // positivity of the ion updates, as cdi_np_step (the flux field is made valid on the member's stream)
+    // positivity of the ion updates, as cdi_np_step (the flux field is made
+    // valid on the member's stream): every member's check is queued on its
+    // stream first and all are read after one wait per member, instead of a
+    // round trip to the host per member
+    bool any_ions = false;
     for (int k = 0; k < bt->n; ++k) {
         if (modes[k] != kModeIons && modes[k] != kModeFused) continue;
-        double worst = 0;
-        int rc = check_stability(bt->m[k], &worst);
+        cdi_solver *s = bt->m[k];
+        int rc = ensure_j(s);
         if (rc) return rc;
-        if (!(worst <= 1.0))
-            return fail(CDI_E_UNSTABLE, "member %d: positivity bound violated (%g > 1)", k, worst);
+        HIPCHK(launch_stability(s->dim, s->g, s->p, s->node.j[s->jcur], s->node.part, s->node.red, s->stream));
+        HIPCHK(hipMemcpyAsync(bt->hworst + k, s->node.red, 8, hipMemcpyDeviceToHost, s->stream));
+        any_ions = true;
+    }
+    if (any_ions) {
+        for (int k = 0; k < bt->n; ++k)
+            if (modes[k] == kModeIons || modes[k] == kModeFused) HIPCHK(hipStreamSynchronize(bt->m[k]->stream));
+        for (int k = 0; k < bt->n; ++k)
+            if ((modes[k] == kModeIons || modes[k] == kModeFused) && !(bt->hworst[k] <= 1.0))
+                return fail(CDI_E_UNSTABLE, "member %d: positivity bound violated (%g > 1)", k, bt->hworst[k]);
     }
     const bool want_resid = any_flow && nsteps >= 2;
     const int64_t suffix = want_resid ? 2 : 0;
