@@ -362,7 +362,7 @@ def serving_run(n_requests: int, precision: int, slots: int, streaming: int, hor
     ex.close()
     torch.cuda.empty_cache()
     st = latency_stats(res, wall)
-    st = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    st = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()}  # 4 significant digits
     st.update(failures=[f"{r.rid}: {r.status[:60]}" for r in res if r.status.startswith("failed")],
               rejected_ids=[r.rid for r in res if r.status.startswith("rejected")])
     st.update(wall_s=round(wall, 2), backlog=srv.backlog, peak_slots=srv.peak_slots,

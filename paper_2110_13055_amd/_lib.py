@@ -171,6 +171,10 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_2110_13055_amd.build`")
+        # torch first: its HIP runtime must be the one the library binds to
+        # (loaded before torch, the library would bind the system runtime and
+        # share no device state, pointers or streams with torch's)
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
