@@ -187,7 +187,7 @@ def potential_rates(coupled_steps: int = 10):
     # the steady ion state on this flow and potential (implicit scheme),
     # BiCGSTAB to 1e-8; per iteration both species (directions stored
     # preconditioned): direction 72 B (r, v, p^, diagonal; p^ written), two
-    # operator applications 78 + 70 B (own vectors, coordinates, map, flux
+    # operator applications 78 + 70 B (own vectors, neighbour indices, flux
     # and potential; the second also the diagonal), s^ 56 B, update 120 B per
     # fluid node
     per_it_np = 72 + 78 + 56 + 70 + 120

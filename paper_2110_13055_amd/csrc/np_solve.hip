@@ -79,16 +79,23 @@ __device__ inline void np_node(const Grid &g, const Phys &p, const float *j, int
 {
     constexpr int D = L::D;
     const int P = g.P;
-    int x, y, z;
-    unpack_xyz(g, ldu(g.fluid, (uint32_t)n), x, y, z);
-    NbCtx ctx;
-    nb_ctx<L>(g, x, y, z, p.npx == kNpxPeriodic, ctx);
     // every load is issued before the per-face branches (a load inside a
     // divergent branch waits for its data before the next face starts): the
     // six neighbours, then the flux (and potential) of each, at the node
-    // itself where the face is not fluid
+    // itself where the face is not fluid. The neighbours come from the list
+    // when the instance has one built with the ions' x periodicity (read
+    // with the node's data), else through the coordinates and the map.
+    if (g.nbr && (p.npx == kNpxPeriodic) == (g.periodic_x != 0)) {
 #pragma unroll
-    for (int k = 0; k < 2 * D; ++k) c.m[k] = nb_get<L>(g, ctx, k + 1);
+        for (int k = 0; k < 2 * D; ++k) c.m[k] = ldu(g.nbr + (size_t)k * P, (uint32_t)n);
+    } else {
+        int x, y, z;
+        unpack_xyz(g, ldu(g.fluid, (uint32_t)n), x, y, z);
+        NbCtx ctx;
+        nb_ctx<L>(g, x, y, z, p.npx == kNpxPeriodic, ctx);
+#pragma unroll
+        for (int k = 0; k < 2 * D; ++k) c.m[k] = nb_get<L>(g, ctx, k + 1);
+    }
     float jP[3], jN[2 * D], psiN[2 * D];
     jP[0] = ldu(j, (uint32_t)n);
     jP[1] = ldu(j + P, (uint32_t)n);
