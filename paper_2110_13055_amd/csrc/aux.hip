@@ -205,6 +205,25 @@ __global__ __launch_bounds__(kTile) void stability_kernel(Grid g, Phys p, const 
         unpack_xyz(g, g.fluid[n], x, y, z);
         const int P = g.P;
         const float psiP = p.psi ? p.psi[n] : 0.f;
+        // the faces' neighbours, then their flux and potential, all loaded
+        // before the species' face loops (a load inside a divergent branch
+        // waits for its data before the next face starts); across an x end
+        // the periodic neighbour, used only by periodic ions
+        int mf[2 * D];
+        float jN[2 * D], psiN[2 * D];
+#pragma unroll
+        for (int k = 0; k < 2 * D; ++k) {
+            const int sgi = (k & 1) ? -1 : 1;
+            const bool xb = k < 2 && (x + sgi < 0 || x + sgi >= g.nx);
+            mf[k] = (g.nbr && !xb) ? g.nbr[(size_t)k * P + n]
+                                   : nb_map<L>(g, x, y, z, k + 1, xb ? true : (bool)g.periodic_x);
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * D; ++k) {
+            const int q = mf[k] >= 0 ? mf[k] : n;
+            jN[k] = j[(size_t)(k >> 1) * P + q];
+            psiN[k] = p.psi ? p.psi[q] : 0.f;
+        }
         for (int s = 0; s < 2; ++s) {
             const float Ds = p.D[s];
             float dg = 0.f;
@@ -225,12 +244,12 @@ __global__ __launch_bounds__(kTile) void stability_kernel(Grid g, Phys p, const 
                     }
                     continue;
                 }
-                const int m = nb_map<L>(g, x, y, z, k + 1, xb ? true : (bool)g.periodic_x);
+                const int m = mf[k];
                 if (m == kElectrode) {
                     dg += p.keff[s];
                 } else if (m >= 0) {
-                    const float un = 0.5f * (j[axis * P + n] + j[axis * P + m]) * sg;
-                    const float dpsi = p.psi ? p.psi[m] - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
+                    const float un = 0.5f * (j[axis * P + n] + jN[k]) * sg;
+                    const float dpsi = p.psi ? psiN[k] - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
                     const float w = un - p.z[s] * Ds * dpsi;
                     dg += Ds * bern(-w / Ds);
                 }
