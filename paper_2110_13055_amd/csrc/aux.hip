@@ -67,12 +67,12 @@ __global__ __launch_bounds__(256) void moments_kernel(Grid g, Phys p, int nee, c
     if (u) {
         u[n] = jx * ri;
         u[P + n] = jy * ri;
-        if (D == 3) u[2 * P + n] = jz * ri;
+        if (D == 3) u[2 * (size_t)P + n] = jz * ri;
     }
     if (j) {
         j[n] = jx;
         j[P + n] = jy;
-        if (D == 3) j[2 * P + n] = jz;
+        if (D == 3) j[2 * (size_t)P + n] = jz;
     }
 }
 
@@ -136,7 +136,7 @@ __global__ void j_from_m_kernel(Grid g, const float4 *M, float *j)
     const float r = 1.f + m.x;
     j[n] = r * m.y;
     j[g.P + n] = r * m.z;
-    if (D == 3) j[2 * g.P + n] = r * m.w;
+    if (D == 3) j[2 * (size_t)g.P + n] = r * m.w;
 }
 
 // Single block of 1024 threads; fixed summation order.
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kTile) void stability_kernel(Grid g, Phys p, const 
                 if (m == kElectrode) {
                     dg += p.keff[s];
                 } else if (m >= 0) {
-                    const float un = 0.5f * (j[axis * P + n] + jN[k]) * sg;
+                    const float un = 0.5f * (j[(size_t)axis * P + n] + jN[k]) * sg;
                     const float dpsi = p.psi ? psiN[k] - psiP : (axis == 0 ? -sg * p.dpsi_dx : 0.f);
                     const float w = un - p.z[s] * Ds * dpsi;
                     dg += Ds * bern(-w / Ds);
