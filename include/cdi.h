@@ -290,7 +290,18 @@ typedef struct {
                               voxel map after the node's coordinates (flow-only and fused FP32 steps
                               always look them up: measured no faster with the list); 0: map lookups
                               everywhere */
+    int32_t stage_odd;     /* odd AA steps with FP32 populations, and fused odd steps with FP16
+                              populations: each workgroup stages its tile's population slots in LDS
+                              (the slots whose reader is in the tile are then read and written there,
+                              and the tile's own slots move as coalesced loads and stores). 0 (the
+                              default): staged when the instance has at least CDI_STAGE_MIN_TILES
+                              tiles of 256 fluid nodes (measured: FP32 steps 2-8 % faster from there
+                              on; a smaller lattice's working set stays largely in the memory-side
+                              cache, and there staging made the steps 5-13 % slower); 1: always;
+                              2: never. Batched launches never stage */
 } cdi_tuning;
+
+#define CDI_STAGE_MIN_TILES 16384
 
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t);
 int cdi_get_tuning(const cdi_solver *s, cdi_tuning *t);

@@ -70,7 +70,7 @@ class CSolverInfo(C.Structure):
 
 class CTuning(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("band_rows", C.c_int32), ("columns", C.c_int32),
-                ("nbr_list", C.c_int32)]
+                ("nbr_list", C.c_int32), ("stage_odd", C.c_int32)]
 
 
 class CPotential(C.Structure):

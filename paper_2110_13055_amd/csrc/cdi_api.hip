@@ -327,7 +327,7 @@ struct cdi_solver {
     int rlive = 0;  // the references have been renewed at least once (before, all are zero)
     int64_t flow_steps = 0, np_steps = 0;
     double ka, keff[2], porosity;
-    cdi_tuning tuning{0, 0, 0, 0};
+    cdi_tuning tuning{0, 0, 0, 0, 0};
     Grid g;
     Phys p;
 };
@@ -505,6 +505,12 @@ int build_schedule(cdi_solver *s, int band_rows, int columns)
     s->tuning.band_rows = columns ? 0 : band_rows;
     s->tuning.columns = columns;
     return CDI_OK;
+}
+
+// Whether an instance of ntiles tiles stages its odd steps (cdi_tuning::stage_odd).
+int stage_odd_for(int mode, int64_t ntiles)
+{
+    return mode == 1 || (mode == 0 && ntiles >= CDI_STAGE_MIN_TILES);
 }
 
 // LDS bytes that leave room for at most k step workgroups per CU.
@@ -847,6 +853,7 @@ int cdi_flow_init(const cdi_geometry *geom, const cdi_params *params, void *vox_
     g.sched = nullptr;
     g.nbr = nullptr;
     g.lds_pad = 0;
+    g.stage_odd = stage_odd_for(0, s->ntiles);
     Phys &p = s->p;
     p.omega = (float)(1.0 / params->tau);
     p.fcoef = (float)(1.0 - 0.5 / params->tau);
@@ -1623,7 +1630,7 @@ int cdi_restore(cdi_solver *s, const void *host, uint64_t bytes)
 int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t)
 {
     if (!s || !t || t->blocks_per_cu < 0 || t->band_rows < 0 || t->columns < 0 || t->columns > 2 ||
-        t->nbr_list < 0 || t->nbr_list > 1)
+        t->nbr_list < 0 || t->nbr_list > 1 || t->stage_odd < 0 || t->stage_odd > 2)
         return fail(CDI_E_INVALID, "bad tuning");
     int pad = 0;
     int rc = occupancy_pad(t->blocks_per_cu, &pad);
@@ -1633,6 +1640,8 @@ int cdi_set_tuning(cdi_solver *s, const cdi_tuning *t)
         if ((rc = build_schedule(s, t->band_rows, t->columns)) != CDI_OK) return rc;
     s->g.lds_pad = pad;
     s->g.nbr = t->nbr_list ? s->node.nbr : nullptr;
+    s->g.stage_odd = stage_odd_for(t->stage_odd, s->ntiles);
+    s->tuning.stage_odd = t->stage_odd;
     s->tuning.nbr_list = t->nbr_list;
     s->tuning.blocks_per_cu = t->blocks_per_cu;
     return CDI_OK;
@@ -1661,12 +1670,14 @@ int cdi_autotune(cdi_solver *s, int32_t steps, int32_t fused_flow, cdi_tuning *c
     for (int nl : {0, 1})
         for (int k : occ) {
             for (int r : bands)
-                if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r, 0, nl});
+                if (s->dim == 3 || r == 0) cands.push_back(cdi_tuning{k, r, 0, nl, 0});
             if (s->dim == 3) {
-                cands.push_back(cdi_tuning{k, 0, 1, nl});
-                cands.push_back(cdi_tuning{k, 0, 2, nl});
+                cands.push_back(cdi_tuning{k, 0, 1, nl, 0});
+                cands.push_back(cdi_tuning{k, 0, 2, nl, 0});
             }
         }
+    // staged and unstaged odd steps, for the plain order and the default list
+    for (int st : {1, 2}) cands.push_back(cdi_tuning{0, 0, 0, 1, st});
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));

@@ -107,6 +107,9 @@ struct Grid {
     // dynamic LDS reserved per step workgroup: caps the workgroups resident
     // per CU (and so the working set the L2 must hold); 0 = no cap
     int lds_pad;
+    // odd AA steps of the storages that allow it stage the tile's population
+    // slots in LDS (set by the host from the tuning and the tile count)
+    int stage_odd;
 };
 
 struct Phys {

@@ -44,18 +44,18 @@ def kernel_source_hash() -> str:
 
 
 def _variant(name: str):
-    """step_kernel<L, ST, ODD, LBM, NP> -> readable label, or None."""
-    m = re.search(r"step_kernel<cdi::(D2Q9|D3Q19), (\d), (\d), (\d), (\d)>", name)
+    """step_kernel<L, ST, ODD, LBM, NP, STG> -> readable label, or None."""
+    m = re.search(r"step_kernel<cdi::(D2Q9|D3Q19), (\d), (\d), (\d), (\d)(?:, (\d))?>", name)
     if not m:
         return None
-    lat, st, odd, lbm, np_ = m.groups()
+    lat, st, odd, lbm, np_, stg = m.groups()
     kind = "fused" if lbm == "1" and np_ == "1" else ("lbm" if lbm == "1" else "np")
     # ion-only steps and moment storage have no AA parity; 2 = pull streaming
     if kind == "np" or st == "2":
         parity = ""
     else:
         parity = {"0": " even", "1": " odd", "2": " pull"}[odd]
-    return f"{lat} {STORAGE[st]} {kind}{parity}"
+    return f"{lat} {STORAGE[st]} {kind}{parity}{' staged' if stg == '1' else ''}"
 
 
 def _csv(path):

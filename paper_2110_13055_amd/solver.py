@@ -376,17 +376,18 @@ class Solver:
     def tuning(self):
         t = L.CTuning()
         L.check(self.lib.cdi_get_tuning(self.h, C.byref(t)), "cdi_get_tuning")
-        return (t.blocks_per_cu, t.band_rows, t.columns, t.nbr_list)
+        return (t.blocks_per_cu, t.band_rows, t.columns, t.nbr_list, t.stage_odd)
 
-    def set_tuning(self, blocks_per_cu: int = 0, band_rows: int = 0, columns: int = 0, nbr_list: int = 0):
-        t = L.CTuning(blocks_per_cu, band_rows, columns, nbr_list)
+    def set_tuning(self, blocks_per_cu: int = 0, band_rows: int = 0, columns: int = 0, nbr_list: int = 0,
+                   stage_odd: int = 0):
+        t = L.CTuning(blocks_per_cu, band_rows, columns, nbr_list, stage_odd)
         L.check(self.lib.cdi_set_tuning(self.h, C.byref(t)), "cdi_set_tuning")
 
     def autotune(self, steps: int = 4, fused: bool = True):
         t, ms = L.CTuning(), C.c_double()
         L.check(self.lib.cdi_autotune(self.h, steps, 1 if fused else 0, C.byref(t), C.byref(ms)),
                 "cdi_autotune")
-        return (t.blocks_per_cu, t.band_rows, t.columns, t.nbr_list), ms.value
+        return (t.blocks_per_cu, t.band_rows, t.columns, t.nbr_list, t.stage_odd), ms.value
 
     def snapshot(self) -> bytes:
         nb = C.c_uint64()

@@ -336,12 +336,12 @@ def test_snapshot_restore_continues_bitwise(precision, streaming):
 
 def test_results_do_not_depend_on_tuning_and_autotune_restores_state():
     outs = []
-    for occ, band, cols, nl in ((0, 0, 0, 0), (3, 8, 0, 0), (6, 32, 0, 1), (0, 0, 1, 0), (4, 0, 1, 1),
-                                (0, 0, 0, 1), (0, 0, 2, 1), (3, 0, 2, 0)):
+    for tun in ((0, 0, 0, 0, 0), (3, 8, 0, 0, 0), (6, 32, 0, 1, 1), (0, 0, 1, 0, 2), (4, 0, 1, 1, 1),
+                (0, 0, 0, 1, 0), (0, 0, 2, 1, 1), (3, 0, 2, 0, 0), (2, 0, 0, 1, 1)):
         g, p = small3d(seed=13)
         s = Solver(g, p)
-        s.set_tuning(occ, band, cols, nl)
-        assert s.tuning() == (occ, band, cols, nl)
+        s.set_tuning(*tun)
+        assert s.tuning() == tun
         s.flow_steps(21)
         s.np_step(30, fused=True)
         outs.append((s.concentration(), s.velocity(), s.adsorbed_total()))
@@ -359,6 +359,36 @@ def test_results_do_not_depend_on_tuning_and_autotune_restores_state():
     assert before[2] == after[2]
     s.np_step(30, fused=True)
     assert np.array_equal(outs[0][0], s.concentration())
+
+
+def _staged_case(kind, precision):
+    if kind == "channel2d":
+        g, p, _ = preset("channel2d_128x64", precision=precision)
+    elif kind == "body_force3d":
+        g, p = small3d(seed=3, precision=precision, tau=0.8, drive=L.BODY_FORCE, body_force=(2e-6, 0.0, 0.0))
+    else:  # inlet/outlet, tau = 0.8 (the collision's general branch) or 1
+        g, p = small3d(seed=9, phi=0.7, precision=precision, tau=0.8 if kind == "inout3d_tau08" else 1.0)
+    return g, p
+
+
+@pytest.mark.parametrize("kind", ["inout3d", "inout3d_tau08", "body_force3d", "channel2d"])
+@pytest.mark.parametrize("precision", [L.FP32, L.FP16], ids=["fp32", "fp16"])
+def test_staged_odd_steps_equal_unstaged(kind, precision):
+    # staging the tile's population slots in LDS moves the same stored values
+    # to the same nodes: flow-only, fused and ion-only steps, odd counts, agree
+    # bit for bit with the unstaged kernels
+    out = []
+    for stage in (1, 2):
+        g, p = _staged_case(kind, precision)
+        s = Solver(g, p)
+        s.set_tuning(0, 0, 0, 1, stage)
+        s.flow_steps(57)
+        s.np_step(33, fused=True)
+        s.np_step(5, fused=False)
+        s.np_step(3, fused=True)
+        out.append((s.velocity(), s.density(), s.concentration(), s.adsorbed_total()))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("precision", [L.FP32, L.FP16_DEV])

@@ -77,4 +77,9 @@ def test_variant_labels():
     assert ps._variant(LBM16) == "D3Q19 fp16 lbm pull"
     assert ps._variant("void cdi::(anonymous namespace)::step_kernel<cdi::D3Q19, 2, 0, 1, 1>(x)") == "D3Q19 moments fused"
     assert ps._variant("void cdi::(anonymous namespace)::step_kernel<cdi::D2Q9, 0, 0, 0, 1>(x)") == "D2Q9 fp32 np"
+    # the sixth argument: the odd step staged in LDS
+    assert (ps._variant("void cdi::(anonymous namespace)::step_kernel<cdi::D3Q19, 0, 1, 1, 1, 1>(x)")
+            == "D3Q19 fp32 fused odd staged")
+    assert ps._variant("void cdi::(anonymous namespace)::step_kernel<cdi::D3Q19, 0, 0, 1, 1, 0>(x)") == \
+        "D3Q19 fp32 fused even"
     assert ps._variant(COPY) is None
