@@ -230,18 +230,22 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     double res[2] = {0, 0};
 
-    // odd parity: the node's own slots into the stage
-    if (kStage && active) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) stg[q * kTile + threadIdx.x] = ldu(plane_of<StageT<ST>>(b.f, P, q), (uint32_t)n);
-    }
-
     // coordinates and neighbour map values of the node
     int x = 0, y = 0, z = 0;
     int nb[Q];
     bool edge = false;
+    // odd parity, staged: the node's own slots are loaded between its
+    // coordinates and its neighbours' map values (the three in flight
+    // together: each wait is for the earliest), and stored into the stage
+    // after the lookups are issued
+    StageT<ST> own[kStage ? Q : 1];
     if (active) {
-        unpack_xyz(g, ldu(g.fluid, (uint32_t)n), x, y, z);
+        const uint32_t packed = ldu(g.fluid, (uint32_t)n);
+        if constexpr (kStage) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) own[q] = ldu(plane_of<StageT<ST>>(b.f, P, q), (uint32_t)n);
+        }
+        unpack_xyz(g, packed, x, y, z);
         constexpr bool need_all = LBM && (ODD || !kPlain<ST>);
         edge = LBM && g.inout && (b.flags & kNee) && (x <= 1 || x >= g.nx - 2);
         nb[0] = n;
@@ -267,6 +271,10 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 const bool want = need_all || (NP && i <= 2 * D) || (edge && i <= 2);
                 nb[i] = want ? nb_get<L>(g, ctx, i) : kOutside;
             }
+        }
+        if constexpr (kStage) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) stg[q * kTile + threadIdx.x] = own[q];
         }
     }
 
@@ -546,6 +554,10 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         // tile: node x - e_q for slot q when that voxel is fluid, else the node
         __syncthreads();
         if (active) {
+            // all stage reads first, then the stores (one wait for the reads)
+            StageT<ST> v[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v[q] = stg[q * kTile + threadIdx.x];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = L::opp[q];
@@ -553,7 +565,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 const int c = fl ? nb[r] : n;
                 const int xc = fl ? x - L::ex[q] : x;
                 if ((uint32_t)(c - base) < (uint32_t)kTile && !(nee && (xc == 0 || xc == g.nx - 1)))
-                    stu(plane_of<StageT<ST>>(b.f, P, q), (uint32_t)n, stg[q * kTile + threadIdx.x]);
+                    stu(plane_of<StageT<ST>>(b.f, P, q), (uint32_t)n, v[q]);
             }
         }
         if (BATCH) __syncthreads();  // a next tile's loads would reuse the stage
