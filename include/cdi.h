@@ -290,8 +290,8 @@ typedef struct {
                               voxel map after the node's coordinates (flow-only and fused FP32 steps
                               always look them up: measured no faster with the list); 0: map lookups
                               everywhere */
-    int32_t stage_odd;     /* odd AA steps with FP32 populations, and fused odd steps with FP16
-                              populations: each workgroup stages its tile's population slots in LDS
+    int32_t stage_odd;     /* odd AA steps with FP32 or FP16 populations: each workgroup stages its
+                              tile's population slots in LDS
                               (the slots whose reader is in the tile are then read and written there,
                               and the tile's own slots move as coalesced loads and stores). 0 (the
                               default): staged when the instance has at least CDI_STAGE_MIN_TILES

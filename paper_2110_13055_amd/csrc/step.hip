@@ -22,8 +22,8 @@ namespace cdi {
 
 namespace {
 
-// Odd AA parity with FP32 populations, and with FP16 populations in fused
-// steps: the tile stages the slots of its own 256 nodes in LDS. Every slot has exactly one reader, which is also
+// Odd AA parity with FP32 or FP16 populations: the tile stages the slots of
+// its own 256 nodes in LDS. Every slot has exactly one reader, which is also
 // its writer (the AA rule above), so a slot whose reader lies in the tile is
 // read from and written to LDS, and the owner loads it before and stores it
 // after the step, both coalesced; a slot read by a node of another tile is
@@ -31,9 +31,9 @@ namespace {
 // (advanced by their interior partner under extrapolation) write through
 // global memory, so their slots are never stored back by an owner. On the
 // 512^3 electrode about 29 % of the slots lie outside their reader's tile;
-// staged, the FP32 fused odd step took 3.43 ms instead of 3.73, the FP32
-// flow-only one 2.59 instead of 2.87, the FP16 fused one 2.83 instead of
-// 2.87 (the FP16 flow-only step, 2.07 ms, took 2.14 staged: not staged).
+// staged, the FP32 fused odd step took 3.39 ms instead of 3.73, the FP32
+// flow-only one 2.55 instead of 2.87, the FP16 fused one 2.76 instead of
+// 2.87 (its flow-only step gains about 1 %).
 // On lattices whose working set stays largely in the memory-side cache the
 // extra work and barrier do not pay (96^3 to 160^3 electrodes stepped 5-13 %
 // slower staged), so the host stages an instance's odd steps only from a
@@ -48,7 +48,7 @@ namespace {
 // and a global load into one generic-address access (which goes through the
 // vector memory path and waits on both counters).
 template <class L, int ST, int ODD, int LBM, int NP>
-constexpr bool kStageOdd = LBM && ODD == 1 && (ST == kF32 || (ST == kH16 && NP));
+constexpr bool kStageOdd = LBM && ODD == 1 && (ST == kF32 || ST == kH16);
 
 template <int ST>
 using StageT = typename std::conditional<kHalfPop<ST>, uint16_t, float>::type;  // FP16 as its bits
