@@ -3,9 +3,10 @@
 //
 // Data layout in device memory (N_f fluid nodes, stride P = N_f rounded up to
 // a whole number of 256-node tiles):
-//   populations  Q planes of P values (structure of arrays), FP32 f - w_i or
-//                FP16 scaled deviations from the emitter's equilibrium; none
-//                with moment storage
+//   populations  Q x P values in blocks of 64 nodes (block k: the Q
+//                directions of nodes 64k .. 64k + 63, 64 values each), FP32
+//                f - w_i(1 + R[x]) or FP16 scaled values; none with moment
+//                storage
 //   moments      FP16 and moment storage: float4 (rho - 1, ux, uy, uz) per
 //                node, double buffered (the moments of the previous step
 //                belong to the emitters of the populations now stored)

@@ -282,43 +282,48 @@ __device__ __forceinline__ float stored_pop(float g, int i, const int *nb, const
     return nb[i] >= 0 ? g + L::w[i] * r.dOut[L::ex[i] + 1] : g;
 }
 
-// Plane i of a structure-of-arrays field (planes P apart). The plane's base
-// is the same for the whole wave, so an access is that base plus a 32-bit
-// byte offset of the node: no 64-bit address arithmetic per lane.
-template <class T>
-__device__ __forceinline__ T *plane_of(void *F, int P, int i)
+// Populations are stored in blocks of 64 nodes, one wave: block k holds the
+// Q directions of nodes 64k .. 64k + 63, direction by direction (64
+// consecutive values each). A wave's access to one direction is one
+// contiguous run of 256 bytes (FP32) as with whole planes, but the Q streams
+// of a block lie in one region of Q x 256 bytes instead of Q planes far
+// apart. Measured on the 512^3 electrode against whole planes of P values:
+// FP32 fused step 3 % and flow-only step 6 % faster (blocks of 256 nodes:
+// 0.5 % slower than 64). P is a multiple of the 256-node tile, so every block
+// is whole.
+constexpr int kPopBlockLog = 6;
+
+template <int Q, class T>
+__device__ __forceinline__ T *pop_at(void *F, int q, int n)
 {
-    return reinterpret_cast<T *>(F) + (size_t)i * (size_t)P;
+    return reinterpret_cast<T *>(F) + ((((size_t)(n >> kPopBlockLog)) * Q + q) << kPopBlockLog) +
+           (n & ((1 << kPopBlockLog) - 1));
 }
-template <class T>
-__device__ __forceinline__ const T *plane_of(const void *F, int P, int i)
+template <int Q, class T>
+__device__ __forceinline__ const T *pop_at(const void *F, int q, int n)
 {
-    return reinterpret_cast<const T *>(F) + (size_t)i * (size_t)P;
+    return reinterpret_cast<const T *>(F) + ((((size_t)(n >> kPopBlockLog)) * Q + q) << kPopBlockLog) +
+           (n & ((1 << kPopBlockLog) - 1));
 }
 
-// Value of plane a at node na, or of plane b at node nb (one of the two per
-// lane), where a and b are the same plane or two adjacent ones (a direction
-// and its opposite are numbered as neighbours): both are addressed from the
-// lower plane's base, so a single load with a 32-bit offset of at most 2P
-// elements serves either case.
-template <int FP16>
-__device__ __forceinline__ float ld_pair(const void *F, int P, int a, int na, int b, int nb, bool first)
+// Value of direction a at node na, or of direction b at node nb (one of the
+// two per lane).
+template <int FP16, int Q>
+__device__ __forceinline__ float ld_pair(const void *F, int a, int na, int b, int nb, bool first)
 {
-    const int lo = a < b ? a : b;
-    const uint32_t idx = first ? (uint32_t)na + (a > lo ? (uint32_t)P : 0u) : (uint32_t)nb + (b > lo ? (uint32_t)P : 0u);
-    if (FP16) return __half2float(ldu(plane_of<__half>(F, P, lo), idx));
-    return ldu(plane_of<float>(F, P, lo), idx);
+    const int q = first ? a : b, m = first ? na : nb;
+    if (FP16) return __half2float(*pop_at<Q, __half>(F, q, m));
+    return *pop_at<Q, float>(F, q, m);
 }
 
-template <int FP16>
-__device__ __forceinline__ void st_pair(void *F, int P, int a, int na, int b, int nb, bool first, float v)
+template <int FP16, int Q>
+__device__ __forceinline__ void st_pair(void *F, int a, int na, int b, int nb, bool first, float v)
 {
-    const int lo = a < b ? a : b;
-    const uint32_t idx = first ? (uint32_t)na + (a > lo ? (uint32_t)P : 0u) : (uint32_t)nb + (b > lo ? (uint32_t)P : 0u);
+    const int q = first ? a : b, m = first ? na : nb;
     if (FP16)
-        stu(plane_of<__half>(F, P, lo), idx, __float2half_rn(v));
+        *pop_at<Q, __half>(F, q, m) = __float2half_rn(v);
     else
-        stu(plane_of<float>(F, P, lo), idx, v);
+        *pop_at<Q, float>(F, q, m) = v;
 }
 
 // Stored value behind the incoming population i of node n (FP32 f - w_i or
@@ -331,9 +336,9 @@ __device__ inline float gather_raw(const void *F, int P, const int *nb, int n, i
     const int j = L::opp[i];
     const bool fl = (i != 0) && nb[j] >= 0;
     // pull: plane i of the emitter x - e_i, or the node's own reflected plane j
-    if (ODD == kPull) return ld_pair<H>(F, P, i, nb[j], j, n, fl);
+    if (ODD == kPull) return ld_pair<H, L::Q>(F, i, nb[j], j, n, fl);
     // AA: plane i of the node itself, or (odd parity, fluid emitter) plane j of the emitter
-    return ld_pair<H>(F, P, i, n, j, nb[j], !ODD || i == 0 || !fl);
+    return ld_pair<H, L::Q>(F, i, n, j, nb[j], !ODD || i == 0 || !fl);
 }
 
 // FP16 and moment storage: f_i - w_i from the stored value and the emitter's
@@ -375,11 +380,11 @@ __device__ inline void scatter(void *F, int P, const int *nb, int n, int i, floa
     constexpr bool H = kHalfPop<ST>;
     const int j = L::opp[i];
     if (ODD == kPull)
-        st_pair<H>(F, P, i, n, i, n, true, v);  // the node's own plane i
+        st_pair<H, L::Q>(F, i, n, i, n, true, v);  // the node's own slot i
     else
         // even parity (or the rest direction): the node's own plane opp(i); odd
         // parity: plane i of the fluid neighbour x + e_i, else (reflected) plane opp(i)
-        st_pair<H>(F, P, j, n, i, nb[i], !ODD || i == 0 || nb[i] < 0, v);
+        st_pair<H, L::Q>(F, j, n, i, nb[i], !ODD || i == 0 || nb[i] < 0, v);
 }
 
 // Non-equilibrium extrapolation (Guo, Zheng & Shi 2002) for the inlet

@@ -107,7 +107,7 @@ __device__ __forceinline__ void staged_gather(const void *F, int P, const int *n
         int pl;
         uint32_t loc;
         if (!staged_slot<L>(nb, n, i, base, pl, loc))  // a fluid emitter: plane opp(i) of it
-            raw[i] = ldu(plane_of<StageT<ST>>(F, P, L::opp[i]), (uint32_t)nb[L::opp[i]]);
+            raw[i] = *pop_at<L::Q, StageT<ST>>(F, L::opp[i], nb[L::opp[i]]);
     }
 }
 
@@ -122,7 +122,7 @@ __device__ __forceinline__ void staged_scatter(void *F, int P, const int *nb, in
     const uint32_t loc = (uint32_t)((own ? n : nb[i]) - base);
     const bool in = lds_ok && loc < (uint32_t)kTile;
     stage[in ? (own ? j : i) * kTile + (int)loc : L::Q * kTile + (int)threadIdx.x] = pop_stored<ST>(v);
-    if (!in) st_pair<kHalfPop<ST>>(F, P, j, n, i, nb[i], own, v);
+    if (!in) st_pair<kHalfPop<ST>, L::Q>(F, j, n, i, nb[i], own, v);
 }
 
 // Moments, residual terms, collision and the AA store of one node whose
@@ -243,7 +243,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
         const uint32_t packed = ldu(g.fluid, (uint32_t)n);
         if constexpr (kStage) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) own[q] = ldu(plane_of<StageT<ST>>(b.f, P, q), (uint32_t)n);
+            for (int q = 0; q < Q; ++q) own[q] = *pop_at<Q, StageT<ST>>(b.f, q, n);
         }
         unpack_xyz(g, packed, x, y, z);
         constexpr bool need_all = LBM && (ODD || !kPlain<ST>);
@@ -565,7 +565,7 @@ __device__ __attribute__((always_inline)) inline void step_tile(const Grid &g, c
                 const int c = fl ? nb[r] : n;
                 const int xc = fl ? x - L::ex[q] : x;
                 if ((uint32_t)(c - base) < (uint32_t)kTile && !(nee && (xc == 0 || xc == g.nx - 1)))
-                    stu(plane_of<StageT<ST>>(b.f, P, q), (uint32_t)n, v[q]);
+                    *pop_at<Q, StageT<ST>>(b.f, q, n) = v[q];
             }
         }
         if (BATCH) __syncthreads();  // a next tile's loads would reuse the stage
