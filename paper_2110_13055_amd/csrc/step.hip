@@ -593,6 +593,41 @@ __global__ __launch_bounds__(kTile) void step_kernel(Grid g, Phys p, Bufs b)
     step_tile<L, ST, ODD, LBM, NP, 0, STG>(g, p, b, block_tile(g), sm, stage);
 }
 
+// A batch member's descriptor is read from memory, and a pointer read from
+// memory is a generic address to the compiler: its accesses become flat
+// instructions, which take the vector memory path and count on both wait
+// counters. Read through the constant address space (the descriptors do not
+// change during a launch), the pointers are known to address global memory
+// and their accesses are global ones.
+__device__ __forceinline__ void load_inst(const BatchInst *inst, int k, Grid &g, Phys &p, Bufs &b)
+{
+    g = inst[k].g;
+    p = inst[k].p;
+    b = inst[k].b;
+    typedef const __attribute__((address_space(4))) BatchInst const_inst_t;
+    const_inst_t &c = ((const_inst_t *)inst)[k];
+    g.fluid = c.g.fluid;
+    g.map = c.g.map;
+    g.sched = c.g.sched;
+    g.nbr = c.g.nbr;
+    p.psi = c.p.psi;
+    b.f = c.b.f;
+    b.f2 = c.b.f2;
+    b.Min = c.b.Min;
+    b.Mout = c.b.Mout;
+    b.jin = c.b.jin;
+    b.jout = c.b.jout;
+    b.Cin = c.b.Cin;
+    b.Cout = c.b.Cout;
+    b.Clin = c.b.Clin;
+    b.Clout = c.b.Clout;
+    b.acc = c.b.acc;
+    b.resid = c.b.resid;
+    b.ubuf = c.b.ubuf;
+    b.rin = c.b.rin;
+    b.rout = c.b.rout;
+}
+
 // Many instances in one persistent launch per step class (LBM parity and
 // mode): workgroup w takes entries w, w + G, w + 2G, ... of the class's list
 // of (instance, tile) pairs. Each instance carries its own lattice,
@@ -619,9 +654,10 @@ __global__ __launch_bounds__(kTile) void batch_kernel(const BatchInst *__restric
     }
     for (int q = first; q < hi; q += stride) {
         const int2 e = tiles[q];
-        const Grid g = inst[e.x].g;
-        const Phys p = inst[e.x].p;
-        const Bufs b = inst[e.x].b;
+        Grid g;
+        Phys p;
+        Bufs b;
+        load_inst(inst, e.x, g, p, b);
         step_tile<L, ST, ODD, LBM, NP, 1>(g, p, b, e.y, sm, nullptr);  // not staged
     }
 }
