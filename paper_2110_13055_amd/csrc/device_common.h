@@ -293,17 +293,22 @@ __device__ __forceinline__ float stored_pop(float g, int i, const int *nb, const
 // is whole.
 constexpr int kPopBlockLog = 6;
 
+// (the node's part, one 64-bit product, and the direction's constant part
+// apart, so that a node's Q accesses share the first and fold the second
+// into the instructions' offsets)
 template <int Q, class T>
 __device__ __forceinline__ T *pop_at(void *F, int q, int n)
 {
-    return reinterpret_cast<T *>(F) + ((((size_t)(n >> kPopBlockLog)) * Q + q) << kPopBlockLog) +
-           (n & ((1 << kPopBlockLog) - 1));
+    T *const node = reinterpret_cast<T *>(F) + (size_t)(uint32_t)(n >> kPopBlockLog) * (Q << kPopBlockLog) +
+                    (n & ((1 << kPopBlockLog) - 1));
+    return node + (q << kPopBlockLog);
 }
 template <int Q, class T>
 __device__ __forceinline__ const T *pop_at(const void *F, int q, int n)
 {
-    return reinterpret_cast<const T *>(F) + ((((size_t)(n >> kPopBlockLog)) * Q + q) << kPopBlockLog) +
-           (n & ((1 << kPopBlockLog) - 1));
+    const T *const node = reinterpret_cast<const T *>(F) +
+                          (size_t)(uint32_t)(n >> kPopBlockLog) * (Q << kPopBlockLog) + (n & ((1 << kPopBlockLog) - 1));
+    return node + (q << kPopBlockLog);
 }
 
 // Value of direction a at node na, or of direction b at node nb (one of the
